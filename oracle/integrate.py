@@ -1,0 +1,129 @@
+"""Linearly implicit backward-Euler integration (Section 2.1 names backward
+Euler among the implicit solvers for the stiff discretised continuity
+equation).  Test infrastructure only.
+
+One step: solve (I/dt - J(n)) Delta = F(n), then n <- n + Delta.
+"""
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import grid as grid_mod
+from . import rates as rates_mod
+from .rhs import rhs
+from .jacobian import step_matrix
+from .linalg import btd, dense_solve
+
+
+class Problem:
+    """Network + column with the grid and rate coefficients precomputed (the
+    coefficients depend on T, n_gas and tau only, which are fixed)."""
+
+    def __init__(self, net, col):
+        self.net = net
+        self.col = col
+        self.grid = grid_mod.make_grid(col, net.mass_amu)
+        self.kf, self.kr = rates_mod.rates(net, self.grid)
+
+    def rhs(self, n):
+        return rhs(self.net, self.grid, self.kf, self.kr, n)
+
+    def step_matrix(self, n, dt):
+        return step_matrix(self.net, self.grid, self.kf, self.kr, n, dt)
+
+
+def be_step(prob, n, dt, solver="btd", newton_iters=1):
+    """One linearly implicit BE step; newton_iters > 1 adds frozen-Jacobian
+    corrections of the nonlinear BE equation n1 - n - dt F(n1) = 0.
+    Returns (n_new, delta)."""
+    B, a, c = prob.step_matrix(n, dt)
+    solve = btd if solver == "btd" else dense_solve
+    delta = solve(B, a, c, prob.rhs(n))
+    for _ in range(newton_iters - 1):
+        n1 = n + delta
+        resid = prob.rhs(n1) - delta / dt
+        delta = delta + solve(B, a, c, resid)
+    return n + delta, delta
+
+
+def fixed_schedule(nsteps=200, dt0=1.0e-8, growth=1.2):
+    """dt_j = dt0 * growth^j, j = 0 .. nsteps-1."""
+    return [dt0 * growth ** j for j in range(nsteps)]
+
+
+def run_fixed(prob, n0, schedule, solver="btd"):
+    n = n0.copy()
+    for dt in schedule:
+        n, _ = be_step(prob, n, dt, solver)
+    return n
+
+
+@dataclass
+class SteadyResult:
+    n: np.ndarray
+    t: float
+    dt: float
+    steps: int
+    rejects: int
+    converged: bool
+    clipped: float
+    history: list
+
+
+def steady_state(prob, n0, tol_rel=1.0e-4, y_floor=1.0e-30, y_sig=1.0e-10,
+                 t_end=1.0e12, dt0=1.0e-8, max_steps=5000,
+                 max_consec_rejects=30, use_mix_rule=True):
+    """Adaptive backward-Euler driver to steady state.
+
+    * Reject a step (dt <- dt/2) if it is not finite or if a species whose
+      mixing ratio exceeded y_sig turns negative; after more than
+      max_consec_rejects consecutive rejections give up (not converged).
+    * On acceptance clip negative densities to zero (the clipped amount is
+      recorded) and adapt dt from the largest relative change of the
+      species above y_sig, c = max |n1 - n0| / max(n0, n1):
+      dt <- 2 dt if c < 0.5, 1.2 dt if c < 0.9, else 0.7 dt.
+    * Converged when the largest relative change max |Delta n| / n over
+      mixing ratios above y_floor is below tol_rel while dt is at least the
+      longest layer mixing time dzh^2/(K + D) (Section 3.2: the variation
+      timescale must exceed the layer mixing timescale; Section 2 checks
+      convergence as a relative change between iterations), or when
+      t >= t_end.
+    """
+    ngas = prob.grid.ngas[:, None]
+    mix = prob.grid.mix_time if use_mix_rule else 0.0
+    n = n0.copy()
+    t, dt = 0.0, dt0
+    steps = rejects = consec = 0
+    clipped = 0.0
+    hist = []
+    converged = False
+    while steps < max_steps:
+        n_new, delta = be_step(prob, n, dt)
+        sig = n > y_sig * ngas
+        if not np.all(np.isfinite(n_new)) or np.any(sig & (n_new < 0.0)):
+            rejects += 1
+            consec += 1
+            dt *= 0.5
+            if consec > max_consec_rejects:
+                break
+            continue
+        consec = 0
+        neg = n_new < 0.0
+        clipped += float(-n_new[neg].sum())
+        n_new[neg] = 0.0
+        keep = n_new > y_floor * ngas
+        rel = float(np.max(np.abs(n_new[keep] - n[keep]) / n_new[keep])) if keep.any() else 0.0
+        ctl = n_new > y_sig * ngas
+        big = np.maximum(n_new[ctl], n[ctl])
+        c = float(np.max(np.abs(n_new[ctl] - n[ctl]) / big)) if ctl.any() else 0.0
+        t += dt
+        steps += 1
+        n = n_new
+        hist.append((t, dt, rel, c))
+        if (rel < tol_rel and dt >= mix) or t >= t_end:
+            converged = True
+            break
+        dt *= 2.0 if c < 0.5 else (1.2 if c < 0.9 else 0.7)
+    return SteadyResult(n=n, t=t, dt=dt, steps=steps, rejects=rejects,
+                        converged=converged, clipped=clipped, history=hist)
