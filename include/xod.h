@@ -1,0 +1,264 @@
+/*
+ * xod.h -- C ABI of the implicit photochemical column solver (libxod).
+ *
+ * The library integrates the coupled species-continuity equations of a 1-D
+ * atmospheric column (Section 2.1, Eq. continuity):
+ *
+ *     dn_y/dt = P_y - L_y - d(phi_y)/dz ,   y = 1..S
+ *
+ * with the transport flux of Eq. transportflux (eddy + molecular diffusion),
+ * discretised on N layers (Eq. discrete_continuity, Eq. dzz) with zero-flux
+ * boundaries (Section 2.5), chemistry from two-body (Kooij / modified
+ * Arrhenius), three-body (Lindemann) and photolysis reactions with reverse
+ * rates from NASA-7 Gibbs energies (Section 2.3), by linearly implicit
+ * backward-Euler steps (Section 2.1 lists backward Euler among the implicit
+ * integrators).  Each step solves the block-tridiagonal system
+ *
+ *     a_k * x_{k-1} + B_k x_k + c_k * x_{k+1} = F_k(n),   B_k = I/dt - dF_k/dn_k
+ *
+ * (S x S dense diagonal blocks, diagonal off-diagonal blocks a_k, c_k) by a
+ * block Thomas elimination whose Schur complements are inverted on the GPU.
+ *
+ * Conventions
+ *   - Every function returns xod_status; XOD_OK == 0.  No exception crosses
+ *     the ABI.  xod_last_error() returns a thread-local message naming the
+ *     failing column / layer / row where that applies.
+ *   - Units are CGS (cm^-3, s, K); pressures are given in bar.
+ *   - Layer k = 0 is the bottom of the column.  Arrays are layer-major:
+ *     n[k*S + y], kf[k*R + r], B[(k*ld + i)*ld + j].
+ *   - Host arrays passed to *_create are copied; the caller keeps ownership.
+ *     The library owns every device allocation inside a handle and frees it
+ *     in *_destroy.
+ *   - Pointers passed to the hot-path calls (xod_rates .. xod_btd_solve) are
+ *     DEVICE pointers owned by the caller (e.g. torch tensors' data_ptr());
+ *     the library never frees them.  Work is enqueued on the column's HIP
+ *     stream and is asynchronous unless stated otherwise.
+ *   - After an error no partial result is promised; the column state of
+ *     xod_step / steady-state calls is left unchanged on a rejected step.
+ */
+#ifndef XOD_H
+#define XOD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  XOD_OK = 0,
+  XOD_EINVAL = 1,         /* bad argument: null pointer, size, index range  */
+  XOD_ENOMEM = 2,         /* device allocation failed                        */
+  XOD_ESINGULAR = 3,      /* zero / non-finite pivot in a Schur complement   */
+  XOD_ENOTCONVERGED = 4,  /* step rejected too often / refinement stalled    */
+  XOD_ENONFINITE = 5,     /* NaN or Inf in a state or right-hand side        */
+  XOD_EHIP = 6,           /* HIP runtime error                               */
+  XOD_ENOTIMPL = 7,       /* size outside the supported range                */
+  XOD_EBUSY = 8           /* serving: no slot or memory free right now       */
+} xod_status;
+
+typedef enum {
+  XOD_FP64 = 0,   /* every kernel in FP64                                      */
+  XOD_MIXED = 1   /* Schur complements and their inverses in FP32 with row
+                     scaling, FP64 rates / residuals / pivot blocks and FP64
+                     iterative refinement of every solve                       */
+} xod_precision;
+
+enum { XOD_MAX_REAC = 3, XOD_MAX_PROD = 3 };
+enum { XOD_RT_BIMOL = 0, XOD_RT_TERMOL = 1, XOD_RT_PHOTO = 2 };
+
+typedef struct xod_network xod_network;   /* opaque, device-resident */
+typedef struct xod_column xod_column;     /* opaque, owns state + workspace */
+typedef struct xod_batch xod_batch;       /* set of columns stepped together */
+typedef struct xod_server xod_server;     /* continuous-batching request loop */
+
+/* Reaction network (Section 2.2-2.3).  Host arrays, copied at create.
+ *   elem_comp [E*S]    atom counts a_{e,y} (diagnostics only)
+ *   mass_amu  [S]      molecular masses
+ *   nasa7     [S*2*7]  NASA-7 sets, low range then high range per species
+ *                      (Appendix A); the high range is used iff T >= t_mid
+ *   rtype     [R]      XOD_RT_BIMOL | XOD_RT_TERMOL | XOD_RT_PHOTO
+ *   reac,prod [R*3]    species ids, -1 padded; a repeated id is a power;
+ *                      the third body M is never listed
+ *   reversible[R]      1: k_r = k_f / K_c from Gibbs energies (Section
+ *                      2.3.4); ignored for photolysis (always irreversible)
+ *   tb_kooij  [R]      1: T_b = T/300 (Kooij), 0: T_b = T (mod. Arrhenius)
+ *   params    [R*6]    two-body (ln alpha, beta, gamma, -, -, -);
+ *                      three-body (ln alpha0, beta0, gamma0, ln alpha_inf,
+ *                      beta_inf, gamma_inf); photolysis (ln J0, -, ...).   */
+typedef struct {
+  int32_t S, R, E;
+  const int32_t *elem_comp;
+  const double *mass_amu;
+  const double *nasa7;
+  double t_mid;
+  const int32_t *rtype;
+  const int32_t *reac;
+  const int32_t *prod;
+  const int32_t *reversible;
+  const int32_t *tb_kooij;
+  const double *params;
+} xod_network_desc;
+
+/* Column profile.  Host arrays, copied at create.
+ *   P_bar, T_K, Kzz [N]   bottom (k = 0) to top; P strictly decreasing
+ *   Dmol  [N*S] or NULL   molecular-diffusion coefficients (NULL = 0)
+ *   alphaT [S] or NULL    thermal-diffusion factors (NULL = 0)
+ *   mbar_amu, g_cgs       mean molecular mass and gravity (hydrostatic grid)
+ *   sigma_tau             gray cross section: tau_k = sigma_tau times the
+ *                         total-gas column above the layer midpoint
+ *                         (Section 2.3.3, with t_f = mu = 1).              */
+typedef struct {
+  int32_t N;
+  const double *P_bar, *T_K, *Kzz;
+  const double *Dmol;
+  const double *alphaT;
+  double mbar_amu, g_cgs, sigma_tau;
+} xod_profile;
+
+/* ---- lifecycle -------------------------------------------------------- */
+
+/* Validates the description (species ids in range, S >= 1, R >= 0, S <=
+ * 1024), builds the incidence and Jacobian-pattern tables on the host and
+ * uploads everything.  XOD_EINVAL on a bad description. */
+xod_status xod_network_create(const xod_network_desc *desc, xod_network **out);
+xod_status xod_network_destroy(xod_network *net);
+xod_status xod_network_sizes(const xod_network *net, int32_t *S, int32_t *R,
+                             int32_t *ld);
+
+/* Allocates the column's device state and workspace (dense blocks: N*ld*ld
+ * doubles, or floats in XOD_MIXED, ld = S rounded up to 32), runs the grid
+ * set-up kernel (number densities, half levels, hydrostatic heights, optical
+ * depths, transport coefficients, Gibbs energies) and uploads n0 (host,
+ * [N*S] cm^-3).  hip_stream may be NULL (default stream).  The network
+ * must outlive the column. */
+xod_status xod_column_create(const xod_network *net, const xod_profile *prof,
+                             const double *n0, xod_precision prec,
+                             void *hip_stream, xod_column **out);
+xod_status xod_column_destroy(xod_column *col);
+
+/* State transfer (synchronous).  n is a HOST pointer [N*S]; t and dt may be
+ * NULL.  The state (n, t, dt) is the whole checkpoint of a column. */
+xod_status xod_column_get_state(const xod_column *col, double *n, double *t,
+                                double *dt);
+xod_status xod_column_set_state(xod_column *col, const double *n, double t,
+                                double dt);
+/* Device pointer of the column's state n [N*S] (owned by the column). */
+xod_status xod_column_state_ptr(xod_column *col, double **n_dev);
+/* Grid quantities (host copies, any pointer may be NULL): n_gas [N],
+ * tau [N], dz [N]; mix_time = max over half levels and species of
+ * dzh^2 / (K + D). */
+xod_status xod_column_grid(const xod_column *col, double *ngas, double *tau,
+                           double *dz, double *mix_time);
+
+/* ---- hot-path calls (device pointers, asynchronous on the column stream) */
+
+/* Rate coefficients (Section 2.3): kf, kr [N*R].  Two-body:
+ * alpha T_b^beta exp(-gamma/T); three-body: Lindemann with [M] = n_gas,k;
+ * photolysis: J0 exp(-tau_k); reverse: k_r = k_f exp(dg - dnu ln(P0/kT)),
+ * i.e. k_f / K_c with K_c = exp(-dg) (P0/kT)^dnu. */
+xod_status xod_rates(xod_column *col, double *kf, double *kr);
+
+/* Right-hand side F(n) = P - L - d(phi)/dz [N*S] for the given rate
+ * coefficients (from xod_rates) and state n [N*S]. */
+xod_status xod_rhs(xod_column *col, const double *kf, const double *kr,
+                   const double *n, double *f);
+
+/* Step matrix blocks of M = I/dt - dF/dn at state n:
+ *   B [N*ld*ld] dense diagonal blocks (rows/columns >= S padded with the
+ *   identity), a, c [N*ld] sub/super-diagonal coupling (zero padded;
+ *   a_0 = c_{N-1} = 0).  ld must be >= S and a multiple of 32. */
+xod_status xod_jacobian(xod_column *col, const double *kf, const double *kr,
+                        const double *n, double dt, double *B, double *a,
+                        double *c, int32_t ld);
+
+/* Block Thomas elimination in place (FP64).  For k = 0..N-1 the Schur
+ * complement D'_k = B_k - diag(a_k) D'_{k-1}^{-1} diag(c_{k-1}) is inverted
+ * by Gauss-Jordan elimination with partial pivoting (implicit row
+ * pivoting, first maximum wins).  On return block k holds W_k and piv[k*ld+j]
+ * the row chosen as pivot for column j, such that
+ *   (D'_k^{-1})[j][i] = W_k[piv[j]][q(i)],  q = inverse permutation of piv.
+ * XOD_ESINGULAR (layer and column in xod_last_error) on a zero or
+ * non-finite pivot.  Synchronises the stream to read the singular flag. */
+xod_status xod_btd_factor(xod_column *col, double *B, const double *a,
+                          const double *c, int32_t ld, int32_t *piv);
+
+/* Forward / backward substitution with factors from xod_btd_factor:
+ * g'_k = g_k - a_k * D'^{-1}_{k-1} g'_{k-1};
+ * x_k = D'^{-1}_k (g'_k - c_k * x_{k+1}).  rhs [N*S] is overwritten by x. */
+xod_status xod_btd_solve(xod_column *col, const double *B, const double *a,
+                         const double *c, int32_t ld, const int32_t *piv,
+                         double *rhs);
+
+/* One linearly implicit backward-Euler step of the column state:
+ * solve (I/dt - J(n)) delta = F(n), n <- n + delta (no clipping).  In
+ * XOD_MIXED the solve is refined in FP64 until the residual satisfies
+ * |r|_inf <= 1e-14 (|M| |delta| + |F|)_inf or 10 refinements, after which an
+ * FP64 refactorisation is used.  Synchronous (reads the statistics). */
+typedef struct {
+  double max_rel_change;   /* max |delta| / |n_new| over n_new/n_gas > 1e-30 */
+  double min_ratio;        /* min n_new / n_gas                               */
+  double resid_inf;        /* final scaled residual (mixed) or 0              */
+  int32_t refine_iters;    /* refinement iterations used (mixed)              */
+  int32_t fp64_fallback;   /* 1 if the mixed solve fell back to FP64          */
+  int32_t nonfinite;       /* 1 if the new state holds NaN / Inf              */
+  int32_t pad_;
+} xod_step_stats;
+xod_status xod_step(xod_column *col, double dt, xod_step_stats *stats);
+
+/* Adaptive driver to steady state.
+ *   reject (dt /= 2) if the step is not finite or a species whose mixing
+ *   ratio exceeded y_sig turns negative; accept otherwise, clip negatives to
+ *   zero and set dt *= 2 / 1.2 / 0.7 for a control change c < 0.5 / < 0.9 /
+ *   otherwise, c = max |n1 - n0| / max(n0, n1) over mixing ratios > y_sig;
+ *   converged when max |dn| / n over mixing ratios > y_floor is < tol_rel
+ *   with dt >= the mixing time (Section 3.2), or when t >= t_end.
+ * Zero fields take the defaults in brackets. */
+typedef struct {
+  double tol_rel;    /* [1e-4]  */
+  double y_floor;    /* [1e-30] */
+  double y_sig;      /* [1e-10] */
+  double t_end;      /* [1e12 s] */
+  double dt0;        /* [1e-8 s] */
+  int32_t max_steps; /* [5000]  */
+  int32_t max_consec_rejects; /* [30] */
+  int32_t use_mix_rule;       /* 0/1 [1 if the struct is NULL] */
+  int32_t pad_;
+} xod_ss_opts;
+typedef struct {
+  double t, dt, clipped;
+  int64_t steps, rejects;
+  int32_t converged;
+  int32_t pad_;
+} xod_ss_result;
+xod_status xod_integrate_to_steady_state(xod_column *col,
+                                         const xod_ss_opts *opts,
+                                         xod_ss_result *res);
+
+/* Copy of the last error message of this thread (always NUL-terminated). */
+xod_status xod_last_error(char *buf, size_t len);
+
+/* Kernel options (process-wide; for tests and tuning).
+ *   "gemm": 0 = VALU FMA Schur update, 1 = MFMA Schur update (default). */
+xod_status xod_set_option(const char *name, int64_t value);
+
+/* ---- batches ---------------------------------------------------------- */
+
+/* A batch steps many columns together: columns with the same block size
+ * share every launch (their layer chains advance in lock step; a column
+ * with fewer layers idles once its chain ends).  Columns keep ownership of
+ * their state; a column may belong to one batch at a time. */
+xod_status xod_batch_create(xod_column *const *cols, int32_t ncols,
+                            xod_batch **out);
+xod_status xod_batch_destroy(xod_batch *b);
+/* One BE step of every column with its own dt (host array [ncols]); stats
+ * (host array [ncols]) may be NULL.  Synchronous. */
+xod_status xod_batch_step(xod_batch *b, const double *dt_per_col,
+                          xod_step_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XOD_H */

@@ -1,0 +1,329 @@
+"""Thin Python binding of libxod (the HIP implicit column solver).
+
+Argument marshalling only: every numerical step runs in the library's HIP
+kernels.  Device buffers are torch tensors (their data_ptr() is passed to
+the C ABI); host inputs are numpy arrays copied by the library at create
+time.  The names follow include/xod.h.
+
+If libxod.so is missing, importing this package raises: there is no CPU
+fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libxod.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "xod.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is not built; run `python paper_2512_06729_amd/build.py` "
+        "(there is no CPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+c_int32 = ctypes.c_int32
+c_double = ctypes.c_double
+c_void_p = ctypes.c_void_p
+P_int = ctypes.POINTER(ctypes.c_int32)
+P_dbl = ctypes.POINTER(ctypes.c_double)
+
+XOD_OK, XOD_EINVAL, XOD_ENOMEM, XOD_ESINGULAR, XOD_ENOTCONVERGED, \
+    XOD_ENONFINITE, XOD_EHIP, XOD_ENOTIMPL, XOD_EBUSY = range(9)
+STATUS_NAMES = ["OK", "EINVAL", "ENOMEM", "ESINGULAR", "ENOTCONVERGED",
+                "ENONFINITE", "EHIP", "ENOTIMPL", "EBUSY"]
+XOD_FP64, XOD_MIXED = 0, 1
+
+
+class XodError(RuntimeError):
+    def __init__(self, status, message):
+        self.status = status
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"XOD_{name}: {message}")
+
+
+class NetworkDesc(ctypes.Structure):
+    _fields_ = [("S", c_int32), ("R", c_int32), ("E", c_int32),
+                ("elem_comp", P_int), ("mass_amu", P_dbl), ("nasa7", P_dbl),
+                ("t_mid", c_double), ("rtype", P_int), ("reac", P_int),
+                ("prod", P_int), ("reversible", P_int), ("tb_kooij", P_int),
+                ("params", P_dbl)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("N", c_int32), ("P_bar", P_dbl), ("T_K", P_dbl), ("Kzz", P_dbl),
+                ("Dmol", P_dbl), ("alphaT", P_dbl), ("mbar_amu", c_double),
+                ("g_cgs", c_double), ("sigma_tau", c_double)]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("max_rel_change", c_double), ("min_ratio", c_double),
+                ("resid_inf", c_double), ("refine_iters", c_int32),
+                ("fp64_fallback", c_int32), ("nonfinite", c_int32), ("pad_", c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+
+
+class SSOpts(ctypes.Structure):
+    _fields_ = [("tol_rel", c_double), ("y_floor", c_double), ("y_sig", c_double),
+                ("t_end", c_double), ("dt0", c_double), ("max_steps", c_int32),
+                ("max_consec_rejects", c_int32), ("use_mix_rule", c_int32),
+                ("pad_", c_int32)]
+
+
+class SSResult(ctypes.Structure):
+    _fields_ = [("t", c_double), ("dt", c_double), ("clipped", c_double),
+                ("steps", ctypes.c_int64), ("rejects", ctypes.c_int64),
+                ("converged", c_int32), ("pad_", c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+
+
+def _sig(name, *args):
+    f = getattr(_lib, name)
+    f.restype = c_int32
+    f.argtypes = list(args)
+    return f
+
+
+_f = {
+    "xod_network_create": _sig("xod_network_create", ctypes.POINTER(NetworkDesc), ctypes.POINTER(c_void_p)),
+    "xod_network_destroy": _sig("xod_network_destroy", c_void_p),
+    "xod_network_sizes": _sig("xod_network_sizes", c_void_p, P_int, P_int, P_int),
+    "xod_column_create": _sig("xod_column_create", c_void_p, ctypes.POINTER(Profile), P_dbl,
+                              c_int32, c_void_p, ctypes.POINTER(c_void_p)),
+    "xod_column_destroy": _sig("xod_column_destroy", c_void_p),
+    "xod_column_get_state": _sig("xod_column_get_state", c_void_p, P_dbl, P_dbl, P_dbl),
+    "xod_column_set_state": _sig("xod_column_set_state", c_void_p, P_dbl, c_double, c_double),
+    "xod_column_state_ptr": _sig("xod_column_state_ptr", c_void_p, ctypes.POINTER(c_void_p)),
+    "xod_column_grid": _sig("xod_column_grid", c_void_p, P_dbl, P_dbl, P_dbl, P_dbl),
+    "xod_rates": _sig("xod_rates", c_void_p, c_void_p, c_void_p),
+    "xod_rhs": _sig("xod_rhs", c_void_p, c_void_p, c_void_p, c_void_p, c_void_p),
+    "xod_jacobian": _sig("xod_jacobian", c_void_p, c_void_p, c_void_p, c_void_p, c_double,
+                         c_void_p, c_void_p, c_void_p, c_int32),
+    "xod_btd_factor": _sig("xod_btd_factor", c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
+                           c_void_p),
+    "xod_btd_solve": _sig("xod_btd_solve", c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
+                          c_void_p, c_void_p),
+    "xod_step": _sig("xod_step", c_void_p, c_double, ctypes.POINTER(StepStats)),
+    "xod_integrate_to_steady_state": _sig("xod_integrate_to_steady_state", c_void_p,
+                                          ctypes.POINTER(SSOpts), ctypes.POINTER(SSResult)),
+    "xod_last_error": _sig("xod_last_error", ctypes.c_char_p, ctypes.c_size_t),
+    "xod_set_option": _sig("xod_set_option", ctypes.c_char_p, ctypes.c_int64),
+    "xod_batch_create": _sig("xod_batch_create", ctypes.POINTER(c_void_p), c_int32,
+                             ctypes.POINTER(c_void_p)),
+    "xod_batch_destroy": _sig("xod_batch_destroy", c_void_p),
+    "xod_batch_step": _sig("xod_batch_step", c_void_p, P_dbl, ctypes.POINTER(StepStats)),
+}
+
+
+def header_symbols(path=HEADER):
+    """Function names declared in include/xod.h."""
+    text = open(path).read()
+    return sorted(set(re.findall(r"\b(xod_[a-z0-9_]+)\s*\(", text)))
+
+
+def last_error():
+    buf = ctypes.create_string_buffer(1024)
+    _f["xod_last_error"](buf, 1024)
+    return buf.value.decode(errors="replace")
+
+
+def _check(status):
+    if status != XOD_OK:
+        raise XodError(status, last_error())
+
+
+def set_option(name, value):
+    _check(_f["xod_set_option"](name.encode(), int(value)))
+
+
+def _ptr(arr, ctype):
+    return arr.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _dev(t):
+    """Device pointer of a torch tensor (the library never frees it)."""
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return c_void_p(t.data_ptr())
+
+
+class Network:
+    """Device-resident reaction network (xod_network)."""
+
+    def __init__(self, net):
+        self._keep = dict(
+            elem_comp=np.ascontiguousarray(net.elem_comp, np.int32),
+            mass=np.ascontiguousarray(net.mass_amu, np.float64),
+            nasa7=np.ascontiguousarray(net.nasa7, np.float64),
+            rtype=np.ascontiguousarray(net.rtype, np.int32),
+            reac=np.ascontiguousarray(net.reac, np.int32),
+            prod=np.ascontiguousarray(net.prod, np.int32),
+            rev=np.ascontiguousarray(net.reversible, np.int32),
+            kooij=np.ascontiguousarray(net.tb_kooij, np.int32),
+            params=np.ascontiguousarray(net.params, np.float64))
+        k = self._keep
+        S = k["mass"].shape[0]
+        R = k["rtype"].shape[0]
+        E = k["elem_comp"].shape[0]
+        d = NetworkDesc(S, R, E, _ptr(k["elem_comp"], c_int32), _ptr(k["mass"], c_double),
+                        _ptr(k["nasa7"], c_double), float(net.t_mid),
+                        _ptr(k["rtype"], c_int32), _ptr(k["reac"], c_int32),
+                        _ptr(k["prod"], c_int32), _ptr(k["rev"], c_int32),
+                        _ptr(k["kooij"], c_int32), _ptr(k["params"], c_double))
+        h = c_void_p()
+        _check(_f["xod_network_create"](ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+        S_, R_, ld = c_int32(), c_int32(), c_int32()
+        _check(_f["xod_network_sizes"](h, ctypes.byref(S_), ctypes.byref(R_), ctypes.byref(ld)))
+        self.S, self.R, self.ld = S_.value, R_.value, ld.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _f["xod_network_destroy"](self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Column:
+    """One atmospheric column (xod_column): device state + workspace."""
+
+    def __init__(self, network, col, precision=XOD_FP64, stream=None, n0=None):
+        self.network = network
+        N = int(np.asarray(col.P_bar).shape[0])
+        S = network.S
+        self.N, self.S, self.R, self.ld = N, S, network.R, network.ld
+        self._keep = dict(P=np.ascontiguousarray(col.P_bar, np.float64),
+                          T=np.ascontiguousarray(col.T_K, np.float64),
+                          K=np.ascontiguousarray(col.Kzz, np.float64))
+        k = self._keep
+        if col.Dmol is not None:
+            k["D"] = np.ascontiguousarray(col.Dmol, np.float64)
+        if col.alphaT is not None:
+            k["alpha"] = np.ascontiguousarray(col.alphaT, np.float64)
+        prof = Profile(N, _ptr(k["P"], c_double), _ptr(k["T"], c_double), _ptr(k["K"], c_double),
+                       _ptr(k["D"], c_double) if "D" in k else None,
+                       _ptr(k["alpha"], c_double) if "alpha" in k else None,
+                       float(col.mbar_amu), float(col.g_cgs), float(col.sigma_tau))
+        n0 = np.ascontiguousarray(col.n0 if n0 is None else n0, np.float64)
+        if n0.shape != (N, S):
+            raise ValueError(f"n0 must have shape {(N, S)}")
+        h = c_void_p()
+        _check(_f["xod_column_create"](network.handle, ctypes.byref(prof), _ptr(n0, c_double),
+                                       int(precision), c_void_p(stream or 0), ctypes.byref(h)))
+        self.handle = h
+
+    def state(self):
+        n = np.empty((self.N, self.S))
+        t, dt = c_double(), c_double()
+        _check(_f["xod_column_get_state"](self.handle, _ptr(n, c_double), ctypes.byref(t),
+                                          ctypes.byref(dt)))
+        return n
+
+    def set_state(self, n, t=0.0, dt=0.0):
+        n = np.ascontiguousarray(n, np.float64)
+        _check(_f["xod_column_set_state"](self.handle, _ptr(n, c_double), t, dt))
+
+    def grid(self):
+        ng, tau, dz = np.empty(self.N), np.empty(self.N), np.empty(self.N)
+        mix = c_double()
+        _check(_f["xod_column_grid"](self.handle, _ptr(ng, c_double), _ptr(tau, c_double),
+                                     _ptr(dz, c_double), ctypes.byref(mix)))
+        return dict(ngas=ng, tau=tau, dz=dz, mix_time=mix.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _f["xod_column_destroy"](self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- hot-path calls (torch device tensors) --------------------------------
+
+def xod_rates(col, kf, kr):
+    _check(_f["xod_rates"](col.handle, _dev(kf), _dev(kr)))
+
+
+def xod_rhs(col, kf, kr, n, f):
+    _check(_f["xod_rhs"](col.handle, _dev(kf), _dev(kr), _dev(n), _dev(f)))
+
+
+def xod_jacobian(col, kf, kr, n, dt, B, a, c):
+    _check(_f["xod_jacobian"](col.handle, _dev(kf), _dev(kr), _dev(n), float(dt), _dev(B),
+                              _dev(a), _dev(c), col.ld))
+
+
+def xod_btd_factor(col, B, a, c, piv):
+    _check(_f["xod_btd_factor"](col.handle, _dev(B), _dev(a), _dev(c), col.ld, _dev(piv)))
+
+
+def xod_btd_solve(col, B, a, c, piv, rhs):
+    _check(_f["xod_btd_solve"](col.handle, _dev(B), _dev(a), _dev(c), col.ld, _dev(piv),
+                               _dev(rhs)))
+
+
+def xod_step(col, dt):
+    st = StepStats()
+    _check(_f["xod_step"](col.handle, float(dt), ctypes.byref(st)))
+    return st.as_dict()
+
+
+def xod_integrate_to_steady_state(col, tol_rel=0.0, y_floor=0.0, y_sig=0.0, t_end=0.0,
+                                  dt0=0.0, max_steps=0, max_consec_rejects=0,
+                                  use_mix_rule=1, check=True):
+    o = SSOpts(tol_rel, y_floor, y_sig, t_end, dt0, max_steps, max_consec_rejects,
+               use_mix_rule, 0)
+    r = SSResult()
+    st = _f["xod_integrate_to_steady_state"](col.handle, ctypes.byref(o), ctypes.byref(r))
+    if check and st not in (XOD_OK,):
+        raise XodError(st, last_error())
+    out = r.as_dict()
+    out["status"] = st
+    return out
+
+
+class Batch:
+    """Columns stepped together (xod_batch)."""
+
+    def __init__(self, columns):
+        self.columns = list(columns)
+        arr = (c_void_p * len(self.columns))(*[c.handle for c in self.columns])
+        h = c_void_p()
+        _check(_f["xod_batch_create"](arr, len(self.columns), ctypes.byref(h)))
+        self.handle = h
+
+    def step(self, dts):
+        dts = np.ascontiguousarray(dts, np.float64)
+        stats = (StepStats * len(self.columns))()
+        _check(_f["xod_batch_step"](self.handle, _ptr(dts, c_double), stats))
+        return [s.as_dict() for s in stats]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _f["xod_batch_destroy"](self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

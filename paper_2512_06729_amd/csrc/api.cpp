@@ -1,0 +1,638 @@
+// C ABI of libxod: handles, validation, host-side table construction, the
+// backward-Euler step and the steady-state driver.  Every numerical step runs
+// in the HIP kernels of k_chem.hip, k_btd.hip, k_mixed.hip and k_step.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "xod_internal.h"
+
+namespace xod {
+
+static thread_local std::string g_err;
+void set_error(const std::string &m) { g_err = m; }
+std::string &last_error() { return g_err; }
+Options &options() {
+  static Options o;
+  return o;
+}
+
+}  // namespace xod
+
+using namespace xod;
+
+// ---------------------------------------------------------------------------
+// Device buffer helpers.
+namespace {
+
+template <class T>
+xod_status dalloc(T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    set_error(std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    *p = nullptr;
+    return XOD_ENOMEM;
+  }
+  return XOD_OK;
+}
+
+template <class T>
+xod_status dupload(T **p, const T *host, size_t count) {
+  xod_status s = dalloc(p, count);
+  if (s != XOD_OK) return s;
+  if (count && host) XOD_HIP(hipMemcpy(*p, host, count * sizeof(T), hipMemcpyHostToDevice));
+  return XOD_OK;
+}
+
+#define XOD_TRY(expr)                 \
+  do {                                \
+    xod_status s_ = (expr);           \
+    if (s_ != XOD_OK) return s_;      \
+  } while (0)
+
+#define XOD_CHECK(cond, msg)          \
+  do {                                \
+    if (!(cond)) {                    \
+      set_error(msg);                 \
+      return XOD_EINVAL;              \
+    }                                 \
+  } while (0)
+
+}  // namespace
+
+#include "handles.h"
+
+namespace {
+
+template <class T>
+xod_status nalloc(xod_network *net, T **p, size_t count, const T *host = nullptr) {
+  XOD_TRY(host ? dupload(p, host, count) : dalloc(p, count));
+  net->owned.push_back(*p);
+  return XOD_OK;
+}
+
+template <class T>
+xod_status calloc_(xod_column *col, T **p, size_t count, const T *host = nullptr) {
+  XOD_TRY(host ? dupload(p, host, count) : dalloc(p, count));
+  col->owned.push_back(*p);
+  return XOD_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" xod_status xod_last_error(char *buf, size_t len) {
+  if (!buf || len == 0) return XOD_EINVAL;
+  const std::string &e = last_error();
+  size_t m = std::min(len - 1, e.size());
+  std::memcpy(buf, e.data(), m);
+  buf[m] = '\0';
+  return XOD_OK;
+}
+
+extern "C" xod_status xod_set_option(const char *name, int64_t value) {
+  XOD_CHECK(name != nullptr, "xod_set_option: null name");
+  if (std::strcmp(name, "gemm") == 0) {
+    XOD_CHECK(value == 0 || value == 1, "xod_set_option: gemm must be 0 or 1");
+    options().gemm_mfma = (int)value;
+    return XOD_OK;
+  }
+  set_error(std::string("xod_set_option: unknown option ") + name);
+  return XOD_EINVAL;
+}
+
+extern "C" xod_status xod_network_create(const xod_network_desc *d, xod_network **out) {
+  XOD_CHECK(d && out, "xod_network_create: null argument");
+  *out = nullptr;
+  XOD_CHECK(d->S >= 1 && d->R >= 0 && d->E >= 0, "xod_network_create: bad sizes");
+  XOD_CHECK(d->S <= kMaxLd, "xod_network_create: S > 1024 is not supported");
+  const int S = d->S, R = d->R;
+  XOD_CHECK(d->mass_amu && d->nasa7, "xod_network_create: null mass/nasa7");
+  XOD_CHECK(R == 0 || (d->rtype && d->reac && d->prod && d->reversible && d->tb_kooij &&
+                       d->params),
+            "xod_network_create: null reaction array");
+  for (int y = 0; y < S; ++y)
+    XOD_CHECK(std::isfinite(d->mass_amu[y]) && d->mass_amu[y] > 0.0,
+              "xod_network_create: species mass must be positive");
+  for (int i = 0; i < S * 14; ++i)
+    XOD_CHECK(std::isfinite(d->nasa7[i]), "xod_network_create: non-finite NASA-7 coefficient");
+  std::vector<int> dnu(R, 0);
+  for (int r = 0; r < R; ++r) {
+    XOD_CHECK(d->rtype[r] >= 0 && d->rtype[r] <= 2, "xod_network_create: bad reaction type");
+    int nre = 0, npr = 0;
+    for (int j = 0; j < XOD_MAX_REAC; ++j) {
+      const int y = d->reac[r * XOD_MAX_REAC + j];
+      XOD_CHECK(y >= -1 && y < S, "xod_network_create: reactant id out of range");
+      nre += y >= 0;
+    }
+    for (int j = 0; j < XOD_MAX_PROD; ++j) {
+      const int y = d->prod[r * XOD_MAX_PROD + j];
+      XOD_CHECK(y >= -1 && y < S, "xod_network_create: product id out of range");
+      npr += y >= 0;
+    }
+    XOD_CHECK(nre >= 1, "xod_network_create: reaction without reactant");
+    for (int j = 0; j < 6; ++j)
+      XOD_CHECK(std::isfinite(d->params[r * 6 + j]), "xod_network_create: non-finite parameter");
+    dnu[r] = npr - nre;
+  }
+
+  std::unique_ptr<xod_network> net(new xod_network());
+  net->S = S;
+  net->R = R;
+  net->E = d->E;
+  net->ld = round_up(S, 32);
+  net->t_mid = d->t_mid;
+  net->mass_h.assign(d->mass_amu, d->mass_amu + S);
+
+  // Net stoichiometry nu[y][r] and the species -> reaction incidence lists.
+  std::vector<std::map<int, double>> nu_r(R);
+  for (int r = 0; r < R; ++r) {
+    for (int j = 0; j < XOD_MAX_PROD; ++j) {
+      const int y = d->prod[r * XOD_MAX_PROD + j];
+      if (y >= 0) nu_r[r][y] += 1.0;
+    }
+    for (int j = 0; j < XOD_MAX_REAC; ++j) {
+      const int y = d->reac[r * XOD_MAX_REAC + j];
+      if (y >= 0) nu_r[r][y] -= 1.0;
+    }
+  }
+  std::vector<std::vector<std::pair<int, double>>> inc(S);
+  for (int r = 0; r < R; ++r)
+    for (auto &kv : nu_r[r])
+      if (kv.second != 0.0) inc[kv.first].push_back({r, kv.second});
+  std::vector<int> inc_ptr(S + 1, 0), inc_r;
+  std::vector<double> inc_nu;
+  for (int y = 0; y < S; ++y) {
+    for (auto &e : inc[y]) {
+      inc_r.push_back(e.first);
+      inc_nu.push_back(e.second);
+    }
+    inc_ptr[y + 1] = (int)inc_r.size();
+  }
+
+  // Jacobian pattern: entry (y, x) collects (r, nu_{y,r}) for every reaction
+  // r in which x takes part and y changes.
+  std::map<std::pair<int, int>, std::vector<std::pair<int, double>>> ent;
+  for (int r = 0; r < R; ++r) {
+    std::vector<int> xs;
+    for (int j = 0; j < XOD_MAX_REAC; ++j) {
+      const int y = d->reac[r * XOD_MAX_REAC + j];
+      if (y >= 0 && std::find(xs.begin(), xs.end(), y) == xs.end()) xs.push_back(y);
+    }
+    for (int j = 0; j < XOD_MAX_PROD; ++j) {
+      const int y = d->prod[r * XOD_MAX_PROD + j];
+      if (y >= 0 && std::find(xs.begin(), xs.end(), y) == xs.end()) xs.push_back(y);
+    }
+    for (auto &kv : nu_r[r]) {
+      if (kv.second == 0.0) continue;
+      for (int x : xs) ent[{kv.first, x}].push_back({r, kv.second});
+    }
+  }
+  std::vector<int> jmap((size_t)S * S, -1), jptr(1, 0), jc_r;
+  std::vector<double> jc_nu;
+  for (auto &kv : ent) {
+    jmap[(size_t)kv.first.first * S + kv.first.second] = (int)jptr.size() - 1;
+    for (auto &e : kv.second) {
+      jc_r.push_back(e.first);
+      jc_nu.push_back(e.second);
+    }
+    jptr.push_back((int)jc_r.size());
+  }
+  net->nnz = (int)jptr.size() - 1;
+  net->ncontrib = (int)jc_r.size();
+
+  xod_network *n = net.get();
+  XOD_TRY(nalloc(n, &n->rtype, R, d->rtype));
+  XOD_TRY(nalloc(n, &n->reac, (size_t)R * XOD_MAX_REAC, d->reac));
+  XOD_TRY(nalloc(n, &n->prod, (size_t)R * XOD_MAX_PROD, d->prod));
+  XOD_TRY(nalloc(n, &n->rev, R, d->reversible));
+  XOD_TRY(nalloc(n, &n->kooij, R, d->tb_kooij));
+  XOD_TRY(nalloc(n, &n->dnu, R, dnu.data()));
+  XOD_TRY(nalloc(n, &n->params, (size_t)R * 6, d->params));
+  XOD_TRY(nalloc(n, &n->nasa7, (size_t)S * 14, d->nasa7));
+  XOD_TRY(nalloc(n, &n->mass, S, d->mass_amu));
+  XOD_TRY(nalloc(n, &n->inc_ptr, S + 1, inc_ptr.data()));
+  XOD_TRY(nalloc(n, &n->inc_r, inc_r.size(), inc_r.data()));
+  XOD_TRY(nalloc(n, &n->inc_nu, inc_nu.size(), inc_nu.data()));
+  XOD_TRY(nalloc(n, &n->jmap, jmap.size(), jmap.data()));
+  XOD_TRY(nalloc(n, &n->jptr, jptr.size(), jptr.data()));
+  XOD_TRY(nalloc(n, &n->jc_r, jc_r.size(), jc_r.data()));
+  XOD_TRY(nalloc(n, &n->jc_nu, jc_nu.size(), jc_nu.data()));
+  *out = net.release();
+  return XOD_OK;
+}
+
+extern "C" xod_status xod_network_destroy(xod_network *net) {
+  XOD_CHECK(net, "xod_network_destroy: null network");
+  delete net;
+  return XOD_OK;
+}
+
+extern "C" xod_status xod_network_sizes(const xod_network *net, int32_t *S, int32_t *R,
+                                        int32_t *ld) {
+  XOD_CHECK(net, "xod_network_sizes: null network");
+  if (S) *S = net->S;
+  if (R) *R = net->R;
+  if (ld) *ld = net->ld;
+  return XOD_OK;
+}
+
+extern "C" xod_status xod_column_create(const xod_network *net, const xod_profile *p,
+                                        const double *n0, xod_precision prec, void *stream,
+                                        xod_column **out) {
+  XOD_CHECK(net && p && n0 && out, "xod_column_create: null argument");
+  *out = nullptr;
+  XOD_CHECK(prec == XOD_FP64 || prec == XOD_MIXED, "xod_column_create: bad precision");
+  const int N = p->N, S = net->S;
+  XOD_CHECK(N >= 1 && N <= 100000, "xod_column_create: N out of range");
+  XOD_CHECK(p->P_bar && p->T_K && p->Kzz, "xod_column_create: null profile array");
+  XOD_CHECK(p->mbar_amu > 0 && p->g_cgs > 0 && p->sigma_tau >= 0 &&
+                std::isfinite(p->mbar_amu) && std::isfinite(p->g_cgs) &&
+                std::isfinite(p->sigma_tau),
+            "xod_column_create: bad mbar/g/sigma_tau");
+  for (int k = 0; k < N; ++k) {
+    XOD_CHECK(std::isfinite(p->P_bar[k]) && p->P_bar[k] > 0, "xod_column_create: P must be > 0");
+    XOD_CHECK(std::isfinite(p->T_K[k]) && p->T_K[k] > 0, "xod_column_create: T must be > 0");
+    XOD_CHECK(std::isfinite(p->Kzz[k]) && p->Kzz[k] >= 0, "xod_column_create: Kzz must be >= 0");
+    if (k > 0)
+      XOD_CHECK(p->P_bar[k] < p->P_bar[k - 1], "xod_column_create: P must decrease upward");
+  }
+  if (p->Dmol)
+    for (size_t e = 0; e < (size_t)N * S; ++e)
+      XOD_CHECK(std::isfinite(p->Dmol[e]) && p->Dmol[e] >= 0, "xod_column_create: bad Dmol");
+  if (p->alphaT)
+    for (int y = 0; y < S; ++y)
+      XOD_CHECK(std::isfinite(p->alphaT[y]), "xod_column_create: bad alphaT");
+  for (size_t e = 0; e < (size_t)N * S; ++e)
+    XOD_CHECK(std::isfinite(n0[e]), "xod_column_create: non-finite n0");
+
+  std::unique_ptr<xod_column> col(new xod_column());
+  xod_column *c = col.get();
+  c->net = net;
+  c->N = N;
+  c->S = S;
+  c->R = net->R;
+  c->ld = net->ld;
+  c->prec = prec;
+  c->stream = (hipStream_t)stream;
+  const size_t NS = (size_t)N * S, NR = (size_t)N * net->R, NL = (size_t)N * c->ld;
+  const size_t NLL = NL * c->ld;
+  XOD_TRY(calloc_(c, &c->P, N, p->P_bar));
+  XOD_TRY(calloc_(c, &c->T, N, p->T_K));
+  XOD_TRY(calloc_(c, &c->K, N, p->Kzz));
+  if (p->Dmol) XOD_TRY(calloc_(c, &c->D, NS, p->Dmol));
+  if (p->alphaT) XOD_TRY(calloc_(c, &c->alpha, (size_t)S, p->alphaT));
+  XOD_TRY(calloc_(c, &c->ngas, N));
+  XOD_TRY(calloc_(c, &c->tau, N));
+  XOD_TRY(calloc_(c, &c->lnpref, N));
+  XOD_TRY(calloc_(c, &c->dz, N));
+  XOD_TRY(calloc_(c, &c->dzh, N));
+  XOD_TRY(calloc_(c, &c->mix, 1));
+  XOD_TRY(calloc_(c, &c->g, NS));
+  XOD_TRY(calloc_(c, &c->trl, NS));
+  XOD_TRY(calloc_(c, &c->trd, NS));
+  XOD_TRY(calloc_(c, &c->tru, NS));
+  XOD_TRY(calloc_(c, &c->n, NS, n0));
+  XOD_TRY(calloc_(c, &c->ntmp, NS));
+  XOD_TRY(calloc_(c, &c->f, NS));
+  XOD_TRY(calloc_(c, &c->x, NS));
+  XOD_TRY(calloc_(c, &c->resid, NS));
+  XOD_TRY(calloc_(c, &c->dx, NS));
+  XOD_TRY(calloc_(c, &c->kf, NR));
+  XOD_TRY(calloc_(c, &c->kr, NR));
+  XOD_TRY(calloc_(c, &c->w, NR));
+  XOD_TRY(calloc_(c, &c->gs, NL));
+  XOD_TRY(calloc_(c, &c->a, NL));
+  XOD_TRY(calloc_(c, &c->c, NL));
+  XOD_TRY(calloc_(c, &c->rs, NL));
+  XOD_TRY(calloc_(c, &c->piv, NL));
+  XOD_TRY(calloc_(c, &c->rstep, NL));
+  XOD_TRY(calloc_(c, &c->flag, 4));
+  XOD_TRY(calloc_(c, &c->B, NLL));
+  if (prec == XOD_MIXED) {
+    XOD_TRY(calloc_(c, &c->Bf, NLL));
+    XOD_TRY(calloc_(c, &c->a64, NL));
+    XOD_TRY(calloc_(c, &c->c64, NL));
+  }
+  XOD_TRY(calloc_(c, &c->partial, (size_t)kUpdBlocks * kNStat));
+  XOD_TRY(calloc_(c, &c->stats_dev, kStatLen));
+  XOD_TRY(calloc_(c, &c->upd_dev, 1));
+  XOD_TRY(calloc_(c, &c->red_dev, 1));
+  XOD_HIP(hipHostMalloc((void **)&c->stats_host, kStatLen * sizeof(double), hipHostMallocDefault));
+
+  SetupArgs sa{};
+  sa.N = N;
+  sa.S = S;
+  sa.P_bar = c->P;
+  sa.T = c->T;
+  sa.K = c->K;
+  sa.D = c->D;
+  sa.alpha = c->alpha;
+  sa.mass = net->mass;
+  sa.nasa7 = net->nasa7;
+  sa.t_mid = net->t_mid;
+  sa.mbar_amu = p->mbar_amu;
+  sa.g_cgs = p->g_cgs;
+  sa.sigma_tau = p->sigma_tau;
+  sa.ngas = c->ngas;
+  sa.tau = c->tau;
+  sa.lnpref = c->lnpref;
+  sa.g = c->g;
+  sa.trl = c->trl;
+  sa.trd = c->trd;
+  sa.tru = c->tru;
+  sa.dz = c->dz;
+  sa.dzh = c->dzh;
+  sa.mix = c->mix;
+  XOD_HIP(launch_setup(sa, c->stream));
+  XOD_HIP(hipMemcpyAsync(&c->mix_time, c->mix, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  XOD_HIP(hipStreamSynchronize(c->stream));
+  *out = col.release();
+  return XOD_OK;
+}
+
+extern "C" xod_status xod_column_destroy(xod_column *col) {
+  XOD_CHECK(col, "xod_column_destroy: null column");
+  (void)hipStreamSynchronize(col->stream);
+  delete col;
+  return XOD_OK;
+}
+
+extern "C" xod_status xod_column_get_state(const xod_column *col, double *n, double *t,
+                                           double *dt) {
+  XOD_CHECK(col && n, "xod_column_get_state: null argument");
+  XOD_HIP(hipMemcpyAsync(n, col->n, (size_t)col->N * col->S * sizeof(double),
+                         hipMemcpyDeviceToHost, col->stream));
+  XOD_HIP(hipStreamSynchronize(col->stream));
+  if (t) *t = col->t;
+  if (dt) *dt = col->dt;
+  return XOD_OK;
+}
+
+extern "C" xod_status xod_column_set_state(xod_column *col, const double *n, double t,
+                                           double dt) {
+  XOD_CHECK(col && n, "xod_column_set_state: null argument");
+  for (size_t e = 0; e < (size_t)col->N * col->S; ++e)
+    XOD_CHECK(std::isfinite(n[e]), "xod_column_set_state: non-finite state");
+  XOD_HIP(hipMemcpyAsync(col->n, n, (size_t)col->N * col->S * sizeof(double),
+                         hipMemcpyHostToDevice, col->stream));
+  XOD_HIP(hipStreamSynchronize(col->stream));
+  col->t = t;
+  col->dt = dt;
+  return XOD_OK;
+}
+
+extern "C" xod_status xod_column_state_ptr(xod_column *col, double **n_dev) {
+  XOD_CHECK(col && n_dev, "xod_column_state_ptr: null argument");
+  *n_dev = col->n;
+  return XOD_OK;
+}
+
+extern "C" xod_status xod_column_grid(const xod_column *col, double *ngas, double *tau,
+                                      double *dz, double *mix_time) {
+  XOD_CHECK(col, "xod_column_grid: null column");
+  const size_t bytes = (size_t)col->N * sizeof(double);
+  if (ngas) XOD_HIP(hipMemcpyAsync(ngas, col->ngas, bytes, hipMemcpyDeviceToHost, col->stream));
+  if (tau) XOD_HIP(hipMemcpyAsync(tau, col->tau, bytes, hipMemcpyDeviceToHost, col->stream));
+  if (dz) XOD_HIP(hipMemcpyAsync(dz, col->dz, bytes, hipMemcpyDeviceToHost, col->stream));
+  XOD_HIP(hipStreamSynchronize(col->stream));
+  if (mix_time) *mix_time = col->mix_time;
+  return XOD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Hot-path calls on caller-owned device buffers.
+extern "C" xod_status xod_rates(xod_column *col, double *kf, double *kr) {
+  XOD_CHECK(col && kf && kr, "xod_rates: null argument");
+  ColArgs a = col->args();
+  a.kf = kf;
+  a.kr = kr;
+  XOD_HIP(launch_rates(OneCol{a}, 1, col->N, col->R, col->stream));
+  return XOD_OK;
+}
+
+extern "C" xod_status xod_rhs(xod_column *col, const double *kf, const double *kr,
+                              const double *n, double *f) {
+  XOD_CHECK(col && kf && kr && n && f, "xod_rhs: null argument");
+  ColArgs a = col->args();
+  a.kf_in = kf;
+  a.kr_in = kr;
+  a.n = n;
+  a.f = f;
+  XOD_HIP(launch_rhs(OneCol{a}, 1, col->N, col->R, col->S, col->stream));
+  return XOD_OK;
+}
+
+extern "C" xod_status xod_jacobian(xod_column *col, const double *kf, const double *kr,
+                                   const double *n, double dt, double *B, double *av,
+                                   double *cv, int32_t ld) {
+  XOD_CHECK(col && kf && kr && n && B && av && cv, "xod_jacobian: null argument");
+  XOD_CHECK(ld == col->ld, "xod_jacobian: ld must equal the network's padded size");
+  XOD_CHECK(std::isfinite(dt) && dt > 0, "xod_jacobian: dt must be > 0");
+  ColArgs a = col->args();
+  a.kf_in = kf;
+  a.kr_in = kr;
+  a.n = n;
+  a.dt = dt;
+  a.B = B;
+  a.a = av;
+  a.c = cv;
+  XOD_HIP(launch_jacobian(OneCol{a}, 1, col->N, col->ld, false, col->stream));
+  return XOD_OK;
+}
+
+static xod_status check_flags(xod_column *col, const double *flags) {
+  if (flags[0] >= 0) {
+    set_error("singular Schur complement: layer " + std::to_string((long)flags[0]) +
+              ", column " + std::to_string((long)flags[1]));
+    return XOD_ESINGULAR;
+  }
+  (void)col;
+  return XOD_OK;
+}
+
+extern "C" xod_status xod_btd_factor(xod_column *col, double *B, const double *av,
+                                     const double *cv, int32_t ld, int32_t *piv) {
+  XOD_CHECK(col && B && av && cv && piv, "xod_btd_factor: null argument");
+  XOD_CHECK(ld == col->ld, "xod_btd_factor: ld must equal the network's padded size");
+  ColArgs a = col->args();
+  a.B = B;
+  a.a = const_cast<double *>(av);
+  a.c = const_cast<double *>(cv);
+  a.piv = piv;
+  XOD_HIP(launch_factor_fp64(OneCol{a}, 1, col->N, col->ld, col->stream));
+  int fl[4];
+  XOD_HIP(hipMemcpyAsync(fl, col->flag, sizeof(fl), hipMemcpyDeviceToHost, col->stream));
+  XOD_HIP(hipStreamSynchronize(col->stream));
+  double fd[2] = {(double)fl[0], (double)fl[1]};
+  return check_flags(col, fd);
+}
+
+extern "C" xod_status xod_btd_solve(xod_column *col, const double *B, const double *av,
+                                    const double *cv, int32_t ld, const int32_t *piv,
+                                    double *rhs) {
+  XOD_CHECK(col && B && av && cv && piv && rhs, "xod_btd_solve: null argument");
+  XOD_CHECK(ld == col->ld, "xod_btd_solve: ld must equal the network's padded size");
+  XOD_HIP(launch_invperm(piv, col->rstep, col->N, col->ld, col->stream));
+  ColArgs a = col->args();
+  a.B = const_cast<double *>(B);
+  a.a = const_cast<double *>(av);
+  a.c = const_cast<double *>(cv);
+  a.piv = const_cast<int *>(piv);
+  a.x = rhs;
+  XOD_HIP(launch_solve_fp64(OneCol{a}, 1, col->N, col->ld, col->stream));
+  return XOD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Backward-Euler step on the column's own buffers.
+namespace {
+
+// Enqueue rates + rhs + jacobian + factor + solve for the column (FP64 or
+// mixed); delta ends in col->x.  Returns the refinement count via *iters.
+xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, double *resid);
+
+xod_status run_update(xod_column *c, bool clip, double y_floor, double y_sig, double *out) {
+  UpdArgs u{};
+  u.n = c->n;
+  u.x = c->x;
+  u.ngas = c->ngas;
+  u.nout = c->ntmp;
+  u.partial = c->partial;
+  u.N = c->N;
+  u.S = c->S;
+  u.clip = clip ? 1 : 0;
+  u.y_floor = y_floor;
+  u.y_sig = y_sig;
+  RedArgs r{c->partial, c->flag, c->stats_dev};
+  XOD_HIP(hipMemcpyAsync(c->upd_dev, &u, sizeof(u), hipMemcpyHostToDevice, c->stream));
+  XOD_HIP(hipMemcpyAsync(c->red_dev, &r, sizeof(r), hipMemcpyHostToDevice, c->stream));
+  XOD_HIP(launch_update_state(c->upd_dev, c->red_dev, 1, c->stream));
+  XOD_HIP(hipMemcpyAsync(c->stats_host, c->stats_dev, kStatLen * sizeof(double),
+                         hipMemcpyDeviceToHost, c->stream));
+  XOD_HIP(hipStreamSynchronize(c->stream));
+  std::memcpy(out, c->stats_host, kStatLen * sizeof(double));
+  return XOD_OK;
+}
+
+xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, double *resid) {
+  c->dt = dt;
+  ColArgs a = c->args();
+  OneCol one{a};
+  *iters = 0;
+  *fallback = 0;
+  *resid = 0.0;
+  XOD_HIP(launch_rates(one, 1, c->N, c->R, c->stream));
+  XOD_HIP(launch_rhs(one, 1, c->N, c->R, c->S, c->stream));
+  if (c->prec == XOD_FP64) {
+    XOD_HIP(launch_jacobian(one, 1, c->N, c->ld, false, c->stream));
+    XOD_HIP(launch_factor_fp64(one, 1, c->N, c->ld, c->stream));
+    XOD_HIP(hipMemcpyAsync(c->x, c->f, (size_t)c->N * c->S * sizeof(double),
+                           hipMemcpyDeviceToDevice, c->stream));
+    XOD_HIP(launch_solve_fp64(one, 1, c->N, c->ld, c->stream));
+    return XOD_OK;
+  }
+  set_error("mixed precision step not available in this build");
+  return XOD_ENOTIMPL;
+}
+
+}  // namespace
+
+extern "C" xod_status xod_step(xod_column *col, double dt, xod_step_stats *st) {
+  XOD_CHECK(col, "xod_step: null column");
+  XOD_CHECK(!col->in_batch, "xod_step: column belongs to a batch");
+  XOD_CHECK(std::isfinite(dt) && dt > 0, "xod_step: dt must be > 0");
+  int iters, fb;
+  double res;
+  XOD_TRY(enqueue_solve(col, dt, &iters, &fb, &res));
+  double s[kStatLen];
+  XOD_TRY(run_update(col, false, 1e-30, 1e-10, s));
+  XOD_TRY(check_flags(col, s + kNStat));
+  if (st) {
+    st->max_rel_change = s[0];
+    st->min_ratio = s[1];
+    st->resid_inf = res;
+    st->refine_iters = iters;
+    st->fp64_fallback = fb;
+    st->nonfinite = s[5] > 0 ? 1 : 0;
+  }
+  if (s[5] > 0) {
+    set_error("xod_step: non-finite state after the step");
+    return XOD_ENONFINITE;
+  }
+  std::swap(col->n, col->ntmp);
+  col->t += dt;
+  col->dt = dt;
+  return XOD_OK;
+}
+
+extern "C" xod_status xod_integrate_to_steady_state(xod_column *col, const xod_ss_opts *o,
+                                                    xod_ss_result *res) {
+  XOD_CHECK(col && res, "xod_integrate_to_steady_state: null argument");
+  XOD_CHECK(!col->in_batch, "xod_integrate_to_steady_state: column belongs to a batch");
+  double tol = 1e-4, yfl = 1e-30, ysig = 1e-10, tend = 1e12, dt0 = 1e-8;
+  int maxs = 5000, maxrej = 30, mixrule = 1;
+  if (o) {
+    if (o->tol_rel > 0) tol = o->tol_rel;
+    if (o->y_floor > 0) yfl = o->y_floor;
+    if (o->y_sig > 0) ysig = o->y_sig;
+    if (o->t_end > 0) tend = o->t_end;
+    if (o->dt0 > 0) dt0 = o->dt0;
+    if (o->max_steps > 0) maxs = o->max_steps;
+    if (o->max_consec_rejects > 0) maxrej = o->max_consec_rejects;
+    mixrule = o->use_mix_rule;
+  }
+  const double mix = mixrule ? col->mix_time : 0.0;
+  double t = 0.0, dt = dt0, clipped = 0.0;
+  int64_t steps = 0, rejects = 0;
+  int consec = 0;
+  int converged = 0;
+  while (steps < maxs) {
+    int iters, fb;
+    double rr;
+    XOD_TRY(enqueue_solve(col, dt, &iters, &fb, &rr));
+    double s[kStatLen];
+    XOD_TRY(run_update(col, true, yfl, ysig, s));
+    const bool singular = s[kNStat] >= 0;
+    if (singular || s[5] > 0 || s[4] > 0) {
+      ++rejects;
+      ++consec;
+      dt *= 0.5;
+      if (consec > maxrej) break;
+      continue;
+    }
+    consec = 0;
+    clipped += s[3];
+    std::swap(col->n, col->ntmp);
+    t += dt;
+    ++steps;
+    const double rel = s[0], ctl = s[2];
+    if ((rel < tol && dt >= mix) || t >= tend) {
+      converged = 1;
+      break;
+    }
+    dt *= ctl < 0.5 ? 2.0 : (ctl < 0.9 ? 1.2 : 0.7);
+  }
+  col->t = t;
+  col->dt = dt;
+  res->t = t;
+  res->dt = dt;
+  res->clipped = clipped;
+  res->steps = steps;
+  res->rejects = rejects;
+  res->converged = converged;
+  if (!converged) {
+    set_error("steady state not reached (step or rejection limit)");
+    return XOD_ENOTCONVERGED;
+  }
+  return XOD_OK;
+}

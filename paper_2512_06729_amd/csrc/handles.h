@@ -1,0 +1,104 @@
+// Handle layouts shared by the ABI translation units (api.cpp, batch.cpp).
+#pragma once
+
+#include <vector>
+
+#include "xod_internal.h"
+
+using xod::ColArgs;
+using xod::RedArgs;
+using xod::UpdArgs;
+
+struct xod_network {
+  int S = 0, R = 0, E = 0, ld = 0;
+  double t_mid = 1000.0;
+  std::vector<void *> owned;
+  int *rtype = nullptr, *reac = nullptr, *prod = nullptr, *rev = nullptr, *kooij = nullptr,
+      *dnu = nullptr;
+  double *params = nullptr, *nasa7 = nullptr, *mass = nullptr;
+  int *inc_ptr = nullptr, *inc_r = nullptr;
+  double *inc_nu = nullptr;
+  int *jmap = nullptr, *jptr = nullptr, *jc_r = nullptr;
+  double *jc_nu = nullptr;
+  std::vector<double> mass_h;
+  int nnz = 0, ncontrib = 0;
+  ~xod_network() {
+    for (void *p : owned) (void)hipFree(p);
+  }
+};
+
+struct xod_column {
+  const xod_network *net = nullptr;
+  int N = 0, S = 0, R = 0, ld = 0;
+  xod_precision prec = XOD_FP64;
+  hipStream_t stream = nullptr;
+  std::vector<void *> owned;
+  double *P = nullptr, *T = nullptr, *K = nullptr, *D = nullptr, *alpha = nullptr;
+  double *ngas = nullptr, *tau = nullptr, *lnpref = nullptr, *g = nullptr, *trl = nullptr,
+         *trd = nullptr, *tru = nullptr, *dz = nullptr, *dzh = nullptr, *mix = nullptr;
+  double mix_time = 0.0;
+  double *n = nullptr, *ntmp = nullptr, *kf = nullptr, *kr = nullptr, *w = nullptr,
+         *f = nullptr, *x = nullptr, *gs = nullptr, *resid = nullptr, *dx = nullptr;
+  double *B = nullptr;
+  float *Bf = nullptr;
+  double *a = nullptr, *c = nullptr, *rs = nullptr, *a64 = nullptr, *c64 = nullptr;
+  int *piv = nullptr, *rstep = nullptr, *flag = nullptr;
+  double *partial = nullptr, *stats_dev = nullptr, *stats_host = nullptr;
+  UpdArgs *upd_dev = nullptr;
+  RedArgs *red_dev = nullptr;
+  double t = 0.0, dt = 0.0;
+  bool in_batch = false;
+  ~xod_column() {
+    if (stats_host) (void)hipHostFree(stats_host);
+    for (void *p : owned) (void)hipFree(p);
+  }
+  ColArgs args() const {
+    ColArgs a_{};
+    a_.N = N;
+    a_.S = S;
+    a_.R = R;
+    a_.ld = ld;
+    a_.dt = dt;
+    a_.rtype = net->rtype;
+    a_.reac = net->reac;
+    a_.prod = net->prod;
+    a_.rev = net->rev;
+    a_.kooij = net->kooij;
+    a_.dnu = net->dnu;
+    a_.params = net->params;
+    a_.inc_ptr = net->inc_ptr;
+    a_.inc_r = net->inc_r;
+    a_.inc_nu = net->inc_nu;
+    a_.jmap = net->jmap;
+    a_.jptr = net->jptr;
+    a_.jc_r = net->jc_r;
+    a_.jc_nu = net->jc_nu;
+    a_.T = T;
+    a_.ngas = ngas;
+    a_.tau = tau;
+    a_.lnpref = lnpref;
+    a_.g = g;
+    a_.trl = trl;
+    a_.trd = trd;
+    a_.tru = tru;
+    a_.kf_in = kf;
+    a_.kr_in = kr;
+    a_.n = n;
+    a_.kf = kf;
+    a_.kr = kr;
+    a_.w = w;
+    a_.f = f;
+    a_.B = B;
+    a_.Bf = Bf;
+    a_.a = a;
+    a_.c = c;
+    a_.rs = rs;
+    a_.piv = piv;
+    a_.rstep = rstep;
+    a_.x = x;
+    a_.gs = gs;
+    a_.flag = flag;
+    return a_;
+  }
+};
+

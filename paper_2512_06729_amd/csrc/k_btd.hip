@@ -1,0 +1,339 @@
+// Block Thomas elimination of the block-tridiagonal step system (FP64).
+//
+// For k = 0..N-1 the Schur complement
+//     D'_k = B_k - diag(a_k) D'_{k-1}^{-1} diag(c_{k-1})
+// is inverted in place by blocked Gauss-Jordan elimination with implicit
+// partial pivoting (rows are never moved; piv[j] records the row chosen for
+// column j, rstep[r] the column at which row r became a pivot).  With W the
+// in-place result, D'^{-1}[j][i] = W[piv[j]][rstep[i]].
+//
+// Per layer:
+//   k_prologue   D'_k from B_k and the previous layer's inverse (gather)
+//   per panel of kNB columns:
+//     k_panel    one work-group factors the ld x kNB panel in registers
+//                (argmax over unused rows, first maximum wins)
+//     k_update   Schur update of every other column strip:
+//                C <- mask * C + W[:, J] U,  U = W[piv[J], strip]
+//                (rows that became pivots in this panel are replaced, the
+//                others accumulate), FP64 MFMA 16x16x4 or VALU FMA.
+// The solve is a chain of matrix-vector products with the stored inverses.
+#include "xod_internal.h"
+
+#include <climits>
+
+namespace xod {
+
+// ---------------------------------------------------------------------------
+template <class Acc>
+__global__ void __launch_bounds__(256) k_rstep_init(Acc acc, int maxN) {
+  const ColArgs &c = acc(blockIdx.y);
+  const size_t total = (size_t)c.N * c.ld;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x)
+    c.rstep[e] = INT_MAX;
+  if (blockIdx.x == 0 && threadIdx.x < 4) c.flag[threadIdx.x] = -1;
+}
+
+// D'_k[i][j] = B_k[i][j] - a_k[i] W_{k-1}[piv_{k-1}[i]][rstep_{k-1}[j]] c_{k-1}[j]
+// One work-group per 8 rows of one column; the source rows are contiguous.
+template <class Acc>
+__global__ void __launch_bounds__(256) k_prologue(Acc acc, int k) {
+  const ColArgs &c = acc(blockIdx.y);
+  if (k >= c.N || k == 0) return;
+  const int ld = c.ld;
+  const int *pv = c.piv + (size_t)(k - 1) * ld;
+  const int *rq = c.rstep + (size_t)(k - 1) * ld;
+  const double *W = c.B + (size_t)(k - 1) * ld * ld;
+  double *D = c.B + (size_t)k * ld * ld;
+  const double *ak = c.a + (size_t)k * ld;
+  const double *cp = c.c + (size_t)(k - 1) * ld;
+  const int r0 = blockIdx.x * 8;
+  for (int rr = 0; rr < 8; ++rr) {
+    const int i = r0 + rr;
+    if (i >= ld) break;
+    const double ai = ak[i];
+    if (ai == 0.0) continue;
+    const double *src = W + (size_t)pv[i] * ld;
+    double *dst = D + (size_t)i * ld;
+    for (int j = threadIdx.x; j < ld; j += blockDim.x) {
+      const double cj = cp[j];
+      if (cj != 0.0) dst[j] -= ai * src[rq[j]] * cj;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Panel factorisation.  Thread t owns row t of the panel (kNB values).
+template <class Acc>
+__global__ void __launch_bounds__(kMaxLd) k_panel(Acc acc, int k, int p) {
+  const ColArgs &c = acc(blockIdx.x);
+  if (k >= c.N) return;
+  const int ld = c.ld;
+  const int t = threadIdx.x;
+  const int nw = blockDim.x >> 6;
+  const int lane = t & 63, wid = t >> 6;
+  double *W = c.B + (size_t)k * ld * ld;
+  int *rstep = c.rstep + (size_t)k * ld;
+  int *piv = c.piv + (size_t)k * ld;
+  const int j0 = p * kNB;
+  __shared__ double s_val[kMaxLd / 64];
+  __shared__ int s_idx[kMaxLd / 64];
+  __shared__ double s_prow[kNB];
+  __shared__ int s_bad;
+
+  double reg[kNB];
+  bool used = true;
+  int mystep = INT_MAX;
+  if (t < ld) {
+    const double *row = W + (size_t)t * ld + j0;
+#pragma unroll
+    for (int q = 0; q < kNB; ++q) reg[q] = row[q];
+    mystep = rstep[t];
+    used = mystep < j0;
+  } else {
+#pragma unroll
+    for (int q = 0; q < kNB; ++q) reg[q] = 0.0;
+  }
+  if (t == 0) s_bad = 0;
+
+#pragma unroll
+  for (int jj = 0; jj < kNB; ++jj) {
+    // argmax |W[i][j]| over unused rows; ties go to the lowest row index
+    double v = -1.0;
+    int idx = INT_MAX;
+    if (!used) {
+      const double av = fabs(reg[jj]);
+      v = (av == av) ? av : -2.0;   // NaN never wins; flagged below
+      idx = t;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(v, o, 64);
+      const int oi = __shfl_xor(idx, o, 64);
+      if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+    }
+    if (lane == 0) { s_val[wid] = v; s_idx[wid] = idx; }
+    __syncthreads();
+    v = s_val[0];
+    idx = s_idx[0];
+    for (int q = 1; q < nw; ++q) {
+      const double ov = s_val[q];
+      const int oi = s_idx[q];
+      if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+    }
+    const int r = idx;
+    if (t == r) {
+#pragma unroll
+      for (int q = 0; q < kNB; ++q) s_prow[q] = reg[q];
+    }
+    __syncthreads();
+    if (r == INT_MAX || r >= ld) {
+      // no candidate row (cannot happen for a valid panel)
+      if (t == 0) s_bad = 1;
+      continue;
+    }
+    double pv = s_prow[jj];
+    if (!(fabs(pv) > 0.0) || !isfinite(pv)) {
+      if (t == 0 && atomicCAS(c.flag, -1, k) == -1) c.flag[1] = j0 + jj;
+      pv = 1.0;
+    }
+    const double npiv = 1.0 / pv;
+    if (t < ld) {
+      if (t == r) {
+#pragma unroll
+        for (int q = 0; q < kNB; ++q) reg[q] = s_prow[q] * npiv;
+        reg[jj] = npiv;
+        used = true;
+        mystep = j0 + jj;
+      } else {
+        const double fm = reg[jj] * npiv;
+#pragma unroll
+        for (int q = 0; q < kNB; ++q) reg[q] -= fm * s_prow[q];
+        reg[jj] = -fm;
+      }
+    }
+    if (t == 0) piv[j0 + jj] = r;
+  }
+  if (t < ld) {
+    double *row = W + (size_t)t * ld + j0;
+#pragma unroll
+    for (int q = 0; q < kNB; ++q) row[q] = reg[q];
+    rstep[t] = mystep;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Schur update of the column strips outside the panel.  One work-group per
+// (strip, column); each owns all ld rows of its strip, so reading the pivot
+// rows (U) before overwriting them is race-free.
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+template <class Acc, bool kMfma>
+__global__ void __launch_bounds__(256) k_update(Acc acc, int k, int p) {
+  const ColArgs &c = acc(blockIdx.y);
+  if (k >= c.N) return;
+  const int ld = c.ld;
+  const int j0 = p * kNB;
+  const int nstrip = ld / kStrip;
+  int s = blockIdx.x;
+  const int ps = j0 / kStrip;                 // first strip of the panel
+  if (s >= ps) s += kNB / kStrip;             // skip the panel's strips
+  if (s >= nstrip) return;
+  const int c0 = s * kStrip;
+  double *W = c.B + (size_t)k * ld * ld;
+  const int *piv = c.piv + (size_t)k * ld + j0;
+  const int *rstep = c.rstep + (size_t)k * ld;
+
+  __shared__ double sU[kNB][kStrip];          // U = W[piv[J], strip]
+  const int t = threadIdx.x;
+  for (int e = t; e < kNB * kStrip; e += blockDim.x) {
+    const int q = e / kStrip, col = e % kStrip;
+    sU[q][col] = W[(size_t)piv[q] * ld + c0 + col];
+  }
+  __syncthreads();
+
+  const int lane = t & 63, wid = t >> 6;
+  const int ntile = ld / 16;
+  if (kMfma) {
+    // v_mfma_f64_16x16x4f64: lane supplies A[l%16][l/16], B[l/16][l%16];
+    // lane holds D[l/16 + 4*i][l%16], i = 0..3 (checked on gfx950).
+    for (int tile = wid; tile < ntile; tile += 4) {
+      const int rbase = tile * 16;
+      double4_t accv;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = rbase + (lane >> 4) + 4 * i;
+        const int st = rstep[row];
+        const bool piv_here = st >= j0 && st < j0 + kNB;
+        accv[i] = piv_here ? 0.0 : W[(size_t)row * ld + c0 + (lane & 15)];
+      }
+      const double *Arow = W + (size_t)(rbase + (lane & 15)) * ld + j0;
+#pragma unroll
+      for (int kk = 0; kk < kNB / 4; ++kk) {
+        const double av = Arow[4 * kk + (lane >> 4)];
+        const double bv = sU[4 * kk + (lane >> 4)][lane & 15];
+        accv = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, accv, 0, 0, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = rbase + (lane >> 4) + 4 * i;
+        W[(size_t)row * ld + c0 + (lane & 15)] = accv[i];
+      }
+    }
+  } else {
+    // VALU: thread handles (row = 16-row tile + t/16, col = t%16).
+    const int col = t & 15;
+    for (int row = t >> 4; row < ld; row += 16) {
+      const int st = rstep[row];
+      const bool piv_here = st >= j0 && st < j0 + kNB;
+      double acc = piv_here ? 0.0 : W[(size_t)row * ld + c0 + col];
+      const double *Arow = W + (size_t)row * ld + j0;
+#pragma unroll 8
+      for (int q = 0; q < kNB; ++q) acc = fma(Arow[q], sU[q][col], acc);
+      W[(size_t)row * ld + c0 + col] = acc;
+    }
+  }
+}
+
+template <class Acc>
+hipError_t launch_factor_fp64(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s) {
+  if (maxN <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rstep_init<Acc>, dim3(64, ncols), dim3(256), 0, s, acc, maxN);
+  const int npanel = ld / kNB;
+  const int nupd = ld / kStrip - kNB / kStrip;
+  const int pthreads = round_up(ld, 64);
+  for (int k = 0; k < maxN; ++k) {
+    if (k > 0)
+      hipLaunchKernelGGL(k_prologue<Acc>, dim3((ld + 7) / 8, ncols), dim3(256), 0, s, acc, k);
+    for (int p = 0; p < npanel; ++p) {
+      hipLaunchKernelGGL(k_panel<Acc>, dim3(ncols), dim3(pthreads), 0, s, acc, k, p);
+      if (nupd > 0) {
+        if (options().gemm_mfma)
+          hipLaunchKernelGGL((k_update<Acc, true>), dim3(nupd, ncols), dim3(256), 0, s, acc, k, p);
+        else
+          hipLaunchKernelGGL((k_update<Acc, false>), dim3(nupd, ncols), dim3(256), 0, s, acc, k, p);
+      }
+    }
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Solve.  y = D'^{-1} v:  y[j] = sum_m W[piv[j]][m] v[piv[m]], written as
+// z = W v' with v'[m] = v[piv[m]], then y[rstep[r]] = z[r] (rstep = piv^-1).
+//
+// Forward (k >= 1): g_k = rhs_k - a_k * (D'^{-1}_{k-1} g_{k-1}) into gs.
+// Backward:         x_k = D'^{-1}_k (g_k - c_k * x_{k+1}) into x.
+// One work-group per 16 rows of W; each wave reduces 4 rows.
+template <class Acc, bool kForward>
+__global__ void __launch_bounds__(256) k_solve_step(Acc acc, int k) {
+  const ColArgs &c = acc(blockIdx.y);
+  const int N = c.N, S = c.S, ld = c.ld;
+  if (k >= N) return;
+  const int kin = kForward ? k - 1 : k;        // layer whose inverse is applied
+  if (kForward && k == 0) {
+    // g_0 = rhs_0, kept in gs so the backward pass never reads x[0] while
+    // other work-groups overwrite it.
+    if (blockIdx.x == 0)
+      for (int y = threadIdx.x; y < S; y += blockDim.x) c.gs[y] = c.x[y];
+    return;
+  }
+  const double *W = c.B + (size_t)kin * ld * ld;
+  const int *pv = c.piv + (size_t)kin * ld;
+  const int *rq = c.rstep + (size_t)kin * ld;
+  __shared__ double sv[kMaxLd];
+  const int t = threadIdx.x;
+  // v'[m] = v[piv[m]]
+  for (int m = t; m < ld; m += blockDim.x) {
+    const int src = pv[m];
+    double v = 0.0;
+    if (src < S) {
+      if (kForward) {
+        v = c.gs[(size_t)kin * ld + src];
+      } else {
+        const double g = c.gs[(size_t)k * ld + src];
+        const double nx = (k + 1 < N) ? c.x[(size_t)(k + 1) * S + src] : 0.0;
+        v = g - c.c[(size_t)k * ld + src] * nx;
+      }
+    }
+    sv[m] = v;
+  }
+  __syncthreads();
+  const int lane = t & 63, wid = t >> 6;
+  for (int rr = 0; rr < 4; ++rr) {
+    const int r = blockIdx.x * 16 + wid * 4 + rr;
+    if (r >= ld) break;
+    const double *row = W + (size_t)r * ld;
+    double z = 0.0;
+    for (int m = lane; m < ld; m += 64) z = fma(row[m], sv[m], z);
+    for (int o = 32; o > 0; o >>= 1) z += __shfl_xor(z, o, 64);
+    if (lane == 0) {
+      const int j = rq[r];
+      if (j < S) {
+        if (kForward) {
+          const size_t o = (size_t)k * S + j;
+          c.gs[(size_t)k * ld + j] = c.x[o] - c.a[(size_t)k * ld + j] * z;
+        } else {
+          c.x[(size_t)k * S + j] = z;
+        }
+      }
+    }
+  }
+}
+
+template <class Acc>
+hipError_t launch_solve_fp64(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s) {
+  if (maxN <= 0) return hipSuccess;
+  dim3 grid((ld + 15) / 16, ncols);
+  for (int k = 0; k < maxN; ++k)
+    hipLaunchKernelGGL((k_solve_step<Acc, true>), grid, dim3(256), 0, s, acc, k);
+  for (int k = maxN - 1; k >= 0; --k)
+    hipLaunchKernelGGL((k_solve_step<Acc, false>), grid, dim3(256), 0, s, acc, k);
+  return hipGetLastError();
+}
+
+template hipError_t launch_factor_fp64<OneCol>(const OneCol &, int, int, int, hipStream_t);
+template hipError_t launch_factor_fp64<ManyCols>(const ManyCols &, int, int, int, hipStream_t);
+template hipError_t launch_solve_fp64<OneCol>(const OneCol &, int, int, int, hipStream_t);
+template hipError_t launch_solve_fp64<ManyCols>(const ManyCols &, int, int, int, hipStream_t);
+
+}  // namespace xod

@@ -1,0 +1,62 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads, exports
+every function include/xod.h declares, and rejects invalid descriptions
+before touching the device."""
+
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2512_06729_amd", "libxod.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libxod.so not built")
+
+
+def test_library_exports_every_header_symbol():
+    import paper_2512_06729_amd as xod
+    syms = xod.header_symbols()
+    assert len(syms) >= 20
+    lib = ctypes.CDLL(LIB)
+    missing = [s for s in syms if not hasattr(lib, s)]
+    assert missing == []
+
+
+def _desc(xod, S=3, reac=None):
+    keep = dict(comp=np.ones((1, S), np.int32), mass=np.full(S, 10.0),
+                nasa=np.zeros((S, 2, 7)), rtype=np.zeros(1, np.int32),
+                reac=np.array(reac if reac is not None else [[0, 1, -1]], np.int32),
+                prod=np.array([[2, -1, -1]], np.int32), rev=np.ones(1, np.int32),
+                kooij=np.zeros(1, np.int32), params=np.zeros((1, 6)))
+    p = xod._ptr
+    d = xod.NetworkDesc(S, 1, 1, p(keep["comp"], ctypes.c_int32), p(keep["mass"], ctypes.c_double),
+                        p(keep["nasa"], ctypes.c_double), 1000.0, p(keep["rtype"], ctypes.c_int32),
+                        p(keep["reac"], ctypes.c_int32), p(keep["prod"], ctypes.c_int32),
+                        p(keep["rev"], ctypes.c_int32), p(keep["kooij"], ctypes.c_int32),
+                        p(keep["params"], ctypes.c_double))
+    return d, keep
+
+
+@pytest.mark.parametrize("reac,msg", [([[0, 7, -1]], "out of range"),
+                                      ([[-1, -1, -1]], "without reactant")])
+def test_network_create_rejects_bad_descriptions(reac, msg):
+    import paper_2512_06729_amd as xod
+    d, keep = _desc(xod, reac=reac)
+    h = ctypes.c_void_p()
+    st = xod._f["xod_network_create"](ctypes.byref(d), ctypes.byref(h))
+    assert st == xod.XOD_EINVAL
+    assert msg in xod.last_error()
+    assert not h.value
+
+
+def test_null_arguments_are_einval():
+    import paper_2512_06729_amd as xod
+    assert xod._f["xod_network_create"](None, None) == xod.XOD_EINVAL
+    assert xod._f["xod_step"](None, 1.0, None) == xod.XOD_EINVAL
+    assert xod._f["xod_column_destroy"](None) == xod.XOD_EINVAL
+    assert xod._f["xod_set_option"](b"nope", 1) == xod.XOD_EINVAL
+    assert xod._f["xod_set_option"](b"gemm", 3) == xod.XOD_EINVAL
+    buf = ctypes.create_string_buffer(8)
+    assert xod._f["xod_last_error"](buf, 8) == xod.XOD_OK
+    assert len(buf.value) <= 7

@@ -1,0 +1,250 @@
+"""GPU parity: every step of the HIP path against the FP64 CPU oracle, through
+the C ABI, on the same seeded inputs.
+
+Tolerances (floating point, FP64 on both sides):
+* element-wise kernels (grid, rates, right-hand side, Jacobian): 1e-12
+  relative to the magnitude of the terms that are summed (rounding order and
+  exp/log implementations differ; no cancellation is amplified);
+* linear solves: both sides are backward stable, so forward differences are
+  bounded by cond(M) * eps; the tests assert 50 cond(M) eps where cond is
+  computable, and a residual of <= 100 eps (|M| |x| + |rhs|) everywhere;
+* whole trajectories and steady states: 1e-10 relative on every mixing
+  ratio above 1e-30 (the tolerance the method is held to), which holds
+  because the backward-Euler map damps the per-step rounding differences.
+"""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import synth  # noqa: E402
+from oracle import integrate, jacobian, linalg, rhs as rhs_mod, equilibrium  # noqa: E402
+from tests import gpu_common as G  # noqa: E402
+from tests.helpers import balanced_c1_network  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    import paper_2512_06729_amd  # noqa: F401  (fails loudly if not built)
+    yield
+    import paper_2512_06729_amd as xod
+    xod.set_option("gemm", 1)
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_grid_and_rates_match_oracle(cfg):
+    net, col, prob, gnet, gcol = G.config_pair(cfg)
+    g = gcol.grid()
+    np.testing.assert_allclose(g["ngas"], prob.grid.ngas, rtol=1e-14)
+    np.testing.assert_allclose(g["dz"], prob.grid.dz, rtol=1e-12)
+    np.testing.assert_allclose(g["tau"], prob.grid.tau, rtol=1e-12)
+    assert g["mix_time"] == pytest.approx(prob.grid.mix_time, rel=1e-12)
+    kf, kr = G.gpu_rates(gcol)
+    kf = G.to_np(kf, prob.kf.shape)
+    kr = G.to_np(kr, prob.kr.shape)
+    np.testing.assert_allclose(kf, prob.kf, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(kr, prob.kr, rtol=1e-12, atol=0)
+
+
+def _rhs_scale(prob, n):
+    w = rhs_mod.reaction_rates(prob.net, prob.kf, prob.kr, n)
+    nu_abs = np.zeros((prob.net.rtype.shape[0], n.shape[1]))
+    for j in range(3):
+        for arr in (prob.net.reac, prob.net.prod):
+            idx = arr[:, j]
+            on = idx >= 0
+            nu_abs[np.nonzero(on)[0], idx[on]] += 1.0
+    fwd = prob.kf * np.prod([np.where(prob.net.reac[:, j] >= 0, n[:, prob.net.reac[:, j]], 1.0)
+                             for j in range(3)], axis=0)
+    chem = (np.abs(fwd) + np.abs(fwd - w)) @ nu_abs
+    lo, di, up = jacobian.transport_coefficients(prob.grid)
+    tr = np.abs(di * n)
+    tr[1:] += np.abs(lo[1:] * n[:-1])
+    tr[:-1] += np.abs(up[:-1] * n[1:])
+    return chem + tr
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_rhs_matches_oracle(cfg):
+    net, col, prob, gnet, gcol = G.config_pair(cfg)
+    import paper_2512_06729_amd as xod
+    kf, kr = G.gpu_rates(gcol)
+    rng = np.random.default_rng(5)
+    for n_np in (col.n0, col.n0 * 10.0 ** rng.uniform(-1, 1, col.n0.shape)):
+        n = torch.from_numpy(np.ascontiguousarray(n_np)).to(G.dev()).reshape(-1)
+        f = torch.empty_like(n)
+        xod.xod_rhs(gcol, kf, kr, n, f)
+        f = G.to_np(f, n_np.shape)
+        ref = prob.rhs(n_np)
+        scale = _rhs_scale(prob, n_np)
+        assert np.all(np.abs(f - ref) <= 1e-12 * scale + 1e-300)
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+@pytest.mark.parametrize("dt", [1e-8, 1e4])
+def test_jacobian_blocks_match_oracle(cfg, dt):
+    net, col, prob, gnet, gcol = G.config_pair(cfg)
+    kf, kr = G.gpu_rates(gcol)
+    n, B, a, c = G.gpu_blocks(gcol, kf, kr, col.n0, dt)
+    N, S, ld = gcol.N, gcol.S, gcol.ld
+    B = G.to_np(B, (N, ld, ld))
+    a = G.to_np(a, (N, ld))
+    c = G.to_np(c, (N, ld))
+    layers = sorted(set([0, 1, N // 2, N - 2, N - 1]))
+    J = jacobian.chem_jacobian(net, prob.kf[layers], prob.kr[layers], col.n0[layers])
+    lo, di, up = jacobian.transport_coefficients(prob.grid)
+    for li, k in enumerate(layers):
+        ref = -J[li] + np.eye(S) / dt - np.diag(di[k])
+        rowmax = np.abs(ref).max(axis=1, keepdims=True)
+        assert np.all(np.abs(B[k, :S, :S] - ref) <= 1e-12 * rowmax)
+        # identity padding
+        assert np.all(B[k, S:, S:] == np.eye(ld - S))
+        assert np.all(B[k, :S, S:] == 0) and np.all(B[k, S:, :S] == 0)
+        np.testing.assert_allclose(a[k, :S], -lo[k], rtol=1e-12, atol=0)
+        np.testing.assert_allclose(c[k, :S], -up[k], rtol=1e-12, atol=0)
+        assert np.all(a[k, S:] == 0) and np.all(c[k, S:] == 0)
+
+
+@pytest.mark.parametrize("dt", [1e-6, 1e2, 1e6])
+def test_block_solve_matches_oracle_config1(dt):
+    net, col, prob, gnet, gcol = G.config_pair(1)
+    kf, kr = G.gpu_rates(gcol)
+    f = prob.rhs(col.n0)
+    x = G.gpu_solve(gcol, kf, kr, col.n0, dt, f)
+    B, a, c = prob.step_matrix(col.n0, dt)
+    M = linalg.assemble(B, a, c)
+    ref = np.linalg.solve(M, f.ravel()).reshape(f.shape)
+    kappa = np.linalg.cond(M)
+    assert np.abs(x - ref).max() <= 50 * kappa * G.EPS * np.abs(ref).max()
+    # The solve applies explicit inverses of the Schur complements: forward
+    # stable, with a residual bounded by cond(M) eps |M| |x|.
+    r = M @ x.ravel() - f.ravel()
+    assert np.abs(r).max() <= 50 * kappa * G.EPS * (np.abs(M) @ np.abs(x.ravel()) + np.abs(f.ravel())).max()
+    if dt <= 1e-6:
+        G.assert_solve_agrees(x, ref)
+
+
+@pytest.mark.parametrize("cfg,dt", [(2, 1e-8), (2, 1e-6), (3, 1e-8)])
+def test_block_solve_matches_oracle_large(cfg, dt):
+    net, col, prob, gnet, gcol = G.config_pair(cfg)
+    kf, kr = G.gpu_rates(gcol)
+    f = prob.rhs(col.n0)
+    x = G.gpu_solve(gcol, kf, kr, col.n0, dt, f)
+    B, a, c = prob.step_matrix(col.n0, dt)
+    ref = linalg.btd(B, a, c, f)
+    G.assert_solve_agrees(x, ref, rel=1e-9)
+
+
+def test_gemm_paths_agree():
+    import paper_2512_06729_amd as xod
+    net, col, prob, gnet, gcol = G.config_pair(2)
+    kf, kr = G.gpu_rates(gcol)
+    f = prob.rhs(col.n0)
+    xod.set_option("gemm", 0)
+    x0 = G.gpu_solve(gcol, kf, kr, col.n0, 1e-3, f)
+    xod.set_option("gemm", 1)
+    x1 = G.gpu_solve(gcol, kf, kr, col.n0, 1e-3, f)
+    np.testing.assert_allclose(x1, x0, rtol=1e-10, atol=1e-12 * np.abs(x0).max())
+
+
+def test_fixed_schedule_config1_matches_oracle():
+    import paper_2512_06729_amd as xod
+    net, col, prob, gnet, gcol = G.config_pair(1)
+    sched = integrate.fixed_schedule(200)
+    ref = integrate.run_fixed(prob, col.n0, sched)
+    for dt in sched:
+        st = xod.xod_step(gcol, dt)
+        assert st["nonfinite"] == 0
+    n = gcol.state()
+    ng = prob.grid.ngas[:, None]
+    keep = np.abs(ref) > 1e-30 * ng
+    np.testing.assert_allclose(n[keep], ref[keep], rtol=1e-10)
+    assert np.all(np.abs(n - ref)[~keep] <= 1e-10 * 1e-30 * np.broadcast_to(ng, n.shape)[~keep] + 1e-300)
+
+
+def test_single_step_config3_matches_oracle():
+    import paper_2512_06729_amd as xod
+    net, col, prob, gnet, gcol = G.config_pair(3)
+    dt = 1e-8
+    ref, _ = integrate.be_step(prob, col.n0, dt)
+    xod.xod_step(gcol, dt)
+    n = gcol.state()
+    G.assert_state_agrees(n, ref, ref - col.n0, rel=1e-9)
+
+
+def test_closed_layer_steady_state_gpu():
+    import paper_2512_06729_amd as xod
+    net = balanced_c1_network()
+    col = synth.make_column("c1", net, seed=77, N=3)
+    col.T_K = np.array([1900.0, 1500.0, 1100.0])
+    col.Kzz = np.zeros(3)
+    prob, gnet, gcol = G.make_pair(net, col)
+    res = xod.xod_integrate_to_steady_state(gcol, tol_rel=1e-13, t_end=1e30, max_steps=4000)
+    assert res["converged"] == 1
+    n = gcol.state()
+    ref = integrate.steady_state(prob, col.n0, tol_rel=1e-13, t_end=1e30, max_steps=4000)
+    A = net.elem_comp.astype(float)
+    for k in range(3):
+        b = A @ n[k]
+        on = b > 0
+        lam0 = equilibrium.initial_potentials(net.nasa7, net.t_mid, A[on], col.T_K[k], n[k])
+        neq, _ = equilibrium.equilibrium_layer(net.nasa7, net.t_mid, A[on], col.T_K[k], b[on], lam0)
+        keep = neq > 1e-30 * prob.grid.ngas[k]
+        np.testing.assert_allclose(n[k, keep], neq[keep], rtol=1e-8)
+    keep = ref.n > 1e-30 * prob.grid.ngas[:, None]
+    np.testing.assert_allclose(n[keep], ref.n[keep], rtol=1e-8)
+
+
+def test_singular_block_is_reported():
+    import paper_2512_06729_amd as xod
+    net, col, prob, gnet, gcol = G.config_pair(1)
+    N, ld = gcol.N, gcol.ld
+    B = torch.zeros(N * ld * ld, dtype=torch.float64, device=G.dev())
+    a = torch.zeros(N * ld, dtype=torch.float64, device=G.dev())
+    c = torch.zeros_like(a)
+    piv = torch.empty(N * ld, dtype=torch.int32, device=G.dev())
+    with pytest.raises(xod.XodError) as e:
+        xod.xod_btd_factor(gcol, B, a, c, piv)
+    assert e.value.status == xod.XOD_ESINGULAR
+    assert "layer 0" in str(e.value)
+
+
+def test_single_layer_column():
+    import paper_2512_06729_amd as xod
+    net = synth.make_network("c1", seed=1001)
+    col = synth.make_column("c1", net, seed=5, N=1)
+    prob, gnet, gcol = G.make_pair(net, col)
+    for dt in (1e-6, 1e-3):
+        n0 = gcol.state()
+        ref, delta = integrate.be_step(prob, n0, dt)
+        xod.xod_step(gcol, dt)
+        G.assert_state_agrees(gcol.state(), ref, delta)
+
+
+def test_batch_equals_single_columns():
+    import paper_2512_06729_amd as xod
+    stream = torch.cuda.current_stream().cuda_stream
+    nets = [synth.make_network("c1", seed=1001), synth.make_network("c2", seed=1002)]
+    cols_in = [(nets[0], synth.make_column("c1", nets[0], seed=11, N=20)),
+               (nets[1], synth.make_column("c2", nets[1], seed=12, N=30)),
+               (nets[0], synth.make_column("c1", nets[0], seed=13, N=7)),
+               (nets[1], synth.make_column("c2", nets[1], seed=14, N=41))]
+    gnets = [xod.Network(n) for n in nets]
+    alone, inb = [], []
+    for (net, col) in cols_in:
+        gn = gnets[nets.index(net)]
+        alone.append(xod.Column(gn, col, stream=stream))
+        inb.append(xod.Column(gn, col, stream=stream))
+    batch = xod.Batch(inb)
+    dts = np.array([1e-7, 1e-6, 3e-5, 1e-4])
+    for step in range(3):
+        for c, dt in zip(alone, dts):
+            xod.xod_step(c, dt)
+        batch.step(dts)
+    for c1, c2 in zip(alone, inb):
+        np.testing.assert_array_equal(c1.state(), c2.state())
