@@ -240,8 +240,17 @@ xod_status xod_integrate_to_steady_state(xod_column *col,
 xod_status xod_last_error(char *buf, size_t len);
 
 /* Kernel options (process-wide; for tests and tuning).
- *   "gemm": 0 = VALU FMA Schur update, 1 = MFMA Schur update (default). */
+ *   "gemm": 0 = VALU FMA Schur update, 1 = MFMA Schur update (default).
+ *   "profile": 1 = record HIP events on the launching stream around each
+ *              profiled kernel launch (default 0).
+ *   "profile_every": profile layer k only when k % value == 0 (default 1). */
 xod_status xod_set_option(const char *name, int64_t value);
+
+/* Sum of the recorded launch durations (ms) and the launch count of one
+ * kernel kind: "panel", "update", "prologue", "solve", "jacobian", "rates",
+ * "rhs".  Waits for the recorded events.  xod_profile_reset() drops them. */
+xod_status xod_profile_read(const char *kernel, double *total_ms, int64_t *launches);
+xod_status xod_profile_reset(void);
 
 /* ---- batches ---------------------------------------------------------- */
 

@@ -122,7 +122,21 @@ _f = {
                              ctypes.POINTER(c_void_p)),
     "xod_batch_destroy": _sig("xod_batch_destroy", c_void_p),
     "xod_batch_step": _sig("xod_batch_step", c_void_p, P_dbl, ctypes.POINTER(StepStats)),
+    "xod_profile_read": _sig("xod_profile_read", ctypes.c_char_p, P_dbl,
+                             ctypes.POINTER(ctypes.c_int64)),
+    "xod_profile_reset": _sig("xod_profile_reset"),
 }
+
+
+def profile_read(kernel):
+    """(total milliseconds, launch count) of one profiled kernel kind."""
+    ms, n = c_double(), ctypes.c_int64()
+    _check(_f["xod_profile_read"](kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def profile_reset():
+    _check(_f["xod_profile_reset"]())
 
 
 def header_symbols(path=HEADER):

@@ -106,6 +106,16 @@ extern "C" xod_status xod_set_option(const char *name, int64_t value) {
     options().gemm_mfma = (int)value;
     return XOD_OK;
   }
+  if (std::strcmp(name, "profile") == 0) {
+    XOD_CHECK(value == 0 || value == 1, "xod_set_option: profile must be 0 or 1");
+    options().profile = (int)value;
+    return XOD_OK;
+  }
+  if (std::strcmp(name, "profile_every") == 0) {
+    XOD_CHECK(value >= 1 && value <= 1000000, "xod_set_option: profile_every must be >= 1");
+    options().profile_every = (int)value;
+    return XOD_OK;
+  }
   set_error(std::string("xod_set_option: unknown option ") + name);
   return XOD_EINVAL;
 }
@@ -323,6 +333,8 @@ extern "C" xod_status xod_column_create(const xod_network *net, const xod_profil
     XOD_TRY(calloc_(c, &c->a64, NL));
     XOD_TRY(calloc_(c, &c->c64, NL));
   }
+  XOD_TRY(calloc_(c, &c->ratio, (size_t)N));
+  XOD_TRY(calloc_(c, &c->rmax, 1));
   XOD_TRY(calloc_(c, &c->partial, (size_t)kUpdBlocks * kNStat));
   XOD_TRY(calloc_(c, &c->stats_dev, kStatLen));
   XOD_TRY(calloc_(c, &c->upd_dev, 1));
@@ -541,8 +553,47 @@ xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, do
     XOD_HIP(launch_solve_fp64(one, 1, c->N, c->ld, c->stream));
     return XOD_OK;
   }
-  set_error("mixed precision step not available in this build");
-  return XOD_ENOTIMPL;
+  // Mixed precision: row-scaled FP32 Schur complements, FP64 refinement with a
+  // matrix-free FP64 residual; FP64 refactorisation if refinement stalls.
+  const size_t NSb = (size_t)c->N * c->S * sizeof(double);
+  XOD_HIP(launch_jacobian(one, 1, c->N, c->ld, true, c->stream));
+  XOD_HIP(launch_factor_mixed(one, 1, c->N, c->ld, c->stream));
+  XOD_HIP(launch_scale(one, 1, c->N, c->S, c->stream));
+  XOD_HIP(launch_solve_mixed(one, 1, c->N, c->ld, c->stream));
+  XOD_HIP(hipMemcpyAsync(c->dx, c->x, NSb, hipMemcpyDeviceToDevice, c->stream));
+  bool ok = false;
+  double prev = 1e300, ratio = 1e300;
+  for (int it = 1; it <= c->max_refine; ++it) {
+    XOD_HIP(launch_residual(one, 1, c->N, c->S, c->R, c->dx, c->w, c->stream));
+    XOD_HIP(launch_solve_mixed(one, 1, c->N, c->ld, c->stream));
+    XOD_HIP(launch_axpy_ratio(one, 1, c->N, c->dx, c->ratio, c->rmax, c->stream));
+    XOD_HIP(hipMemcpyAsync(c->stats_host, c->rmax, sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+    XOD_HIP(hipStreamSynchronize(c->stream));
+    ratio = c->stats_host[0];
+    *iters = it;
+    if (ratio <= 1e-13) {
+      ok = true;
+      break;
+    }
+    if (ratio > 0.5 * prev) {          // stagnation: converged to the FP64 floor?
+      ok = ratio <= 1e-9;
+      break;
+    }
+    prev = ratio;
+  }
+  if (!ok && ratio <= 1e-9) ok = true;
+  *resid = ratio;
+  if (ok) {
+    XOD_HIP(hipMemcpyAsync(c->x, c->dx, NSb, hipMemcpyDeviceToDevice, c->stream));
+    return XOD_OK;
+  }
+  *fallback = 1;
+  XOD_HIP(launch_jacobian(one, 1, c->N, c->ld, false, c->stream));
+  XOD_HIP(launch_factor_fp64(one, 1, c->N, c->ld, c->stream));
+  XOD_HIP(hipMemcpyAsync(c->x, c->f, NSb, hipMemcpyDeviceToDevice, c->stream));
+  XOD_HIP(launch_solve_fp64(one, 1, c->N, c->ld, c->stream));
+  return XOD_OK;
 }
 
 }  // namespace

@@ -44,6 +44,8 @@ struct xod_column {
   double *a = nullptr, *c = nullptr, *rs = nullptr, *a64 = nullptr, *c64 = nullptr;
   int *piv = nullptr, *rstep = nullptr, *flag = nullptr;
   double *partial = nullptr, *stats_dev = nullptr, *stats_host = nullptr;
+  double *ratio = nullptr, *rmax = nullptr;   // refinement convergence measure
+  int max_refine = 10;
   UpdArgs *upd_dev = nullptr;
   RedArgs *red_dev = nullptr;
   double t = 0.0, dt = 0.0;

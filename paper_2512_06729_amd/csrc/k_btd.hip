@@ -23,6 +23,11 @@
 
 namespace xod {
 
+// Block storage: FP64 blocks (c.B) or FP32 row-scaled blocks (c.Bf).
+template <class T> __device__ __forceinline__ T *blocks(const ColArgs &c);
+template <> __device__ __forceinline__ double *blocks<double>(const ColArgs &c) { return c.B; }
+template <> __device__ __forceinline__ float *blocks<float>(const ColArgs &c) { return c.Bf; }
+
 // ---------------------------------------------------------------------------
 template <class Acc>
 __global__ void __launch_bounds__(256) k_rstep_init(Acc acc, int maxN) {
@@ -36,15 +41,15 @@ __global__ void __launch_bounds__(256) k_rstep_init(Acc acc, int maxN) {
 
 // D'_k[i][j] = B_k[i][j] - a_k[i] W_{k-1}[piv_{k-1}[i]][rstep_{k-1}[j]] c_{k-1}[j]
 // One work-group per 8 rows of one column; the source rows are contiguous.
-template <class Acc>
+template <class Acc, class T>
 __global__ void __launch_bounds__(256) k_prologue(Acc acc, int k) {
   const ColArgs &c = acc(blockIdx.y);
   if (k >= c.N || k == 0) return;
   const int ld = c.ld;
   const int *pv = c.piv + (size_t)(k - 1) * ld;
   const int *rq = c.rstep + (size_t)(k - 1) * ld;
-  const double *W = c.B + (size_t)(k - 1) * ld * ld;
-  double *D = c.B + (size_t)k * ld * ld;
+  const T *W = blocks<T>(c) + (size_t)(k - 1) * ld * ld;
+  T *D = blocks<T>(c) + (size_t)k * ld * ld;
   const double *ak = c.a + (size_t)k * ld;
   const double *cp = c.c + (size_t)(k - 1) * ld;
   const int r0 = blockIdx.x * 8;
@@ -53,110 +58,127 @@ __global__ void __launch_bounds__(256) k_prologue(Acc acc, int k) {
     if (i >= ld) break;
     const double ai = ak[i];
     if (ai == 0.0) continue;
-    const double *src = W + (size_t)pv[i] * ld;
-    double *dst = D + (size_t)i * ld;
+    const T *src = W + (size_t)pv[i] * ld;
+    T *dst = D + (size_t)i * ld;
     for (int j = threadIdx.x; j < ld; j += blockDim.x) {
       const double cj = cp[j];
-      if (cj != 0.0) dst[j] -= ai * src[rq[j]] * cj;
+      if (cj != 0.0) dst[j] = (T)((double)dst[j] - ai * (double)src[rq[j]] * cj);
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Panel factorisation.  Thread t owns row t of the panel (kNB values).
-template <class Acc>
-__global__ void __launch_bounds__(kMaxLd) k_panel(Acc acc, int k, int p) {
-  const ColArgs &c = acc(blockIdx.x);
-  if (k >= c.N) return;
-  const int ld = c.ld;
-  const int t = threadIdx.x;
-  const int nw = blockDim.x >> 6;
+// Panel factorisation.  Thread t owns row t of the panel (kNB values held in
+// registers; the column loop is unrolled at compile time so every register
+// index is static).  One barrier per column: each wave publishes its best
+// candidate (value, row) and that row's panel values, so after the barrier
+// every thread knows the pivot row without a second exchange.
+struct PanelShared {
+  double cand[2][kMaxLd / 64][kNB];   // double-buffered by column parity
+  double val[2][kMaxLd / 64];
+  int idx[2][kMaxLd / 64];
+};
+
+template <int JJ>
+__device__ __forceinline__ void gj_column(double (&reg)[kNB], bool &used, int &mystep,
+                                          PanelShared &sh, int t, int ld, int nw, int j0,
+                                          int k, int *piv, int *flag) {
+  constexpr int buf = JJ & 1;
   const int lane = t & 63, wid = t >> 6;
-  double *W = c.B + (size_t)k * ld * ld;
-  int *rstep = c.rstep + (size_t)k * ld;
-  int *piv = c.piv + (size_t)k * ld;
-  const int j0 = p * kNB;
-  __shared__ double s_val[kMaxLd / 64];
-  __shared__ int s_idx[kMaxLd / 64];
-  __shared__ double s_prow[kNB];
-  __shared__ int s_bad;
-
-  double reg[kNB];
-  bool used = true;
-  int mystep = INT_MAX;
-  if (t < ld) {
-    const double *row = W + (size_t)t * ld + j0;
-#pragma unroll
-    for (int q = 0; q < kNB; ++q) reg[q] = row[q];
-    mystep = rstep[t];
-    used = mystep < j0;
-  } else {
-#pragma unroll
-    for (int q = 0; q < kNB; ++q) reg[q] = 0.0;
+  // candidate of this thread: |W[t][j]| over rows not yet used as pivots;
+  // ties go to the lowest row index, NaN never wins (flagged below).
+  double v = -1.0;
+  int idx = INT_MAX;
+  if (!used) {
+    const double av = fabs(reg[JJ]);
+    v = (av == av) ? av : -2.0;
+    idx = t;
   }
-  if (t == 0) s_bad = 0;
-
 #pragma unroll
-  for (int jj = 0; jj < kNB; ++jj) {
-    // argmax |W[i][j]| over unused rows; ties go to the lowest row index
-    double v = -1.0;
-    int idx = INT_MAX;
-    if (!used) {
-      const double av = fabs(reg[jj]);
-      v = (av == av) ? av : -2.0;   // NaN never wins; flagged below
-      idx = t;
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(v, o, 64);
-      const int oi = __shfl_xor(idx, o, 64);
-      if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
-    }
-    if (lane == 0) { s_val[wid] = v; s_idx[wid] = idx; }
-    __syncthreads();
-    v = s_val[0];
-    idx = s_idx[0];
-    for (int q = 1; q < nw; ++q) {
-      const double ov = s_val[q];
-      const int oi = s_idx[q];
-      if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
-    }
-    const int r = idx;
-    if (t == r) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(v, o, 64);
+    const int oi = __shfl_xor(idx, o, 64);
+    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+  }
+  if (idx == t) {
 #pragma unroll
-      for (int q = 0; q < kNB; ++q) s_prow[q] = reg[q];
-    }
-    __syncthreads();
-    if (r == INT_MAX || r >= ld) {
-      // no candidate row (cannot happen for a valid panel)
-      if (t == 0) s_bad = 1;
-      continue;
-    }
-    double pv = s_prow[jj];
+    for (int q = 0; q < kNB; ++q) sh.cand[buf][wid][q] = reg[q];
+  }
+  if (lane == 0) {
+    sh.val[buf][wid] = v;
+    sh.idx[buf][wid] = idx;
+  }
+  __syncthreads();
+  int wb = 0;
+  double bv = sh.val[buf][0];
+  int bi = sh.idx[buf][0];
+  for (int q = 1; q < nw; ++q) {
+    const double ov = sh.val[buf][q];
+    const int oi = sh.idx[buf][q];
+    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; wb = q; }
+  }
+  const int r = bi;
+  if (r >= ld) {                     // no candidate row at all
+    if (t == 0 && atomicCAS(flag, -1, k) == -1) flag[1] = j0 + JJ;
+  } else {
+    const double *prow = sh.cand[buf][wb];
+    double pv = prow[JJ];
     if (!(fabs(pv) > 0.0) || !isfinite(pv)) {
-      if (t == 0 && atomicCAS(c.flag, -1, k) == -1) c.flag[1] = j0 + jj;
+      if (t == 0 && atomicCAS(flag, -1, k) == -1) flag[1] = j0 + JJ;
       pv = 1.0;
     }
     const double npiv = 1.0 / pv;
     if (t < ld) {
       if (t == r) {
 #pragma unroll
-        for (int q = 0; q < kNB; ++q) reg[q] = s_prow[q] * npiv;
-        reg[jj] = npiv;
+        for (int q = 0; q < kNB; ++q) reg[q] = prow[q] * npiv;
+        reg[JJ] = npiv;
         used = true;
-        mystep = j0 + jj;
+        mystep = j0 + JJ;
       } else {
-        const double fm = reg[jj] * npiv;
+        const double fm = reg[JJ] * npiv;
 #pragma unroll
-        for (int q = 0; q < kNB; ++q) reg[q] -= fm * s_prow[q];
-        reg[jj] = -fm;
+        for (int q = 0; q < kNB; ++q) reg[q] -= fm * prow[q];
+        reg[JJ] = -fm;
       }
     }
-    if (t == 0) piv[j0 + jj] = r;
+    if (t == 0) piv[j0 + JJ] = r;
   }
+  if constexpr (JJ + 1 < kNB)
+    gj_column<JJ + 1>(reg, used, mystep, sh, t, ld, nw, j0, k, piv, flag);
+}
+
+template <class Acc, class T>
+__global__ void __launch_bounds__(kMaxLd) k_panel(Acc acc, int k, int p) {
+  const ColArgs &c = acc(blockIdx.x);
+  if (k >= c.N) return;
+  const int ld = c.ld;
+  const int t = threadIdx.x;
+  const int nw = blockDim.x >> 6;
+  T *W = blocks<T>(c) + (size_t)k * ld * ld;
+  int *rstep = c.rstep + (size_t)k * ld;
+  int *piv = c.piv + (size_t)k * ld;
+  const int j0 = p * kNB;
+  __shared__ PanelShared sh;
+
+  double reg[kNB];
+  bool used = true;
+  int mystep = INT_MAX;
   if (t < ld) {
-    double *row = W + (size_t)t * ld + j0;
+    const T *row = W + (size_t)t * ld + j0;
 #pragma unroll
-    for (int q = 0; q < kNB; ++q) row[q] = reg[q];
+    for (int q = 0; q < kNB; ++q) reg[q] = (double)row[q];
+    mystep = rstep[t];
+    used = mystep < j0;
+  } else {
+#pragma unroll
+    for (int q = 0; q < kNB; ++q) reg[q] = 0.0;
+  }
+  gj_column<0>(reg, used, mystep, sh, t, ld, nw, j0, k, piv, c.flag);
+  if (t < ld) {
+    T *row = W + (size_t)t * ld + j0;
+#pragma unroll
+    for (int q = 0; q < kNB; ++q) row[q] = (T)reg[q];
     rstep[t] = mystep;
   }
 }
@@ -166,9 +188,27 @@ __global__ void __launch_bounds__(kMaxLd) k_panel(Acc acc, int k, int p) {
 // (strip, column); each owns all ld rows of its strip, so reading the pivot
 // rows (U) before overwriting them is race-free.
 typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
 
-template <class Acc, bool kMfma>
-__global__ void __launch_bounds__(256) k_update(Acc acc, int k, int p) {
+// One 16x16 output tile += A[16 x kNB] U[kNB x 16] on the matrix cores.
+// v_mfma_f64_16x16x4f64: lane holds D[l/16 + 4i][l%16];
+// v_mfma_f32_16x16x4f32: lane holds D[4(l/16) + i][l%16] (checked on gfx950).
+__device__ __forceinline__ int mfma_row(double, int lane, int i) { return (lane >> 4) + 4 * i; }
+__device__ __forceinline__ int mfma_row(float, int lane, int i) { return 4 * (lane >> 4) + i; }
+__device__ __forceinline__ double4_t mfma16(double a, double b, double4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ float4_t mfma16(float a, float b, float4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <class T> struct Vec4;
+template <> struct Vec4<double> { typedef double4_t type; };
+template <> struct Vec4<float> { typedef float4_t type; };
+
+constexpr int kUpdThreads = 1024;   // 16 waves share the row tiles of a strip
+
+template <class Acc, class T, bool kMfma>
+__global__ void __launch_bounds__(kUpdThreads) k_update(Acc acc, int k, int p) {
   const ColArgs &c = acc(blockIdx.y);
   if (k >= c.N) return;
   const int ld = c.ld;
@@ -179,11 +219,11 @@ __global__ void __launch_bounds__(256) k_update(Acc acc, int k, int p) {
   if (s >= ps) s += kNB / kStrip;             // skip the panel's strips
   if (s >= nstrip) return;
   const int c0 = s * kStrip;
-  double *W = c.B + (size_t)k * ld * ld;
+  T *W = blocks<T>(c) + (size_t)k * ld * ld;
   const int *piv = c.piv + (size_t)k * ld + j0;
   const int *rstep = c.rstep + (size_t)k * ld;
 
-  __shared__ double sU[kNB][kStrip];          // U = W[piv[J], strip]
+  __shared__ T sU[kNB][kStrip];               // U = W[piv[J], strip]
   const int t = threadIdx.x;
   for (int e = t; e < kNB * kStrip; e += blockDim.x) {
     const int q = e / kStrip, col = e % kStrip;
@@ -192,41 +232,42 @@ __global__ void __launch_bounds__(256) k_update(Acc acc, int k, int p) {
   __syncthreads();
 
   const int lane = t & 63, wid = t >> 6;
+  const int nwave = blockDim.x >> 6;
   const int ntile = ld / 16;
   if (kMfma) {
     // v_mfma_f64_16x16x4f64: lane supplies A[l%16][l/16], B[l/16][l%16];
     // lane holds D[l/16 + 4*i][l%16], i = 0..3 (checked on gfx950).
-    for (int tile = wid; tile < ntile; tile += 4) {
+    for (int tile = wid; tile < ntile; tile += nwave) {
       const int rbase = tile * 16;
-      double4_t accv;
+      typename Vec4<T>::type accv;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = rbase + (lane >> 4) + 4 * i;
+        const int row = rbase + mfma_row(T(0), lane, i);
         const int st = rstep[row];
         const bool piv_here = st >= j0 && st < j0 + kNB;
-        accv[i] = piv_here ? 0.0 : W[(size_t)row * ld + c0 + (lane & 15)];
+        accv[i] = piv_here ? T(0) : W[(size_t)row * ld + c0 + (lane & 15)];
       }
-      const double *Arow = W + (size_t)(rbase + (lane & 15)) * ld + j0;
+      const T *Arow = W + (size_t)(rbase + (lane & 15)) * ld + j0;
 #pragma unroll
       for (int kk = 0; kk < kNB / 4; ++kk) {
-        const double av = Arow[4 * kk + (lane >> 4)];
-        const double bv = sU[4 * kk + (lane >> 4)][lane & 15];
-        accv = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, accv, 0, 0, 0);
+        const T av = Arow[4 * kk + (lane >> 4)];
+        const T bv = sU[4 * kk + (lane >> 4)][lane & 15];
+        accv = mfma16(av, bv, accv);
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = rbase + (lane >> 4) + 4 * i;
+        const int row = rbase + mfma_row(T(0), lane, i);
         W[(size_t)row * ld + c0 + (lane & 15)] = accv[i];
       }
     }
   } else {
-    // VALU: thread handles (row = 16-row tile + t/16, col = t%16).
+    // VALU: thread handles (row = t/16 + multiples of blockDim/16, col = t%16).
     const int col = t & 15;
-    for (int row = t >> 4; row < ld; row += 16) {
+    for (int row = t >> 4; row < ld; row += blockDim.x >> 4) {
       const int st = rstep[row];
       const bool piv_here = st >= j0 && st < j0 + kNB;
-      double acc = piv_here ? 0.0 : W[(size_t)row * ld + c0 + col];
-      const double *Arow = W + (size_t)row * ld + j0;
+      T acc = piv_here ? T(0) : W[(size_t)row * ld + c0 + col];
+      const T *Arow = W + (size_t)row * ld + j0;
 #pragma unroll 8
       for (int q = 0; q < kNB; ++q) acc = fma(Arow[q], sU[q][col], acc);
       W[(size_t)row * ld + c0 + col] = acc;
@@ -234,27 +275,46 @@ __global__ void __launch_bounds__(256) k_update(Acc acc, int k, int p) {
   }
 }
 
-template <class Acc>
-hipError_t launch_factor_fp64(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s) {
+template <class Acc, class T>
+hipError_t launch_factor(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s) {
   if (maxN <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_rstep_init<Acc>, dim3(64, ncols), dim3(256), 0, s, acc, maxN);
   const int npanel = ld / kNB;
   const int nupd = ld / kStrip - kNB / kStrip;
   const int pthreads = round_up(ld, 64);
   for (int k = 0; k < maxN; ++k) {
-    if (k > 0)
-      hipLaunchKernelGGL(k_prologue<Acc>, dim3((ld + 7) / 8, ncols), dim3(256), 0, s, acc, k);
+    const bool prof = prof_layer(k);
+    if (k > 0) {
+      if (prof) prof_begin(kProfPrologue, s);
+      hipLaunchKernelGGL((k_prologue<Acc, T>), dim3((ld + 7) / 8, ncols), dim3(256), 0, s, acc, k);
+      if (prof) prof_end(kProfPrologue, s);
+    }
     for (int p = 0; p < npanel; ++p) {
-      hipLaunchKernelGGL(k_panel<Acc>, dim3(ncols), dim3(pthreads), 0, s, acc, k, p);
+      if (prof) prof_begin(kProfPanel, s);
+      hipLaunchKernelGGL((k_panel<Acc, T>), dim3(ncols), dim3(pthreads), 0, s, acc, k, p);
+      if (prof) prof_end(kProfPanel, s);
       if (nupd > 0) {
+        if (prof) prof_begin(kProfUpdate, s);
         if (options().gemm_mfma)
-          hipLaunchKernelGGL((k_update<Acc, true>), dim3(nupd, ncols), dim3(256), 0, s, acc, k, p);
+          hipLaunchKernelGGL((k_update<Acc, T, true>), dim3(nupd, ncols), dim3(kUpdThreads), 0, s,
+                             acc, k, p);
         else
-          hipLaunchKernelGGL((k_update<Acc, false>), dim3(nupd, ncols), dim3(256), 0, s, acc, k, p);
+          hipLaunchKernelGGL((k_update<Acc, T, false>), dim3(nupd, ncols), dim3(kUpdThreads), 0, s,
+                             acc, k, p);
+        if (prof) prof_end(kProfUpdate, s);
       }
     }
   }
   return hipGetLastError();
+}
+
+template <class Acc>
+hipError_t launch_factor_fp64(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s) {
+  return launch_factor<Acc, double>(acc, ncols, maxN, ld, s);
+}
+template <class Acc>
+hipError_t launch_factor_mixed(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s) {
+  return launch_factor<Acc, float>(acc, ncols, maxN, ld, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -264,7 +324,7 @@ hipError_t launch_factor_fp64(const Acc &acc, int ncols, int maxN, int ld, hipSt
 // Forward (k >= 1): g_k = rhs_k - a_k * (D'^{-1}_{k-1} g_{k-1}) into gs.
 // Backward:         x_k = D'^{-1}_k (g_k - c_k * x_{k+1}) into x.
 // One work-group per 16 rows of W; each wave reduces 4 rows.
-template <class Acc, bool kForward>
+template <class Acc, class T, bool kForward>
 __global__ void __launch_bounds__(256) k_solve_step(Acc acc, int k) {
   const ColArgs &c = acc(blockIdx.y);
   const int N = c.N, S = c.S, ld = c.ld;
@@ -277,7 +337,7 @@ __global__ void __launch_bounds__(256) k_solve_step(Acc acc, int k) {
       for (int y = threadIdx.x; y < S; y += blockDim.x) c.gs[y] = c.x[y];
     return;
   }
-  const double *W = c.B + (size_t)kin * ld * ld;
+  const T *W = blocks<T>(c) + (size_t)kin * ld * ld;
   const int *pv = c.piv + (size_t)kin * ld;
   const int *rq = c.rstep + (size_t)kin * ld;
   __shared__ double sv[kMaxLd];
@@ -302,9 +362,9 @@ __global__ void __launch_bounds__(256) k_solve_step(Acc acc, int k) {
   for (int rr = 0; rr < 4; ++rr) {
     const int r = blockIdx.x * 16 + wid * 4 + rr;
     if (r >= ld) break;
-    const double *row = W + (size_t)r * ld;
+    const T *row = W + (size_t)r * ld;
     double z = 0.0;
-    for (int m = lane; m < ld; m += 64) z = fma(row[m], sv[m], z);
+    for (int m = lane; m < ld; m += 64) z = fma((double)row[m], sv[m], z);
     for (int o = 32; o > 0; o >>= 1) z += __shfl_xor(z, o, 64);
     if (lane == 0) {
       const int j = rq[r];
@@ -320,20 +380,41 @@ __global__ void __launch_bounds__(256) k_solve_step(Acc acc, int k) {
   }
 }
 
-template <class Acc>
-hipError_t launch_solve_fp64(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s) {
+template <class Acc, class T>
+hipError_t launch_solve(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s) {
   if (maxN <= 0) return hipSuccess;
   dim3 grid((ld + 15) / 16, ncols);
-  for (int k = 0; k < maxN; ++k)
-    hipLaunchKernelGGL((k_solve_step<Acc, true>), grid, dim3(256), 0, s, acc, k);
-  for (int k = maxN - 1; k >= 0; --k)
-    hipLaunchKernelGGL((k_solve_step<Acc, false>), grid, dim3(256), 0, s, acc, k);
+  for (int k = 0; k < maxN; ++k) {
+    const bool prof = prof_layer(k);
+    if (prof) prof_begin(kProfSolve, s);
+    hipLaunchKernelGGL((k_solve_step<Acc, T, true>), grid, dim3(256), 0, s, acc, k);
+    if (prof) prof_end(kProfSolve, s);
+  }
+  for (int k = maxN - 1; k >= 0; --k) {
+    const bool prof = prof_layer(k);
+    if (prof) prof_begin(kProfSolve, s);
+    hipLaunchKernelGGL((k_solve_step<Acc, T, false>), grid, dim3(256), 0, s, acc, k);
+    if (prof) prof_end(kProfSolve, s);
+  }
   return hipGetLastError();
+}
+
+template <class Acc>
+hipError_t launch_solve_fp64(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s) {
+  return launch_solve<Acc, double>(acc, ncols, maxN, ld, s);
+}
+template <class Acc>
+hipError_t launch_solve_mixed(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s) {
+  return launch_solve<Acc, float>(acc, ncols, maxN, ld, s);
 }
 
 template hipError_t launch_factor_fp64<OneCol>(const OneCol &, int, int, int, hipStream_t);
 template hipError_t launch_factor_fp64<ManyCols>(const ManyCols &, int, int, int, hipStream_t);
 template hipError_t launch_solve_fp64<OneCol>(const OneCol &, int, int, int, hipStream_t);
 template hipError_t launch_solve_fp64<ManyCols>(const ManyCols &, int, int, int, hipStream_t);
+template hipError_t launch_factor_mixed<OneCol>(const OneCol &, int, int, int, hipStream_t);
+template hipError_t launch_factor_mixed<ManyCols>(const ManyCols &, int, int, int, hipStream_t);
+template hipError_t launch_solve_mixed<OneCol>(const OneCol &, int, int, int, hipStream_t);
+template hipError_t launch_solve_mixed<ManyCols>(const ManyCols &, int, int, int, hipStream_t);
 
 }  // namespace xod

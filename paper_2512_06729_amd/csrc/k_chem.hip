@@ -165,7 +165,9 @@ template <class Acc>
 hipError_t launch_rates(const Acc &acc, int ncols, int maxN, int maxR, hipStream_t s) {
   if (maxR <= 0 || maxN <= 0) return hipSuccess;
   dim3 grid((maxR + 255) / 256, maxN, ncols);
+  if (options().profile) prof_begin(kProfRates, s);
   hipLaunchKernelGGL(k_rates<Acc>, grid, dim3(256), 0, s, acc);
+  if (options().profile) prof_end(kProfRates, s);
   return hipGetLastError();
 }
 
@@ -210,12 +212,14 @@ __global__ void __launch_bounds__(256) k_rhs(Acc acc) {
 template <class Acc>
 hipError_t launch_rhs(const Acc &acc, int ncols, int maxN, int maxR, int maxS, hipStream_t s) {
   if (maxN <= 0) return hipSuccess;
+  if (options().profile) prof_begin(kProfRhs, s);
   if (maxR > 0) {
     dim3 g1((maxR + 255) / 256, maxN, ncols);
     hipLaunchKernelGGL(k_wrate<Acc>, g1, dim3(256), 0, s, acc);
   }
   dim3 g2((maxS + 255) / 256, maxN, ncols);
   hipLaunchKernelGGL(k_rhs<Acc>, g2, dim3(256), 0, s, acc);
+  if (options().profile) prof_end(kProfRhs, s);
   return hipGetLastError();
 }
 
@@ -307,10 +311,12 @@ template <class Acc>
 hipError_t launch_jacobian(const Acc &acc, int ncols, int maxN, int ld, bool mixed, hipStream_t s) {
   if (maxN <= 0) return hipSuccess;
   dim3 grid((ld + 3) / 4, maxN, ncols);
+  if (options().profile) prof_begin(kProfJac, s);
   if (mixed)
     hipLaunchKernelGGL((k_jac<Acc, true>), grid, dim3(256), 0, s, acc);
   else
     hipLaunchKernelGGL((k_jac<Acc, false>), grid, dim3(256), 0, s, acc);
+  if (options().profile) prof_end(kProfJac, s);
   return hipGetLastError();
 }
 

@@ -1,0 +1,151 @@
+// Mixed-precision solve support: FP64 residuals of the step system computed
+// matrix-free from the reaction list and the transport coefficients (no dense
+// FP64 copy of the blocks), row scaling of right-hand sides, and the update /
+// convergence measure of iterative refinement.
+//
+//   k_dwrate   dw_r = (dw_r/dn) . delta, the directional derivative of every
+//              reaction rate (same product rule as the Jacobian)
+//   k_resid    x = s * (F - M delta),  M delta = delta/dt - J_chem delta
+//              - (trl delta_{k-1} + trd delta_k + tru delta_{k+1})
+//   k_scale    x = s * F
+//   k_axpy     delta += x, per-layer max|x| / max|delta|
+#include "xod_internal.h"
+
+namespace xod {
+
+template <class Acc>
+__global__ void __launch_bounds__(256) k_dwrate(Acc acc, const double *delta, double *dw) {
+  const ColArgs &c = acc(blockIdx.z);
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (r >= c.R || k >= c.N) return;
+  const double *n = c.n + (size_t)k * c.S;
+  const double *d = delta + (size_t)k * c.S;
+  const int *rc = c.reac + r * XOD_MAX_REAC;
+  const int *pc = c.prod + r * XOD_MAX_PROD;
+  double df = 0.0, dr = 0.0;
+  for (int s = 0; s < XOD_MAX_REAC; ++s) {
+    if (rc[s] < 0) continue;
+    double p = d[rc[s]];
+    for (int t = 0; t < XOD_MAX_REAC; ++t)
+      if (t != s && rc[t] >= 0) p *= n[rc[t]];
+    df += p;
+  }
+  for (int s = 0; s < XOD_MAX_PROD; ++s) {
+    if (pc[s] < 0) continue;
+    double p = d[pc[s]];
+    for (int t = 0; t < XOD_MAX_PROD; ++t)
+      if (t != s && pc[t] >= 0) p *= n[pc[t]];
+    dr += p;
+  }
+  const size_t o = (size_t)k * c.R + r;
+  dw[o] = c.kf_in[o] * df - c.kr_in[o] * dr;
+}
+
+template <class Acc>
+__global__ void __launch_bounds__(256) k_resid(Acc acc, const double *delta, const double *dw) {
+  const ColArgs &c = acc(blockIdx.z);
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (y >= c.S || k >= c.N) return;
+  const double *w = dw + (size_t)k * c.R;
+  double jd = 0.0;
+  for (int e = c.inc_ptr[y]; e < c.inc_ptr[y + 1]; ++e) jd += c.inc_nu[e] * w[c.inc_r[e]];
+  const size_t o = (size_t)k * c.S + y;
+  double tr = c.trd[o] * delta[o];
+  if (k >= 1) tr += c.trl[o] * delta[o - c.S];
+  if (k + 1 < c.N) tr += c.tru[o] * delta[o + c.S];
+  const double Md = delta[o] / c.dt - jd - tr;
+  c.x[o] = c.rs[(size_t)k * c.ld + y] * (c.f[o] - Md);
+}
+
+template <class Acc>
+__global__ void __launch_bounds__(256) k_scale(Acc acc) {
+  const ColArgs &c = acc(blockIdx.z);
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (y >= c.S || k >= c.N) return;
+  const size_t o = (size_t)k * c.S + y;
+  c.x[o] = c.rs[(size_t)k * c.ld + y] * c.f[o];
+}
+
+// delta += x; ratio[k] = max|x_k| / max|delta_k| (0 if delta_k == 0).
+template <class Acc>
+__global__ void __launch_bounds__(256) k_axpy(Acc acc, double *delta, double *ratio) {
+  const ColArgs &c = acc(blockIdx.y);
+  const int k = blockIdx.x;
+  double *rk = ratio + (size_t)blockIdx.y * gridDim.x + k;
+  if (k >= c.N) {
+    if (threadIdx.x == 0) *rk = 0.0;
+    return;
+  }
+  __shared__ double s1[256], s2[256];
+  double m1 = 0.0, m2 = 0.0;
+  for (int y = threadIdx.x; y < c.S; y += blockDim.x) {
+    const size_t o = (size_t)k * c.S + y;
+    const double d = delta[o] + c.x[o];
+    delta[o] = d;
+    m1 = fmax(m1, fabs(c.x[o]));
+    m2 = fmax(m2, fabs(d));
+  }
+  s1[threadIdx.x] = m1;
+  s2[threadIdx.x] = m2;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + o]);
+      s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double r = s2[0] > 0.0 ? s1[0] / s2[0] : (s1[0] > 0.0 ? 1.0 : 0.0);
+    *rk = isfinite(r) ? r : 1e300;
+  }
+}
+
+__global__ void k_maxreduce(const double *v, int n, double *out) {
+  __shared__ double s[256];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, v[i]);
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = s[0];
+}
+
+template <class Acc>
+hipError_t launch_residual(const Acc &acc, int ncols, int maxN, int maxS, int maxR,
+                           const double *delta, double *dw, hipStream_t s) {
+  if (maxR > 0)
+    hipLaunchKernelGGL(k_dwrate<Acc>, dim3((maxR + 255) / 256, maxN, ncols), dim3(256), 0, s,
+                       acc, delta, dw);
+  hipLaunchKernelGGL(k_resid<Acc>, dim3((maxS + 255) / 256, maxN, ncols), dim3(256), 0, s, acc,
+                     delta, dw);
+  return hipGetLastError();
+}
+
+template <class Acc>
+hipError_t launch_scale(const Acc &acc, int ncols, int maxN, int maxS, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale<Acc>, dim3((maxS + 255) / 256, maxN, ncols), dim3(256), 0, s, acc);
+  return hipGetLastError();
+}
+
+template <class Acc>
+hipError_t launch_axpy_ratio(const Acc &acc, int ncols, int maxN, double *delta, double *ratio,
+                             double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy<Acc>, dim3(maxN, ncols), dim3(256), 0, s, acc, delta, ratio);
+  hipLaunchKernelGGL(k_maxreduce, dim3(1), dim3(256), 0, s, ratio, maxN * ncols, out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_residual<OneCol>(const OneCol &, int, int, int, int, const double *,
+                                            double *, hipStream_t);
+template hipError_t launch_scale<OneCol>(const OneCol &, int, int, int, hipStream_t);
+template hipError_t launch_axpy_ratio<OneCol>(const OneCol &, int, int, double *, double *,
+                                              double *, hipStream_t);
+
+}  // namespace xod

@@ -78,8 +78,20 @@ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 // Process-wide kernel options.
 struct Options {
   int gemm_mfma = 1;
+  int profile = 0;        // record HIP events around profiled launches
+  int profile_every = 1;  // profile layers k with k % profile_every == 0
 };
 Options &options();
+
+// Event-based launch timing (enabled with the "profile" option).  Kinds:
+enum ProfKind { kProfPanel = 0, kProfUpdate, kProfPrologue, kProfSolve, kProfJac,
+                kProfRates, kProfRhs, kProfNum };
+// Record an event pair around the next launch of `kind` on stream s.
+void prof_begin(int kind, hipStream_t s);
+void prof_end(int kind, hipStream_t s);
+inline bool prof_layer(int k) {
+  return options().profile && (k % options().profile_every) == 0;
+}
 
 // Launchers (defined in the .hip files).  Each enqueues on `stream` and
 // returns hipSuccess or the launch error.
@@ -94,6 +106,18 @@ template <class Acc>
 hipError_t launch_factor_fp64(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s);
 template <class Acc>
 hipError_t launch_solve_fp64(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s);
+template <class Acc>
+hipError_t launch_factor_mixed(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s);
+template <class Acc>
+hipError_t launch_residual(const Acc &acc, int ncols, int maxN, int maxS, int maxR,
+                           const double *delta, double *dw, hipStream_t s);
+template <class Acc>
+hipError_t launch_scale(const Acc &acc, int ncols, int maxN, int maxS, hipStream_t s);
+template <class Acc>
+hipError_t launch_axpy_ratio(const Acc &acc, int ncols, int maxN, double *delta, double *ratio,
+                             double *out, hipStream_t s);
+template <class Acc>
+hipError_t launch_solve_mixed(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s);
 
 // Column set-up arguments (k_setup).
 struct SetupArgs {

@@ -248,3 +248,48 @@ def test_batch_equals_single_columns():
         batch.step(dts)
     for c1, c2 in zip(alone, inb):
         np.testing.assert_array_equal(c1.state(), c2.state())
+
+
+# ---- mixed precision: FP32 Schur complements + FP64 refinement ------------
+
+@pytest.mark.parametrize("cfg,dt", [(1, 1e-6), (2, 1e-6), (3, 1e-7)])
+def test_mixed_step_matches_fp64_oracle(cfg, dt):
+    import paper_2512_06729_amd as xod
+    net, col, prob, gnet, gcol = G.config_pair(cfg, precision=xod.XOD_MIXED)
+    ref, delta = integrate.be_step(prob, col.n0, dt)
+    st = xod.xod_step(gcol, dt)
+    assert st["fp64_fallback"] == 0 and st["refine_iters"] >= 1
+    n = gcol.state()
+    keep = np.abs(ref) > 1e-30 * prob.grid.ngas[:, None]
+    rel = np.abs(n - ref)[keep] / np.abs(ref)[keep]
+    assert rel.max() <= 1e-6, rel.max()
+    # refinement reaches the FP64 result far below the required 1e-6
+    G.assert_state_agrees(n, ref, delta, rel=1e-8)
+
+
+def test_mixed_fixed_schedule_config1():
+    import paper_2512_06729_amd as xod
+    net, col, prob, gnet, gcol = G.config_pair(1, precision=xod.XOD_MIXED)
+    sched = integrate.fixed_schedule(200)
+    ref = integrate.run_fixed(prob, col.n0, sched)
+    fallbacks = 0
+    for dt in sched:
+        fallbacks += xod.xod_step(gcol, dt)["fp64_fallback"]
+    n = gcol.state()
+    keep = np.abs(ref) > 1e-30 * prob.grid.ngas[:, None]
+    rel = np.abs(n - ref)[keep] / np.abs(ref)[keep]
+    print(f"mixed fixed schedule: {fallbacks} FP64 fallbacks of 200, max rel err {rel.max():.2e}")
+    assert rel.max() <= 1e-6
+
+
+def test_mixed_falls_back_to_fp64_when_refinement_stalls():
+    import paper_2512_06729_amd as xod
+    net, col, prob, gnet, gcol = G.config_pair(2, precision=xod.XOD_MIXED)
+    _, _, _, _, g64 = G.config_pair(2)
+    dt = 1e9
+    st = xod.xod_step(gcol, dt)
+    xod.xod_step(g64, dt)
+    if st["fp64_fallback"]:
+        np.testing.assert_array_equal(gcol.state(), g64.state())
+    else:
+        assert st["resid_inf"] <= 1e-9
