@@ -266,6 +266,39 @@ xod_status xod_batch_destroy(xod_batch *b);
 xod_status xod_batch_step(xod_batch *b, const double *dt_per_col,
                           xod_step_stats *stats);
 
+/* ---- serving: continuous batching of steady-state solves -------------- */
+
+/* hbm_budget_bytes bounds the device memory held by resident requests;
+ * max_slots bounds their number.  All work goes to hip_stream. */
+xod_status xod_serve_create(size_t hbm_budget_bytes, int32_t max_slots,
+                            xod_precision prec, void *hip_stream,
+                            xod_server **out);
+xod_status xod_serve_destroy(xod_server *srv);
+/* Device bytes one request of this network and layer count occupies. */
+xod_status xod_serve_footprint(const xod_network *net, int32_t N,
+                               xod_precision prec, size_t *bytes);
+/* Queue a steady-state solve (host arrays copied; opts as for
+ * xod_integrate_to_steady_state, NULL = defaults).  Never blocks: a request
+ * waits in the queue until a slot and memory are free.  XOD_EINVAL if the
+ * request could never fit the budget. */
+xod_status xod_serve_submit(xod_server *srv, const xod_network *net,
+                            const xod_profile *prof, const double *n0,
+                            const xod_ss_opts *opts, uint64_t *req_id);
+/* One iteration: admit queued requests (arrival order) while a slot is free
+ * and the footprint fits, advance every resident request by one adaptive BE
+ * step (FP64 requests share batched launches), retire converged / failed
+ * ones (state copied to the host, slot and memory freed).  Synchronous. */
+xod_status xod_serve_step(xod_server *srv, int32_t *n_active, int32_t *n_queued);
+/* state: 0 queued, 1 running, 2 converged, 3 failed.  n_out (host [N*S],
+ * may be NULL) and latency_s (completion - submission, seconds) are valid
+ * once state >= 2.  Returns the failure status for state 3. */
+xod_status xod_serve_poll(xod_server *srv, uint64_t req_id, int32_t *state,
+                          double *n_out, xod_ss_result *res, double *latency_s);
+/* Forget a finished request. */
+xod_status xod_serve_release(xod_server *srv, uint64_t req_id);
+xod_status xod_serve_usage(const xod_server *srv, size_t *used_bytes,
+                           int32_t *active, int32_t *queued, int64_t *iterations);
+
 #ifdef __cplusplus
 }
 #endif

@@ -125,6 +125,19 @@ _f = {
     "xod_profile_read": _sig("xod_profile_read", ctypes.c_char_p, P_dbl,
                              ctypes.POINTER(ctypes.c_int64)),
     "xod_profile_reset": _sig("xod_profile_reset"),
+    "xod_serve_create": _sig("xod_serve_create", ctypes.c_size_t, c_int32, c_int32, c_void_p,
+                             ctypes.POINTER(c_void_p)),
+    "xod_serve_destroy": _sig("xod_serve_destroy", c_void_p),
+    "xod_serve_footprint": _sig("xod_serve_footprint", c_void_p, c_int32, c_int32,
+                                ctypes.POINTER(ctypes.c_size_t)),
+    "xod_serve_submit": _sig("xod_serve_submit", c_void_p, c_void_p, ctypes.POINTER(Profile),
+                             P_dbl, ctypes.POINTER(SSOpts), ctypes.POINTER(ctypes.c_uint64)),
+    "xod_serve_step": _sig("xod_serve_step", c_void_p, P_int, P_int),
+    "xod_serve_poll": _sig("xod_serve_poll", c_void_p, ctypes.c_uint64, P_int, P_dbl,
+                           ctypes.POINTER(SSResult), P_dbl),
+    "xod_serve_release": _sig("xod_serve_release", c_void_p, ctypes.c_uint64),
+    "xod_serve_usage": _sig("xod_serve_usage", c_void_p, ctypes.POINTER(ctypes.c_size_t), P_int,
+                            P_int, ctypes.POINTER(ctypes.c_int64)),
 }
 
 
@@ -334,6 +347,95 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None):
             _f["xod_batch_destroy"](self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _profile_struct(col, N):
+    keep = dict(P=np.ascontiguousarray(col.P_bar, np.float64),
+                T=np.ascontiguousarray(col.T_K, np.float64),
+                K=np.ascontiguousarray(col.Kzz, np.float64))
+    if col.Dmol is not None:
+        keep["D"] = np.ascontiguousarray(col.Dmol, np.float64)
+    if col.alphaT is not None:
+        keep["alpha"] = np.ascontiguousarray(col.alphaT, np.float64)
+    prof = Profile(N, _ptr(keep["P"], c_double), _ptr(keep["T"], c_double),
+                   _ptr(keep["K"], c_double),
+                   _ptr(keep["D"], c_double) if "D" in keep else None,
+                   _ptr(keep["alpha"], c_double) if "alpha" in keep else None,
+                   float(col.mbar_amu), float(col.g_cgs), float(col.sigma_tau))
+    return prof, keep
+
+
+class Server:
+    """Continuous-batching steady-state solver (xod_server)."""
+
+    QUEUED, RUNNING, DONE, FAILED = 0, 1, 2, 3
+
+    def __init__(self, hbm_budget_bytes, max_slots, precision=XOD_FP64, stream=None):
+        h = c_void_p()
+        _check(_f["xod_serve_create"](int(hbm_budget_bytes), int(max_slots), int(precision),
+                                      c_void_p(stream or 0), ctypes.byref(h)))
+        self.handle = h
+        self.precision = precision
+        self._shapes = {}
+
+    @staticmethod
+    def footprint(network, N, precision=XOD_FP64):
+        b = ctypes.c_size_t()
+        _check(_f["xod_serve_footprint"](network.handle, int(N), int(precision), ctypes.byref(b)))
+        return b.value
+
+    def submit(self, network, col, tol_rel=0.0, y_floor=0.0, y_sig=0.0, t_end=0.0, dt0=0.0,
+               max_steps=0, max_consec_rejects=0, use_mix_rule=1):
+        N = int(np.asarray(col.P_bar).shape[0])
+        prof, keep = _profile_struct(col, N)
+        n0 = np.ascontiguousarray(col.n0, np.float64)
+        o = SSOpts(tol_rel, y_floor, y_sig, t_end, dt0, max_steps, max_consec_rejects,
+                   use_mix_rule, 0)
+        rid = ctypes.c_uint64()
+        _check(_f["xod_serve_submit"](self.handle, network.handle, ctypes.byref(prof),
+                                      _ptr(n0, c_double), ctypes.byref(o), ctypes.byref(rid)))
+        self._shapes[rid.value] = (N, network.S)
+        return rid.value
+
+    def step(self):
+        a, q = c_int32(), c_int32()
+        _check(_f["xod_serve_step"](self.handle, ctypes.byref(a), ctypes.byref(q)))
+        return a.value, q.value
+
+    def poll(self, rid):
+        st = c_int32()
+        res = SSResult()
+        lat = c_double()
+        N, S = self._shapes[rid]
+        n = np.zeros((N, S))
+        status = _f["xod_serve_poll"](self.handle, rid, ctypes.byref(st), _ptr(n, c_double),
+                                      ctypes.byref(res), ctypes.byref(lat))
+        out = res.as_dict()
+        out.update(state=st.value, latency_s=lat.value, status=status)
+        if st.value >= 2:
+            out["n"] = n
+        return out
+
+    def release(self, rid):
+        _check(_f["xod_serve_release"](self.handle, rid))
+        self._shapes.pop(rid, None)
+
+    def usage(self):
+        used, a, q, it = ctypes.c_size_t(), c_int32(), c_int32(), ctypes.c_int64()
+        _check(_f["xod_serve_usage"](self.handle, ctypes.byref(used), ctypes.byref(a),
+                                     ctypes.byref(q), ctypes.byref(it)))
+        return dict(used_bytes=used.value, active=a.value, queued=q.value, iterations=it.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _f["xod_serve_destroy"](self.handle)
             self.handle = None
 
     def __del__(self):

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libxod.so")
 ARCH = os.environ.get("XOD_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "k_chem.hip", "k_btd.hip", "k_mixed.hip", "k_step.hip",
-           "batch.cpp", "prof.cpp"]
+           "batch.cpp", "prof.cpp", "serve.cpp"]
 
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -507,11 +507,20 @@ extern "C" xod_status xod_btd_solve(xod_column *col, const double *B, const doub
 
 // ---------------------------------------------------------------------------
 // Backward-Euler step on the column's own buffers.
-namespace {
+namespace xod {
 
-// Enqueue rates + rhs + jacobian + factor + solve for the column (FP64 or
-// mixed); delta ends in col->x.  Returns the refinement count via *iters.
-xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, double *resid);
+size_t column_footprint(const xod_network *net, int N, xod_precision prec) {
+  const size_t S = net->S, R = net->R, ld = net->ld, n = (size_t)N;
+  size_t b = 0;
+  b += 8 * (6 * n + 4 * n * S);                 // profile + grid vectors
+  b += 8 * (6 * n * S);                         // n, ntmp, f, x, resid, dx
+  b += 8 * (3 * n * R);                         // kf, kr, w
+  b += 8 * (4 * n * ld) + 4 * (2 * n * ld);     // gs, a, c, rs, piv, rstep
+  b += 8 * n * ld * ld;                         // FP64 blocks
+  if (prec == XOD_MIXED) b += 4 * n * ld * ld + 8 * 2 * n * ld;
+  b += 64 * 1024;                               // statistics, flags, alignment
+  return b;
+}
 
 xod_status run_update(xod_column *c, bool clip, double y_floor, double y_sig, double *out) {
   UpdArgs u{};
@@ -596,7 +605,7 @@ xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, do
   return XOD_OK;
 }
 
-}  // namespace
+}  // namespace xod
 
 extern "C" xod_status xod_step(xod_column *col, double dt, xod_step_stats *st) {
   XOD_CHECK(col, "xod_step: null column");

@@ -5,6 +5,7 @@
 // depend on which other columns share the launch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -12,40 +13,119 @@
 #include <string>
 #include <vector>
 
-#include "handles.h"
+#include "batch.h"
 
 using namespace xod;
 
-struct BatchGroup {
-  int ld = 0, maxN = 0, maxR = 0, maxS = 0;
-  std::vector<xod_column *> cols;
-  ColArgs *d_args = nullptr;
-  ColArgs *h_args = nullptr;   // pinned staging
-  UpdArgs *d_upd = nullptr;
-  UpdArgs *h_upd = nullptr;
-  RedArgs *d_red = nullptr;
-  RedArgs *h_red = nullptr;
-  double *d_stats = nullptr;   // [ncols * kStatLen]
-  double *h_stats = nullptr;
-  double *d_partial = nullptr; // [ncols * kUpdBlocks * kNStat]
-};
+namespace xod {
+
+BatchRunner::~BatchRunner() {
+  (void)hipFree(d_args);
+  (void)hipFree(d_upd);
+  (void)hipFree(d_red);
+  (void)hipFree(d_stats);
+  (void)hipFree(d_partial);
+  (void)hipHostFree(h_args);
+  (void)hipHostFree(h_upd);
+  (void)hipHostFree(h_red);
+  (void)hipHostFree(h_stats);
+}
+
+xod_status BatchRunner::init(int capacity) {
+  cap = capacity;
+  const size_t n = (size_t)cap;
+  XOD_HIP(hipMalloc((void **)&d_args, n * sizeof(ColArgs)));
+  XOD_HIP(hipMalloc((void **)&d_upd, n * sizeof(UpdArgs)));
+  XOD_HIP(hipMalloc((void **)&d_red, n * sizeof(RedArgs)));
+  XOD_HIP(hipMalloc((void **)&d_stats, n * kStatLen * sizeof(double)));
+  XOD_HIP(hipMalloc((void **)&d_partial, n * kUpdBlocks * kNStat * sizeof(double)));
+  XOD_HIP(hipHostMalloc((void **)&h_args, n * sizeof(ColArgs), hipHostMallocDefault));
+  XOD_HIP(hipHostMalloc((void **)&h_upd, n * sizeof(UpdArgs), hipHostMallocDefault));
+  XOD_HIP(hipHostMalloc((void **)&h_red, n * sizeof(RedArgs), hipHostMallocDefault));
+  XOD_HIP(hipHostMalloc((void **)&h_stats, n * kStatLen * sizeof(double), hipHostMallocDefault));
+  return XOD_OK;
+}
+
+// One FP64 BE step of every column (delta solved, n_new written to ntmp,
+// statistics into stats[i*kStatLen..]).  States are not committed here.
+xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double *dts,
+                             bool clip, double y_floor, double y_sig, hipStream_t s,
+                             std::vector<double> &stats) {
+  const int n = (int)cols.size();
+  if (n > cap) {
+    set_error("batch step: more columns than the runner's capacity");
+    return XOD_EINVAL;
+  }
+  stats.assign((size_t)n * kStatLen, 0.0);
+  // group by padded block size, keeping the caller's order inside a group
+  std::map<int, std::vector<int>> groups;
+  for (int i = 0; i < n; ++i) groups[cols[i]->ld].push_back(i);
+  int base = 0;
+  std::vector<std::pair<int, int>> slots;   // (caller index, staging slot)
+  for (auto &kv : groups) {
+    const int ld = kv.first;
+    const std::vector<int> &idx = kv.second;
+    int maxN = 0, maxR = 0, maxS = 0;
+    for (size_t j = 0; j < idx.size(); ++j) {
+      xod_column *c = cols[idx[j]];
+      const int sl = base + (int)j;
+      c->dt = dts[idx[j]];
+      h_args[sl] = c->args();
+      UpdArgs u{};
+      u.n = c->n;
+      u.x = c->x;
+      u.ngas = c->ngas;
+      u.nout = c->ntmp;
+      u.partial = d_partial + (size_t)sl * kUpdBlocks * kNStat;
+      u.N = c->N;
+      u.S = c->S;
+      u.clip = clip ? 1 : 0;
+      u.y_floor = y_floor;
+      u.y_sig = y_sig;
+      h_upd[sl] = u;
+      h_red[sl] = RedArgs{u.partial, c->flag, d_stats + (size_t)sl * kStatLen};
+      maxN = std::max(maxN, c->N);
+      maxR = std::max(maxR, c->R);
+      maxS = std::max(maxS, c->S);
+      slots.push_back({idx[j], sl});
+    }
+    const int nc = (int)idx.size();
+    XOD_HIP(hipMemcpyAsync(d_args + base, h_args + base, nc * sizeof(ColArgs),
+                           hipMemcpyHostToDevice, s));
+    XOD_HIP(hipMemcpyAsync(d_upd + base, h_upd + base, nc * sizeof(UpdArgs),
+                           hipMemcpyHostToDevice, s));
+    XOD_HIP(hipMemcpyAsync(d_red + base, h_red + base, nc * sizeof(RedArgs),
+                           hipMemcpyHostToDevice, s));
+    ManyCols acc{d_args + base};
+    XOD_HIP(launch_rates(acc, nc, maxN, maxR, s));
+    XOD_HIP(launch_rhs(acc, nc, maxN, maxR, maxS, s));
+    XOD_HIP(launch_jacobian(acc, nc, maxN, ld, false, s));
+    XOD_HIP(launch_factor_fp64(acc, nc, maxN, ld, s));
+    for (int j = 0; j < nc; ++j) {
+      xod_column *c = cols[idx[j]];
+      XOD_HIP(hipMemcpyAsync(c->x, c->f, (size_t)c->N * c->S * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+    }
+    XOD_HIP(launch_solve_fp64(acc, nc, maxN, ld, s));
+    XOD_HIP(launch_update_state(d_upd + base, d_red + base, nc, s));
+    base += nc;
+  }
+  XOD_HIP(hipMemcpyAsync(h_stats, d_stats, (size_t)n * kStatLen * sizeof(double),
+                         hipMemcpyDeviceToHost, s));
+  XOD_HIP(hipStreamSynchronize(s));
+  for (auto &pr : slots)
+    std::memcpy(&stats[(size_t)pr.first * kStatLen], h_stats + (size_t)pr.second * kStatLen,
+                kStatLen * sizeof(double));
+  return XOD_OK;
+}
+
+}  // namespace xod
 
 struct xod_batch {
   std::vector<xod_column *> cols;
-  std::vector<BatchGroup> groups;
+  BatchRunner runner;
   hipStream_t stream = nullptr;
   ~xod_batch() {
-    for (auto &g : groups) {
-      (void)hipFree(g.d_args);
-      (void)hipFree(g.d_upd);
-      (void)hipFree(g.d_red);
-      (void)hipFree(g.d_stats);
-      (void)hipFree(g.d_partial);
-      (void)hipHostFree(g.h_args);
-      (void)hipHostFree(g.h_upd);
-      (void)hipHostFree(g.h_red);
-      (void)hipHostFree(g.h_stats);
-    }
     for (auto *c : cols) c->in_batch = false;
   }
 };
@@ -70,34 +150,7 @@ extern "C" xod_status xod_batch_create(xod_column *const *cols, int32_t ncols, x
   std::unique_ptr<xod_batch> b(new xod_batch());
   b->cols.assign(cols, cols + ncols);
   b->stream = cols[0]->stream;
-  std::map<int, int> by_ld;
-  for (auto *c : b->cols) {
-    auto it = by_ld.find(c->ld);
-    if (it == by_ld.end()) {
-      by_ld[c->ld] = (int)b->groups.size();
-      b->groups.emplace_back();
-      b->groups.back().ld = c->ld;
-      it = by_ld.find(c->ld);
-    }
-    BatchGroup &g = b->groups[it->second];
-    g.cols.push_back(c);
-    g.maxN = std::max(g.maxN, c->N);
-    g.maxR = std::max(g.maxR, c->R);
-    g.maxS = std::max(g.maxS, c->S);
-  }
-  for (auto &g : b->groups) {
-    const size_t n = g.cols.size();
-    XOD_HIP(hipMalloc((void **)&g.d_args, n * sizeof(ColArgs)));
-    XOD_HIP(hipMalloc((void **)&g.d_upd, n * sizeof(UpdArgs)));
-    XOD_HIP(hipMalloc((void **)&g.d_red, n * sizeof(RedArgs)));
-    XOD_HIP(hipMalloc((void **)&g.d_stats, n * kStatLen * sizeof(double)));
-    XOD_HIP(hipMalloc((void **)&g.d_partial, n * kUpdBlocks * kNStat * sizeof(double)));
-    XOD_HIP(hipHostMalloc((void **)&g.h_args, n * sizeof(ColArgs), hipHostMallocDefault));
-    XOD_HIP(hipHostMalloc((void **)&g.h_upd, n * sizeof(UpdArgs), hipHostMallocDefault));
-    XOD_HIP(hipHostMalloc((void **)&g.h_red, n * sizeof(RedArgs), hipHostMallocDefault));
-    XOD_HIP(hipHostMalloc((void **)&g.h_stats, n * kStatLen * sizeof(double),
-                          hipHostMallocDefault));
-  }
+  XOD_TRY_B(b->runner.init(ncols));
   for (auto *c : b->cols) c->in_batch = true;
   *out = b.release();
   return XOD_OK;
@@ -114,80 +167,33 @@ extern "C" xod_status xod_batch_step(xod_batch *b, const double *dts, xod_step_s
   BCHECK(b && dts, "xod_batch_step: null argument");
   for (size_t i = 0; i < b->cols.size(); ++i)
     BCHECK(std::isfinite(dts[i]) && dts[i] > 0, "xod_batch_step: dt must be > 0");
-  hipStream_t s = b->stream;
-  // Stage per-column arguments (pinned buffers: the copies read them when
-  // the stream reaches them, and the step synchronises before returning).
-  size_t ci = 0;
-  std::map<xod_column *, size_t> index;
-  for (size_t i = 0; i < b->cols.size(); ++i) index[b->cols[i]] = i;
-  for (auto &g : b->groups) {
-    for (size_t j = 0; j < g.cols.size(); ++j) {
-      xod_column *c = g.cols[j];
-      c->dt = dts[index[c]];
-      g.h_args[j] = c->args();
-      UpdArgs u{};
-      u.n = c->n;
-      u.x = c->x;
-      u.ngas = c->ngas;
-      u.nout = c->ntmp;
-      u.partial = g.d_partial + j * kUpdBlocks * kNStat;
-      u.N = c->N;
-      u.S = c->S;
-      u.clip = 0;
-      u.y_floor = 1e-30;
-      u.y_sig = 1e-10;
-      g.h_upd[j] = u;
-      g.h_red[j] = RedArgs{u.partial, c->flag, g.d_stats + j * kStatLen};
-    }
-    const size_t n = g.cols.size();
-    XOD_HIP(hipMemcpyAsync(g.d_args, g.h_args, n * sizeof(ColArgs), hipMemcpyHostToDevice, s));
-    XOD_HIP(hipMemcpyAsync(g.d_upd, g.h_upd, n * sizeof(UpdArgs), hipMemcpyHostToDevice, s));
-    XOD_HIP(hipMemcpyAsync(g.d_red, g.h_red, n * sizeof(RedArgs), hipMemcpyHostToDevice, s));
-    ManyCols acc{g.d_args};
-    const int nc = (int)n;
-    XOD_HIP(launch_rates(acc, nc, g.maxN, g.maxR, s));
-    XOD_HIP(launch_rhs(acc, nc, g.maxN, g.maxR, g.maxS, s));
-    XOD_HIP(launch_jacobian(acc, nc, g.maxN, g.ld, false, s));
-    XOD_HIP(launch_factor_fp64(acc, nc, g.maxN, g.ld, s));
-    for (auto *c : g.cols)
-      XOD_HIP(hipMemcpyAsync(c->x, c->f, (size_t)c->N * c->S * sizeof(double),
-                             hipMemcpyDeviceToDevice, s));
-    XOD_HIP(launch_solve_fp64(acc, nc, g.maxN, g.ld, s));
-    XOD_HIP(launch_update_state(g.d_upd, g.d_red, nc, s));
-    XOD_HIP(hipMemcpyAsync(g.h_stats, g.d_stats, n * kStatLen * sizeof(double),
-                           hipMemcpyDeviceToHost, s));
-    ci += n;
-  }
-  XOD_HIP(hipStreamSynchronize(s));
+  std::vector<double> stats;
+  XOD_TRY_B(b->runner.step(b->cols, dts, false, 1e-30, 1e-10, b->stream, stats));
   xod_status ret = XOD_OK;
-  for (auto &g : b->groups) {
-    for (size_t j = 0; j < g.cols.size(); ++j) {
-      xod_column *c = g.cols[j];
-      const double *sv = g.h_stats + j * kStatLen;
-      const size_t i = index[c];
-      if (st) {
-        st[i].max_rel_change = sv[0];
-        st[i].min_ratio = sv[1];
-        st[i].resid_inf = 0.0;
-        st[i].refine_iters = 0;
-        st[i].fp64_fallback = 0;
-        st[i].nonfinite = sv[5] > 0 ? 1 : 0;
-      }
-      if (sv[kNStat] >= 0) {
-        set_error("batch column " + std::to_string(i) + ": singular Schur complement at layer " +
-                  std::to_string((long)sv[kNStat]));
-        ret = XOD_ESINGULAR;
-        continue;
-      }
-      if (sv[5] > 0) {
-        set_error("batch column " + std::to_string(i) + ": non-finite state");
-        if (ret == XOD_OK) ret = XOD_ENONFINITE;
-        continue;
-      }
-      std::swap(c->n, c->ntmp);
-      c->t += c->dt;
+  for (size_t i = 0; i < b->cols.size(); ++i) {
+    xod_column *c = b->cols[i];
+    const double *sv = &stats[i * kStatLen];
+    if (st) {
+      st[i].max_rel_change = sv[0];
+      st[i].min_ratio = sv[1];
+      st[i].resid_inf = 0.0;
+      st[i].refine_iters = 0;
+      st[i].fp64_fallback = 0;
+      st[i].nonfinite = sv[5] > 0 ? 1 : 0;
     }
+    if (sv[kNStat] >= 0) {
+      set_error("batch column " + std::to_string(i) + ": singular Schur complement at layer " +
+                std::to_string((long)sv[kNStat]));
+      ret = XOD_ESINGULAR;
+      continue;
+    }
+    if (sv[5] > 0) {
+      set_error("batch column " + std::to_string(i) + ": non-finite state");
+      if (ret == XOD_OK) ret = XOD_ENONFINITE;
+      continue;
+    }
+    std::swap(c->n, c->ntmp);
+    c->t += c->dt;
   }
-  (void)ci;
   return ret;
 }

@@ -1,0 +1,29 @@
+// Batched steps shared by xod_batch and the serving loop.
+#pragma once
+
+#include <vector>
+
+#include "handles.h"
+
+#define XOD_TRY_B(expr)            \
+  do {                             \
+    xod_status s_ = (expr);        \
+    if (s_ != XOD_OK) return s_;   \
+  } while (0)
+
+namespace xod {
+
+// Staging buffers for up to `cap` columns per batched step.
+struct BatchRunner {
+  int cap = 0;
+  ColArgs *d_args = nullptr, *h_args = nullptr;
+  UpdArgs *d_upd = nullptr, *h_upd = nullptr;
+  RedArgs *d_red = nullptr, *h_red = nullptr;
+  double *d_stats = nullptr, *h_stats = nullptr, *d_partial = nullptr;
+  ~BatchRunner();
+  xod_status init(int capacity);
+  xod_status step(const std::vector<xod_column *> &cols, const double *dts, bool clip,
+                  double y_floor, double y_sig, hipStream_t s, std::vector<double> &stats);
+};
+
+}  // namespace xod

@@ -104,3 +104,13 @@ struct xod_column {
   }
 };
 
+
+namespace xod {
+// Enqueue rates + rhs + Jacobian + factor + solve of one column (FP64, or
+// mixed with refinement and FP64 fallback); delta ends in col->x.
+xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, double *resid);
+// n_new = n + delta into col->ntmp plus statistics (host copy, kStatLen).
+xod_status run_update(xod_column *c, bool clip, double y_floor, double y_sig, double *out);
+// Device bytes a column of this network with N layers allocates.
+size_t column_footprint(const xod_network *net, int N, xod_precision prec);
+}  // namespace xod

@@ -69,83 +69,44 @@ __global__ void __launch_bounds__(256) k_prologue(Acc acc, int k) {
 
 // ---------------------------------------------------------------------------
 // Panel factorisation.  Thread t owns row t of the panel (kNB values held in
-// registers; the column loop is unrolled at compile time so every register
-// index is static).  One barrier per column: each wave publishes its best
-// candidate (value, row) and that row's panel values, so after the barrier
-// every thread knows the pivot row without a second exchange.
+// registers).  The column loop is compact (not unrolled across columns): the
+// register row rotates left by one each column, so the active column is
+// always reg[0] and every register index is static.  After kNB columns the
+// rotation is back at the identity.
+//
+// One barrier per column: each wave finds its best candidate with a DPP
+// max-reduction and a ballot (first maximum = lowest row index), publishes
+// (value, row) and that row's panel values in LDS; after the barrier every
+// thread knows the pivot row.  The loop touches no global memory (pivot rows
+// are kept in LDS and written once at the end): a work-group barrier is also
+// a release fence and would otherwise wait for outstanding global stores.
 struct PanelShared {
   double cand[2][kMaxLd / 64][kNB];   // double-buffered by column parity
   double val[2][kMaxLd / 64];
   int idx[2][kMaxLd / 64];
+  int piv[kNB];
+  int bad[2];
 };
 
-template <int JJ>
-__device__ __forceinline__ void gj_column(double (&reg)[kNB], bool &used, int &mystep,
-                                          PanelShared &sh, int t, int ld, int nw, int j0,
-                                          int k, int *piv, int *flag) {
-  constexpr int buf = JJ & 1;
-  const int lane = t & 63, wid = t >> 6;
-  // candidate of this thread: |W[t][j]| over rows not yet used as pivots;
-  // ties go to the lowest row index, NaN never wins (flagged below).
-  double v = -1.0;
-  int idx = INT_MAX;
-  if (!used) {
-    const double av = fabs(reg[JJ]);
-    v = (av == av) ? av : -2.0;
-    idx = t;
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double ov = __shfl_xor(v, o, 64);
-    const int oi = __shfl_xor(idx, o, 64);
-    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
-  }
-  if (idx == t) {
-#pragma unroll
-    for (int q = 0; q < kNB; ++q) sh.cand[buf][wid][q] = reg[q];
-  }
-  if (lane == 0) {
-    sh.val[buf][wid] = v;
-    sh.idx[buf][wid] = idx;
-  }
-  __syncthreads();
-  int wb = 0;
-  double bv = sh.val[buf][0];
-  int bi = sh.idx[buf][0];
-  for (int q = 1; q < nw; ++q) {
-    const double ov = sh.val[buf][q];
-    const int oi = sh.idx[buf][q];
-    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; wb = q; }
-  }
-  const int r = bi;
-  if (r >= ld) {                     // no candidate row at all
-    if (t == 0 && atomicCAS(flag, -1, k) == -1) flag[1] = j0 + JJ;
-  } else {
-    const double *prow = sh.cand[buf][wb];
-    double pv = prow[JJ];
-    if (!(fabs(pv) > 0.0) || !isfinite(pv)) {
-      if (t == 0 && atomicCAS(flag, -1, k) == -1) flag[1] = j0 + JJ;
-      pv = 1.0;
-    }
-    const double npiv = 1.0 / pv;
-    if (t < ld) {
-      if (t == r) {
-#pragma unroll
-        for (int q = 0; q < kNB; ++q) reg[q] = prow[q] * npiv;
-        reg[JJ] = npiv;
-        used = true;
-        mystep = j0 + JJ;
-      } else {
-        const double fm = reg[JJ] * npiv;
-#pragma unroll
-        for (int q = 0; q < kNB; ++q) reg[q] -= fm * prow[q];
-        reg[JJ] = -fm;
-      }
-    }
-    if (t == 0) piv[j0 + JJ] = r;
-  }
-  if constexpr (JJ + 1 < kNB)
-    gj_column<JJ + 1>(reg, used, mystep, sh, t, ld, nw, j0, k, piv, flag);
+template <int C>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), C, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), C, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Maximum over the 64 lanes (quad_perm, row_ror, row_bcast:15/31), read from
+// the last lane and returned to every lane.
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_move<0xb1>(v));    // quad_perm [1,0,3,2]
+  v = fmax(v, dpp_move<0x4e>(v));    // quad_perm [2,3,0,1]
+  v = fmax(v, dpp_move<0x124>(v));   // row_ror:4
+  v = fmax(v, dpp_move<0x128>(v));   // row_ror:8
+  v = fmax(v, dpp_move<0x142>(v));   // row_bcast:15
+  v = fmax(v, dpp_move<0x143>(v));   // row_bcast:31
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 template <class Acc, class T>
@@ -155,6 +116,7 @@ __global__ void __launch_bounds__(kMaxLd) k_panel(Acc acc, int k, int p) {
   const int ld = c.ld;
   const int t = threadIdx.x;
   const int nw = blockDim.x >> 6;
+  const int lane = t & 63, wid = t >> 6;
   T *W = blocks<T>(c) + (size_t)k * ld * ld;
   int *rstep = c.rstep + (size_t)k * ld;
   int *piv = c.piv + (size_t)k * ld;
@@ -174,7 +136,67 @@ __global__ void __launch_bounds__(kMaxLd) k_panel(Acc acc, int k, int p) {
 #pragma unroll
     for (int q = 0; q < kNB; ++q) reg[q] = 0.0;
   }
-  gj_column<0>(reg, used, mystep, sh, t, ld, nw, j0, k, piv, c.flag);
+  if (t == 0) sh.bad[0] = sh.bad[1] = -1;
+
+#pragma unroll 1
+  for (int jj = 0; jj < kNB; ++jj) {
+    const int buf = jj & 1;
+    // candidate |W[t][j]| over rows not yet used as pivots; NaN never wins
+    double v = -1.0;
+    if (!used) {
+      const double av = fabs(reg[0]);
+      v = (av == av) ? av : -2.0;
+    }
+    const double m = wave_max(v);
+    const unsigned long long hit = __ballot(v == m);
+    const int first = __ffsll((long long)hit) - 1;
+    const int idx = (m >= 0.0) ? wid * 64 + first : INT_MAX;
+    if (idx == t) {
+#pragma unroll
+      for (int q = 0; q < kNB; ++q) sh.cand[buf][wid][q] = reg[q];
+    }
+    if (lane == 0) {
+      sh.val[buf][wid] = m;
+      sh.idx[buf][wid] = idx;
+    }
+    __syncthreads();
+    int wb = 0;
+    double bv = sh.val[buf][0];
+    int bi = sh.idx[buf][0];
+    for (int q = 1; q < nw; ++q) {
+      const double ov = sh.val[buf][q];
+      const int oi = sh.idx[buf][q];
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; wb = q; }
+    }
+    const int r = bi;
+    if (r >= ld) {                       // no candidate row at all
+      if (t == 0) { sh.piv[jj] = 0; if (sh.bad[0] < 0) sh.bad[0] = jj; }
+      continue;
+    }
+    const double *prow = sh.cand[buf][wb];
+    double pv = prow[0];
+    if (!(fabs(pv) > 0.0) || !isfinite(pv)) {
+      if (t == 0 && sh.bad[0] < 0) sh.bad[0] = jj;
+      pv = 1.0;
+    }
+    const double npiv = 1.0 / pv;
+    if (t == r) {
+#pragma unroll
+      for (int q = 0; q < kNB - 1; ++q) reg[q] = prow[q + 1] * npiv;
+      reg[kNB - 1] = npiv;
+      used = true;
+      mystep = j0 + jj;
+    } else {
+      const double fm = reg[0] * npiv;
+#pragma unroll
+      for (int q = 0; q < kNB - 1; ++q) reg[q] = reg[q + 1] - fm * prow[q + 1];
+      reg[kNB - 1] = -fm;
+    }
+    if (t == 0) sh.piv[jj] = r;
+  }
+  __syncthreads();
+  if (t < kNB) piv[j0 + t] = sh.piv[t];
+  if (t == 0 && sh.bad[0] >= 0 && atomicCAS(c.flag, -1, k) == -1) c.flag[1] = j0 + sh.bad[0];
   if (t < ld) {
     T *row = W + (size_t)t * ld + j0;
 #pragma unroll
