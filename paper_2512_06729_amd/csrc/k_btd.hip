@@ -68,24 +68,29 @@ __global__ void __launch_bounds__(256) k_prologue(Acc acc, int k) {
 }
 
 // ---------------------------------------------------------------------------
-// Panel factorisation.  Thread t owns row t of the panel (kNB values held in
-// registers).  The column loop is compact (not unrolled across columns): the
-// register row rotates left by one each column, so the active column is
-// always reg[0] and every register index is static.  After kNB columns the
-// rotation is back at the identity.
+// Panel factorisation: Gauss-Jordan on the ld x kNB panel of one Schur
+// complement, with implicit partial pivoting.
 //
-// One barrier per column: each wave finds its best candidate with a DPP
-// max-reduction and a ballot (first maximum = lowest row index), publishes
-// (value, row) and that row's panel values in LDS; after the barrier every
-// thread knows the pivot row.  The loop touches no global memory (pivot rows
-// are kept in LDS and written once at the end): a work-group barrier is also
-// a release fence and would otherwise wait for outstanding global stores.
+// Four waves (one per SIMD) of 64 lanes; thread t owns the R contiguous rows
+// R*t .. R*t+R-1 (R = ceil(ld/256) <= 4), each held as a 32-wide register
+// vector indexed by the uniform column number.  Row order (thread, chunk
+// index) is the global row order, so "first maximum wins" is exact: the local
+// pick keeps the lowest chunk index, the ballot the lowest lane, the cross-wave
+// pick the lowest wave.
+//
+// One barrier per column: each wave finds its best candidate with a DPP max
+// and a ballot and publishes (value, row) and the row's panel values in LDS
+// (double-buffered by column parity).  The loop touches no global memory.
+constexpr int kPanelRows = 2;      // rows per thread (kept in registers)
+constexpr int kPanelWaves = kMaxLd / (64 * kPanelRows);   // up to 8 waves
+constexpr int kGroup = 8;          // columns per unrolled group
+
 struct PanelShared {
-  double cand[2][kMaxLd / 64][kNB];   // double-buffered by column parity
-  double val[2][kMaxLd / 64];
-  int idx[2][kMaxLd / 64];
+  double cand[2][kPanelWaves][kNB];
+  double val[2][kPanelWaves];
+  int idx[2][kPanelWaves];
   int piv[kNB];
-  int bad[2];
+  int bad;
 };
 
 template <int C>
@@ -109,100 +114,156 @@ __device__ __forceinline__ double wave_max(double v) {
   return __hiloint2double(hi, lo);
 }
 
-template <class Acc, class T>
-__global__ void __launch_bounds__(kMaxLd) k_panel(Acc acc, int k, int p) {
+// One Gauss-Jordan column at static position U of the (rotated) rows.
+template <int R, int U>
+__device__ __forceinline__ void gj_col(double (&row)[R][kNB], bool (&used)[R], int (&mystep)[R],
+                                       PanelShared &sh, int t, int ld, int jcol, int j0) {
+  const int lane = t & 63, wid = t >> 6;
+  const int buf = jcol & 1;
+  // best candidate of this thread (lowest chunk index among equals)
+  double v = -1.0;
+  int ib = 0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    if (!used[i]) {
+      const double av = fabs(row[i][U]);
+      const double a2 = (av == av) ? av : -2.0;   // NaN never wins (flagged below)
+      if (a2 > v) { v = a2; ib = i; }
+    }
+  }
+  const double m = wave_max(v);
+  const unsigned long long hit = __ballot(v == m);
+  const int first = __ffsll((long long)hit) - 1;
+  if (lane == first) {
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      if (i == ib) {
+#pragma unroll
+        for (int q = 0; q < kNB; ++q) sh.cand[buf][wid][q] = row[i][q];
+      }
+    sh.val[buf][wid] = m;
+    sh.idx[buf][wid] = m >= 0.0 ? R * t + ib : INT_MAX;
+  }
+  __syncthreads();
+  const int nw = blockDim.x >> 6;
+  double bv = sh.val[buf][0];
+  int wb = 0;
+#pragma unroll
+  for (int q = 1; q < kPanelWaves; ++q) {
+    const double ov = q < nw ? sh.val[buf][q] : -3.0;
+    if (ov > bv) { bv = ov; wb = q; }                // ties keep the lower wave
+  }
+  const int r = sh.idx[buf][wb];
+  if (r >= ld) {                                       // no candidate row at all
+    if (t == 0) { sh.piv[jcol] = 0; if (sh.bad < 0) sh.bad = jcol; }
+    return;
+  }
+  const double *prow = sh.cand[buf][wb];
+  double pv = prow[U];
+  if (!(fabs(pv) > 0.0) || !isfinite(pv)) {
+    if (t == 0 && sh.bad < 0) sh.bad = jcol;
+    pv = 1.0;
+  }
+  const double npiv = 1.0 / pv;
+  double fm[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) fm[i] = row[i][U] * npiv;
+#pragma unroll
+  for (int q = 0; q < kNB; ++q) {
+    const double pq = prow[q];
+#pragma unroll
+    for (int i = 0; i < R; ++i) row[i][q] = (R * t + i == r) ? pq * npiv : row[i][q] - fm[i] * pq;
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    if (R * t + i == r) {
+      row[i][U] = npiv;
+      used[i] = true;
+      mystep[i] = j0 + jcol;
+    } else {
+      row[i][U] = -fm[i];
+    }
+  }
+  if (t == 0) sh.piv[jcol] = r;
+}
+
+template <int R, int U>
+__device__ __forceinline__ void gj_group(double (&row)[R][kNB], bool (&used)[R],
+                                         int (&mystep)[R], PanelShared &sh, int t, int ld,
+                                         int jbase, int j0) {
+  gj_col<R, U>(row, used, mystep, sh, t, ld, jbase + U, j0);
+  if constexpr (U + 1 < kGroup) gj_group<R, U + 1>(row, used, mystep, sh, t, ld, jbase, j0);
+}
+
+template <class Acc, class T, int R>
+__global__ void __launch_bounds__(64 * kPanelWaves) k_panel(Acc acc, int k, int p) {
   const ColArgs &c = acc(blockIdx.x);
   if (k >= c.N) return;
   const int ld = c.ld;
   const int t = threadIdx.x;
-  const int nw = blockDim.x >> 6;
-  const int lane = t & 63, wid = t >> 6;
   T *W = blocks<T>(c) + (size_t)k * ld * ld;
   int *rstep = c.rstep + (size_t)k * ld;
   int *piv = c.piv + (size_t)k * ld;
   const int j0 = p * kNB;
   __shared__ PanelShared sh;
 
-  double reg[kNB];
-  bool used = true;
-  int mystep = INT_MAX;
-  if (t < ld) {
-    const T *row = W + (size_t)t * ld + j0;
+  double row[R][kNB];
+  bool used[R];
+  int mystep[R];
 #pragma unroll
-    for (int q = 0; q < kNB; ++q) reg[q] = (double)row[q];
-    mystep = rstep[t];
-    used = mystep < j0;
-  } else {
+  for (int i = 0; i < R; ++i) {
+    const int g = R * t + i;
+    used[i] = true;
+    mystep[i] = INT_MAX;
+    if (g < ld) {
+      const T *src = W + (size_t)g * ld + j0;
 #pragma unroll
-    for (int q = 0; q < kNB; ++q) reg[q] = 0.0;
-  }
-  if (t == 0) sh.bad[0] = sh.bad[1] = -1;
-
-#pragma unroll 1
-  for (int jj = 0; jj < kNB; ++jj) {
-    const int buf = jj & 1;
-    // candidate |W[t][j]| over rows not yet used as pivots; NaN never wins
-    double v = -1.0;
-    if (!used) {
-      const double av = fabs(reg[0]);
-      v = (av == av) ? av : -2.0;
-    }
-    const double m = wave_max(v);
-    const unsigned long long hit = __ballot(v == m);
-    const int first = __ffsll((long long)hit) - 1;
-    const int idx = (m >= 0.0) ? wid * 64 + first : INT_MAX;
-    if (idx == t) {
-#pragma unroll
-      for (int q = 0; q < kNB; ++q) sh.cand[buf][wid][q] = reg[q];
-    }
-    if (lane == 0) {
-      sh.val[buf][wid] = m;
-      sh.idx[buf][wid] = idx;
-    }
-    __syncthreads();
-    int wb = 0;
-    double bv = sh.val[buf][0];
-    int bi = sh.idx[buf][0];
-    for (int q = 1; q < nw; ++q) {
-      const double ov = sh.val[buf][q];
-      const int oi = sh.idx[buf][q];
-      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; wb = q; }
-    }
-    const int r = bi;
-    if (r >= ld) {                       // no candidate row at all
-      if (t == 0) { sh.piv[jj] = 0; if (sh.bad[0] < 0) sh.bad[0] = jj; }
-      continue;
-    }
-    const double *prow = sh.cand[buf][wb];
-    double pv = prow[0];
-    if (!(fabs(pv) > 0.0) || !isfinite(pv)) {
-      if (t == 0 && sh.bad[0] < 0) sh.bad[0] = jj;
-      pv = 1.0;
-    }
-    const double npiv = 1.0 / pv;
-    if (t == r) {
-#pragma unroll
-      for (int q = 0; q < kNB - 1; ++q) reg[q] = prow[q + 1] * npiv;
-      reg[kNB - 1] = npiv;
-      used = true;
-      mystep = j0 + jj;
+      for (int q = 0; q < kNB; ++q) row[i][q] = (double)src[q];
+      mystep[i] = rstep[g];
+      used[i] = mystep[i] < j0;
     } else {
-      const double fm = reg[0] * npiv;
 #pragma unroll
-      for (int q = 0; q < kNB - 1; ++q) reg[q] = reg[q + 1] - fm * prow[q + 1];
-      reg[kNB - 1] = -fm;
+      for (int q = 0; q < kNB; ++q) row[i][q] = 0.0;
     }
-    if (t == 0) sh.piv[jj] = r;
+  }
+  if (t == 0) sh.bad = -1;
+
+  // Columns in groups of kGroup: the group's columns sit at static positions
+  // 0..kGroup-1; afterwards every row rotates left by kGroup, so after the
+  // last group the rows are back in panel order.
+#pragma unroll 1
+  for (int jb = 0; jb < kNB; jb += kGroup) {
+    gj_group<R, 0>(row, used, mystep, sh, t, ld, jb, j0);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      double tmp[kGroup];
+#pragma unroll
+      for (int q = 0; q < kGroup; ++q) tmp[q] = row[i][q];
+#pragma unroll
+      for (int q = 0; q + kGroup < kNB; ++q) row[i][q] = row[i][q + kGroup];
+#pragma unroll
+      for (int q = 0; q < kGroup; ++q) row[i][kNB - kGroup + q] = tmp[q];
+    }
   }
   __syncthreads();
   if (t < kNB) piv[j0 + t] = sh.piv[t];
-  if (t == 0 && sh.bad[0] >= 0 && atomicCAS(c.flag, -1, k) == -1) c.flag[1] = j0 + sh.bad[0];
-  if (t < ld) {
-    T *row = W + (size_t)t * ld + j0;
+  if (t == 0 && sh.bad >= 0 && atomicCAS(c.flag, -1, k) == -1) c.flag[1] = j0 + sh.bad;
 #pragma unroll
-    for (int q = 0; q < kNB; ++q) row[q] = (T)reg[q];
-    rstep[t] = mystep;
+  for (int i = 0; i < R; ++i) {
+    const int g = R * t + i;
+    if (g < ld) {
+      T *dst = W + (size_t)g * ld + j0;
+#pragma unroll
+      for (int q = 0; q < kNB; ++q) dst[q] = (T)row[i][q];
+      rstep[g] = mystep[i];
+    }
   }
+}
+
+template <class Acc, class T>
+void launch_panel(const Acc &acc, int ncols, int ld, int k, int p, hipStream_t s) {
+  const int threads = 64 * ((ld + 64 * kPanelRows - 1) / (64 * kPanelRows));
+  hipLaunchKernelGGL((k_panel<Acc, T, kPanelRows>), dim3(ncols), dim3(threads), 0, s, acc, k, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -235,54 +296,75 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(Acc acc, int k, int p) {
   if (k >= c.N) return;
   const int ld = c.ld;
   const int j0 = p * kNB;
-  const int nstrip = ld / kStrip;
-  int s = blockIdx.x;
-  const int ps = j0 / kStrip;                 // first strip of the panel
-  if (s >= ps) s += kNB / kStrip;             // skip the panel's strips
-  if (s >= nstrip) return;
+  // Strip s is always work-group s of the launch (all ld/16 strips are
+  // launched, the panel's own strips return), so a strip stays on the same
+  // XCD for every panel and layer.
+  const int s = blockIdx.x;
   const int c0 = s * kStrip;
+  if (c0 >= ld || (c0 >= j0 && c0 < j0 + kNB)) return;
   T *W = blocks<T>(c) + (size_t)k * ld * ld;
   const int *piv = c.piv + (size_t)k * ld + j0;
   const int *rstep = c.rstep + (size_t)k * ld;
 
   __shared__ T sU[kNB][kStrip];               // U = W[piv[J], strip]
   const int t = threadIdx.x;
-  for (int e = t; e < kNB * kStrip; e += blockDim.x) {
-    const int q = e / kStrip, col = e % kStrip;
-    sU[q][col] = W[(size_t)piv[q] * ld + c0 + col];
-  }
-  __syncthreads();
-
   const int lane = t & 63, wid = t >> 6;
   const int nwave = blockDim.x >> 6;
   const int ntile = ld / 16;
   if (kMfma) {
-    // v_mfma_f64_16x16x4f64: lane supplies A[l%16][l/16], B[l/16][l%16];
-    // lane holds D[l/16 + 4*i][l%16], i = 0..3 (checked on gfx950).
-    for (int tile = wid; tile < ntile; tile += nwave) {
-      const int rbase = tile * 16;
-      typename Vec4<T>::type accv;
+    // Prefetch this wave's tiles (A operand, C tile, pivot mask) before U is
+    // published, so their latency overlaps the U gather.
+    constexpr int kMaxTiles = kMaxLd / 16 / (kUpdThreads / 64);
+    T av[kMaxTiles][kNB / 4];
+    T cv[kMaxTiles][4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = rbase + mfma_row(T(0), lane, i);
-        const int st = rstep[row];
-        const bool piv_here = st >= j0 && st < j0 + kNB;
-        accv[i] = piv_here ? T(0) : W[(size_t)row * ld + c0 + (lane & 15)];
+    for (int u = 0; u < kMaxTiles; ++u) {
+      const int tile = wid + nwave * u;
+      if (tile < ntile) {
+        const int rbase = tile * 16;
+        const T *Arow = W + (size_t)(rbase + (lane & 15)) * ld + j0;
+#pragma unroll
+        for (int kk = 0; kk < kNB / 4; ++kk) av[u][kk] = Arow[4 * kk + (lane >> 4)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = rbase + mfma_row(T(0), lane, i);
+          const int st = rstep[row];
+          const bool piv_here = st >= j0 && st < j0 + kNB;
+          cv[u][i] = piv_here ? T(0) : W[(size_t)row * ld + c0 + (lane & 15)];
+        }
       }
-      const T *Arow = W + (size_t)(rbase + (lane & 15)) * ld + j0;
+    }
+    for (int e = t; e < kNB * kStrip; e += blockDim.x) {
+      const int q = e / kStrip, col = e % kStrip;
+      sU[q][col] = W[(size_t)piv[q] * ld + c0 + col];
+    }
+    __syncthreads();
+    // v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32: lane supplies
+    // A[l%16][l/16] and B[l/16][l%16]; output rows per mfma_row().
 #pragma unroll
-      for (int kk = 0; kk < kNB / 4; ++kk) {
-        const T av = Arow[4 * kk + (lane >> 4)];
-        const T bv = sU[4 * kk + (lane >> 4)][lane & 15];
-        accv = mfma16(av, bv, accv);
-      }
+    for (int u = 0; u < kMaxTiles; ++u) {
+      const int tile = wid + nwave * u;
+      if (tile < ntile) {
+        const int rbase = tile * 16;
+        typename Vec4<T>::type accv;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = rbase + mfma_row(T(0), lane, i);
-        W[(size_t)row * ld + c0 + (lane & 15)] = accv[i];
+        for (int i = 0; i < 4; ++i) accv[i] = cv[u][i];
+#pragma unroll
+        for (int kk = 0; kk < kNB / 4; ++kk)
+          accv = mfma16(av[u][kk], sU[4 * kk + (lane >> 4)][lane & 15], accv);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = rbase + mfma_row(T(0), lane, i);
+          W[(size_t)row * ld + c0 + (lane & 15)] = accv[i];
+        }
       }
     }
   } else {
+    for (int e = t; e < kNB * kStrip; e += blockDim.x) {
+      const int q = e / kStrip, col = e % kStrip;
+      sU[q][col] = W[(size_t)piv[q] * ld + c0 + col];
+    }
+    __syncthreads();
     // VALU: thread handles (row = t/16 + multiples of blockDim/16, col = t%16).
     const int col = t & 15;
     for (int row = t >> 4; row < ld; row += blockDim.x >> 4) {
@@ -302,8 +384,7 @@ hipError_t launch_factor(const Acc &acc, int ncols, int maxN, int ld, hipStream_
   if (maxN <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_rstep_init<Acc>, dim3(64, ncols), dim3(256), 0, s, acc, maxN);
   const int npanel = ld / kNB;
-  const int nupd = ld / kStrip - kNB / kStrip;
-  const int pthreads = round_up(ld, 64);
+  const int nupd = ld / kStrip;   // every strip; the panel's own return
   for (int k = 0; k < maxN; ++k) {
     const bool prof = prof_layer(k);
     if (k > 0) {
@@ -313,7 +394,7 @@ hipError_t launch_factor(const Acc &acc, int ncols, int maxN, int ld, hipStream_
     }
     for (int p = 0; p < npanel; ++p) {
       if (prof) prof_begin(kProfPanel, s);
-      hipLaunchKernelGGL((k_panel<Acc, T>), dim3(ncols), dim3(pthreads), 0, s, acc, k, p);
+      launch_panel<Acc, T>(acc, ncols, ld, k, p, s);
       if (prof) prof_end(kProfPanel, s);
       if (nupd > 0) {
         if (prof) prof_begin(kProfUpdate, s);
