@@ -2,16 +2,20 @@
 species x 150 layers (7720 reactions), the size of the paper's largest
 network (Section 2.2) on a 150-layer column.
 
-One step = rates, right-hand side, step-matrix assembly, block-tridiagonal
-factorisation (Schur complements inverted by blocked Gauss-Jordan with FP64
-MFMA updates), the substitution chain and the state update, i.e. every
-stage of the implicit step, on inputs resident in HBM.
+One step = rates, right-hand side, step-matrix assembly, factorisation of
+the block-tridiagonal step system, the substitution and the state update,
+i.e. every stage of the implicit step, on inputs resident in HBM.  The
+factorisation is block cyclic reduction by default (--solver cr: batched
+Gauss-Jordan inversions of the eliminated layers of each level and dense
+Schur products on the FP64 matrix cores) or block Thomas (--solver thomas:
+one Schur complement inversion per layer, bottom to top).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--solver cr|thomas]
+                    [--no-cpu-baseline] [--skip-mixed] [--skip-thomas]
 
-Prints one JSON line.  The roofline entry is for the dominant kernel (the
-Schur-update GEMM of the factorisation); its average launch duration is
-measured with HIP events on the column's stream during the timed steps.
+Prints one JSON line.  The roofline entry is for the kernel with the largest
+share of the step time; kernel times are measured with HIP events around
+every launch on the column's stream during the timed steps.
 """
 
 import argparse
@@ -24,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_MFMA_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+PEAK_FP64_VALU_TFLOPS = 78.6  # MI355X FP64 vector peak (256 CUs x 2.4 GHz x 128 flop)
 PEAK_HBM_GBS = 8000.0
 
 
@@ -36,6 +41,32 @@ def schur_update_flops(S, nb=32):
         nbp = min(nb, S - j0)
         out.append(2.0 * S * (S - nbp) * nbp)
     return out
+
+
+def cr_levels(N):
+    """Layers eliminated / kept at each level of block cyclic reduction."""
+    out, rem, h = [], list(range(N)), 1
+    while len(rem) > 1:
+        elim = [k for k in rem if (k // h) % 2]
+        kept = [k for k in rem if not (k // h) % 2]
+        out.append((h, elim, kept))
+        rem, h = kept, 2 * h
+    return out
+
+
+def cr_gemm_products(N):
+    """Dense S x S block products of one cyclic-reduction factorisation
+    (levels >= 1; level 0 has diagonal couplings and no products):
+    per kept layer with a left / right neighbour one product A E / C E, one
+    per Schur term subtracted from D, and one for each new coupling."""
+    n = 0
+    for h, elim, kept in cr_levels(N):
+        if h == 1:
+            continue
+        for k in kept:
+            hl, hr = k - h >= 0, k + h <= N - 1
+            n += 2 * (hl + hr) + (k - 2 * h >= 0) + (k + 2 * h <= N - 1)
+    return n
 
 
 def cpu_baseline(net, col, seconds=15.0):
@@ -65,12 +96,13 @@ def cpu_baseline(net, col, seconds=15.0):
                       "NumPy/SciPy with their default BLAS threads"}
 
 
-def bench_mixed(xod, torch, gnet, col, args):
-    """The same steps with FP32 Schur complements and FP64 refinement."""
+def bench_mixed(xod, torch, gnet, col, args, solver):
+    """The same steps with FP32 Schur complements / products and FP64
+    refinement; error of the first step against the FP64 GPU step."""
     import numpy as np
     stream = torch.cuda.current_stream().cuda_stream
-    gm = xod.Column(gnet, col, precision=xod.XOD_MIXED, stream=stream)
-    g64 = xod.Column(gnet, col, precision=xod.XOD_FP64, stream=stream)
+    gm = xod.Column(gnet, col, precision=xod.XOD_MIXED, stream=stream, solver=solver)
+    g64 = xod.Column(gnet, col, precision=xod.XOD_FP64, stream=stream, solver=solver)
     st = xod.xod_step(gm, args.dt)
     xod.xod_step(g64, args.dt)
     a, b = gm.state(), g64.state()
@@ -94,15 +126,29 @@ def bench_mixed(xod, torch, gnet, col, args):
             "first_step_max_rel_err_vs_fp64": err, "first_step_refine_iters": st["refine_iters"]}
 
 
+def timed_steps(xod, torch, gcol, dt, steps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        xod.xod_step(gcol, dt)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+KERNELS = ("panel", "update", "gemm", "prologue", "solve", "jacobian", "rates", "rhs")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dt", type=float, default=1e-6)
+    ap.add_argument("--solver", choices=("cr", "thomas"), default="cr")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-every", type=int, default=10)
+    ap.add_argument("--profile-every", type=int, default=1)
     ap.add_argument("--skip-mixed", action="store_true")
+    ap.add_argument("--skip-thomas", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): columns are "
@@ -119,35 +165,63 @@ def main():
     net, col = synth.make_config(3)
     stream = torch.cuda.current_stream().cuda_stream
     gnet = xod.Network(net)
-    gcol = xod.Column(gnet, col, precision=xod.XOD_FP64, stream=stream)
+    solver = xod.XOD_SOLVER_CR if args.solver == "cr" else xod.XOD_SOLVER_THOMAS
+    gcol = xod.Column(gnet, col, precision=xod.XOD_FP64, stream=stream, solver=solver)
 
     for _ in range(args.warmup):
         xod.xod_step(gcol, args.dt)
     torch.cuda.synchronize()
 
+    # timed region: kernel events on (profile_every thins the per-layer
+    # block-Thomas events; cyclic reduction records every launch)
     xod.profile_reset()
     xod.set_option("profile_every", args.profile_every)
     xod.set_option("profile", 1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        xod.xod_step(gcol, args.dt)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    el = timed_steps(xod, torch, gcol, args.dt, args.steps)
     xod.set_option("profile", 0)
 
     kern = {}
-    for name in ("panel", "update", "prologue", "solve", "jacobian", "rates", "rhs"):
+    for name in KERNELS:
         ms, cnt = xod.profile_read(name)
         kern[name] = {"total_ms": ms, "launches": cnt,
                       "avg_us": 1e3 * ms / cnt if cnt else None}
 
     S, N = net.S, col.N
-    fl = schur_update_flops(S)
-    upd_launch_flops = float(np.mean(fl[:-1] if len(fl) > 1 else fl))
-    # every layer profiled when profile_every == 1: launches = steps * N * npanel
-    upd = kern["update"]
-    achieved = upd_launch_flops / (upd["avg_us"] * 1e-6) / 1e12 if upd["avg_us"] else None
+    # algorithmic flops per step of the kernels that carry the factorisation
+    npanel = -(-S // 32)
+    gj_flops = 2.0 * S ** 3                          # one Gauss-Jordan inversion
+    panel_flops = 2.0 * S * 32 * 32 * npanel         # the panels' share of it
+    if args.solver == "cr":
+        gemm_flops = 2.0 * S ** 3 * cr_gemm_products(N)
+    else:
+        gemm_flops = 0.0
+    upd_flops = N * (gj_flops - panel_flops)
+    flops = {"gemm": gemm_flops, "update": upd_flops, "panel": N * panel_flops}
+    dominant = max(("panel", "update", "gemm"), key=lambda k: kern[k]["total_ms"])
+    dk = kern[dominant]
+    steps_prof = args.steps   # events cover every timed step
+    frac_prof = 1.0 if args.solver == "cr" else 1.0 / args.profile_every
+    per_launch_flops = flops[dominant] * steps_prof * frac_prof / max(dk["launches"], 1)
+    achieved = per_launch_flops / (dk["avg_us"] * 1e-6) / 1e12 if dk["avg_us"] else None
+    if dominant == "panel":
+        rl = {"bound": "alu", "kernel": "k_panel (Gauss-Jordan panel, FP64 VALU, one "
+              "work-group per block)", "peak": PEAK_FP64_VALU_TFLOPS}
+    else:
+        rl = {"bound": "mfma", "kernel": ("k_gemm (cyclic-reduction Schur products, FP64 MFMA)"
+                                          if dominant == "gemm" else
+                                          "k_update (Gauss-Jordan trailing update, FP64 MFMA)"),
+              "peak": PEAK_FP64_MFMA_TFLOPS}
+    rl.update({"achieved": achieved, "unit": "TFLOP/s",
+               "frac": achieved / rl["peak"] if achieved else None, "traffic": None,
+               "flops_per_launch": per_launch_flops, "avg_launch_us": dk["avg_us"]})
+    gemm = kern["gemm"]
+    gemm_rl = None
+    if gemm["avg_us"]:
+        g_ach = gemm_flops * args.steps / (gemm["total_ms"] * 1e-3) / 1e12
+        gemm_rl = {"bound": "mfma", "kernel": "k_gemm", "achieved": g_ach,
+                   "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                   "frac": g_ach / PEAK_FP64_MFMA_TFLOPS,
+                   "flops_per_step": gemm_flops}
 
     steps_per_s = args.steps / el
     line = {
@@ -164,18 +238,25 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded 594-species / 7720-reaction network, 150-layer column)",
         "config": {"workload": "single column, S=594 species, R=7720 reactions, N=150 layers, "
-                               "backward-Euler step (rates+RHS+Jacobian+block Thomas+solve+update)",
-                   "S": S, "R": net.R, "N": N, "precision": "fp64", "dt": args.dt},
-        "roofline": {"bound": "mfma", "kernel": "k_update (Schur-update GEMM, FP64 MFMA)",
-                     "achieved": achieved, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_MFMA_TFLOPS if achieved else None,
-                     "traffic": None,
-                     "flops_per_launch": upd_launch_flops,
-                     "avg_launch_us": upd["avg_us"]},
+                               "backward-Euler step (rates+RHS+Jacobian+block-tridiagonal "
+                               "factorisation+solve+update)",
+                   "S": S, "R": net.R, "N": N, "precision": "fp64", "dt": args.dt,
+                   "solver": "block cyclic reduction" if args.solver == "cr" else "block Thomas"},
+        "roofline": dict(rl),
+        "roofline_schur_gemm": gemm_rl,
         "kernels": kern,
     }
+    gcol.close()
+    if not args.skip_thomas and args.solver == "cr":
+        gt = xod.Column(gnet, col, precision=xod.XOD_FP64, stream=stream)
+        xod.xod_step(gt, args.dt)
+        k = max(2, args.steps // 5)
+        et = timed_steps(xod, torch, gt, args.dt, k)
+        line["thomas"] = {"value": k / et, "unit": "steps/s", "ms_per_step": 1e3 * et / k,
+                          "steps": k}
+        gt.close()
     if not args.skip_mixed:
-        line["mixed"] = bench_mixed(xod, torch, gnet, col, args)
+        line["mixed"] = bench_mixed(xod, torch, gnet, col, args, solver)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(net, col)
     print(json.dumps(line), flush=True)

@@ -65,6 +65,19 @@ typedef enum {
                      iterative refinement of every solve                       */
 } xod_precision;
 
+/* How a column's step system (block tridiagonal, Section 2.1) is factored.
+ * Both give the solution of the same block system; they differ only in the
+ * elimination order and hence in rounding. */
+typedef enum {
+  XOD_SOLVER_THOMAS = 0,  /* block Thomas: layers eliminated bottom to top,
+                             N dependent block inversions                     */
+  XOD_SOLVER_CR = 1       /* block cyclic reduction: odd-indexed layers of
+                             each level eliminated together, ceil(log2 N)+1
+                             dependent batched inversions plus dense block
+                             products on the matrix cores; needs about 2N
+                             further ld x ld blocks of workspace            */
+} xod_solver;
+
 enum { XOD_MAX_REAC = 3, XOD_MAX_PROD = 3 };
 enum { XOD_RT_BIMOL = 0, XOD_RT_TERMOL = 1, XOD_RT_PHOTO = 2 };
 
@@ -152,6 +165,14 @@ xod_status xod_column_state_ptr(xod_column *col, double **n_dev);
 xod_status xod_column_grid(const xod_column *col, double *ngas, double *tau,
                            double *dz, double *mix_time);
 
+/* Select the factorisation used by xod_step and
+ * xod_integrate_to_steady_state on this column (default XOD_SOLVER_THOMAS).
+ * XOD_SOLVER_CR allocates its workspace on first selection (XOD_ENOMEM if
+ * it does not fit).  The explicit-block calls xod_btd_factor / xod_btd_solve
+ * always use block Thomas.  The FP64 fallback of a mixed-precision solve is
+ * block Thomas as well. */
+xod_status xod_column_set_solver(xod_column *col, xod_solver solver);
+
 /* ---- hot-path calls (device pointers, asynchronous on the column stream) */
 
 /* Rate coefficients (Section 2.3): kf, kr [N*R].  Two-body:
@@ -176,7 +197,8 @@ xod_status xod_jacobian(xod_column *col, const double *kf, const double *kr,
 /* Block Thomas elimination in place (FP64).  For k = 0..N-1 the Schur
  * complement D'_k = B_k - diag(a_k) D'_{k-1}^{-1} diag(c_{k-1}) is inverted
  * by Gauss-Jordan elimination with partial pivoting (implicit row
- * pivoting, first maximum wins).  On return block k holds W_k and piv[k*ld+j]
+ * pivoting: the unused row of largest magnitude, compared to 42 mantissa
+ * bits, lowest row among equals).  On return block k holds W_k and piv[k*ld+j]
  * the row chosen as pivot for column j, such that
  *   (D'_k^{-1})[j][i] = W_k[piv[j]][q(i)],  q = inverse permutation of piv.
  * XOD_ESINGULAR (layer and column in xod_last_error) on a zero or

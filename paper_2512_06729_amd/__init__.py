@@ -39,6 +39,7 @@ XOD_OK, XOD_EINVAL, XOD_ENOMEM, XOD_ESINGULAR, XOD_ENOTCONVERGED, \
 STATUS_NAMES = ["OK", "EINVAL", "ENOMEM", "ESINGULAR", "ENOTCONVERGED",
                 "ENONFINITE", "EHIP", "ENOTIMPL", "EBUSY"]
 XOD_FP64, XOD_MIXED = 0, 1
+XOD_SOLVER_THOMAS, XOD_SOLVER_CR = 0, 1
 
 
 class XodError(RuntimeError):
@@ -105,6 +106,7 @@ _f = {
     "xod_column_set_state": _sig("xod_column_set_state", c_void_p, P_dbl, c_double, c_double),
     "xod_column_state_ptr": _sig("xod_column_state_ptr", c_void_p, ctypes.POINTER(c_void_p)),
     "xod_column_grid": _sig("xod_column_grid", c_void_p, P_dbl, P_dbl, P_dbl, P_dbl),
+    "xod_column_set_solver": _sig("xod_column_set_solver", c_void_p, c_int32),
     "xod_rates": _sig("xod_rates", c_void_p, c_void_p, c_void_p),
     "xod_rhs": _sig("xod_rhs", c_void_p, c_void_p, c_void_p, c_void_p, c_void_p),
     "xod_jacobian": _sig("xod_jacobian", c_void_p, c_void_p, c_void_p, c_void_p, c_double,
@@ -229,7 +231,8 @@ class Network:
 class Column:
     """One atmospheric column (xod_column): device state + workspace."""
 
-    def __init__(self, network, col, precision=XOD_FP64, stream=None, n0=None):
+    def __init__(self, network, col, precision=XOD_FP64, stream=None, n0=None,
+                 solver=XOD_SOLVER_THOMAS):
         self.network = network
         N = int(np.asarray(col.P_bar).shape[0])
         S = network.S
@@ -253,6 +256,12 @@ class Column:
         _check(_f["xod_column_create"](network.handle, ctypes.byref(prof), _ptr(n0, c_double),
                                        int(precision), c_void_p(stream or 0), ctypes.byref(h)))
         self.handle = h
+        if solver != XOD_SOLVER_THOMAS:
+            self.set_solver(solver)
+
+    def set_solver(self, solver):
+        """XOD_SOLVER_THOMAS or XOD_SOLVER_CR (xod_column_set_solver)."""
+        _check(_f["xod_column_set_solver"](self.handle, int(solver)))
 
     def state(self):
         n = np.empty((self.N, self.S))

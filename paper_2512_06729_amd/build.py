@@ -10,14 +10,15 @@ all device code.
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxod.so")
 ARCH = os.environ.get("XOD_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "k_chem.hip", "k_btd.hip", "k_mixed.hip", "k_step.hip",
-           "batch.cpp", "prof.cpp", "serve.cpp"]
+SOURCES = ["api.cpp", "k_chem.hip", "k_btd.hip", "k_mixed.hip", "k_step.hip", "k_cr.hip",
+           "cr.cpp", "batch.cpp", "prof.cpp", "serve.cpp"]
 
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
@@ -38,7 +39,7 @@ def build(verbose=False):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    jobs = []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         if not os.path.exists(path):
@@ -48,8 +49,11 @@ def build(verbose=False):
         cmd = [hipcc] + HIP_FLAGS + lang + ["-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        _run(cmd)
-        objs.append(obj)
+        jobs.append((cmd, obj))
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", "4"))))
+    with ThreadPoolExecutor(workers) as ex:
+        list(ex.map(lambda j: _run(j[0]), jobs))
+    objs = [obj for _, obj in jobs]
     tmp = LIB + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, LIB)

@@ -70,6 +70,7 @@ xod_status dupload(T **p, const T *host, size_t count) {
 }  // namespace
 
 #include "handles.h"
+#include "cr.h"
 
 namespace {
 
@@ -472,6 +473,29 @@ static xod_status check_flags(xod_column *col, const double *flags) {
   return XOD_OK;
 }
 
+extern "C" xod_status xod_column_set_solver(xod_column *col, xod_solver solver) {
+  XOD_CHECK(col, "xod_column_set_solver: null column");
+  XOD_CHECK(solver == XOD_SOLVER_THOMAS || solver == XOD_SOLVER_CR,
+            "xod_column_set_solver: unknown solver");
+  XOD_CHECK(!col->in_batch, "xod_column_set_solver: column belongs to a batch");
+  if (solver == XOD_SOLVER_CR) {
+    if (col->prec == XOD_FP64 && !col->cr64) {
+      std::unique_ptr<xod::CrPlan<double>> p(new xod::CrPlan<double>());
+      const xod_status st = p->build(col);
+      if (st != XOD_OK) return st == XOD_EHIP ? XOD_ENOMEM : st;
+      col->cr64 = p.release();
+    }
+    if (col->prec == XOD_MIXED && !col->cr32) {
+      std::unique_ptr<xod::CrPlan<float>> p(new xod::CrPlan<float>());
+      const xod_status st = p->build(col);
+      if (st != XOD_OK) return st == XOD_EHIP ? XOD_ENOMEM : st;
+      col->cr32 = p.release();
+    }
+  }
+  col->solver = solver;
+  return XOD_OK;
+}
+
 extern "C" xod_status xod_btd_factor(xod_column *col, double *B, const double *av,
                                      const double *cv, int32_t ld, int32_t *piv) {
   XOD_CHECK(col && B && av && cv && piv, "xod_btd_factor: null argument");
@@ -554,27 +578,43 @@ xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, do
   *resid = 0.0;
   XOD_HIP(launch_rates(one, 1, c->N, c->R, c->stream));
   XOD_HIP(launch_rhs(one, 1, c->N, c->R, c->S, c->stream));
+  const bool cr = c->solver == XOD_SOLVER_CR;
   if (c->prec == XOD_FP64) {
     XOD_HIP(launch_jacobian(one, 1, c->N, c->ld, false, c->stream));
-    XOD_HIP(launch_factor_fp64(one, 1, c->N, c->ld, c->stream));
+    if (cr)
+      XOD_TRY(c->cr64->factor(c));
+    else
+      XOD_HIP(launch_factor_fp64(one, 1, c->N, c->ld, c->stream));
     XOD_HIP(hipMemcpyAsync(c->x, c->f, (size_t)c->N * c->S * sizeof(double),
                            hipMemcpyDeviceToDevice, c->stream));
-    XOD_HIP(launch_solve_fp64(one, 1, c->N, c->ld, c->stream));
+    if (cr)
+      XOD_TRY(c->cr64->solve(c));
+    else
+      XOD_HIP(launch_solve_fp64(one, 1, c->N, c->ld, c->stream));
     return XOD_OK;
   }
   // Mixed precision: row-scaled FP32 Schur complements, FP64 refinement with a
   // matrix-free FP64 residual; FP64 refactorisation if refinement stalls.
   const size_t NSb = (size_t)c->N * c->S * sizeof(double);
   XOD_HIP(launch_jacobian(one, 1, c->N, c->ld, true, c->stream));
-  XOD_HIP(launch_factor_mixed(one, 1, c->N, c->ld, c->stream));
+  if (cr)
+    XOD_TRY(c->cr32->factor(c));
+  else
+    XOD_HIP(launch_factor_mixed(one, 1, c->N, c->ld, c->stream));
   XOD_HIP(launch_scale(one, 1, c->N, c->S, c->stream));
-  XOD_HIP(launch_solve_mixed(one, 1, c->N, c->ld, c->stream));
+  if (cr)
+    XOD_TRY(c->cr32->solve(c));
+  else
+    XOD_HIP(launch_solve_mixed(one, 1, c->N, c->ld, c->stream));
   XOD_HIP(hipMemcpyAsync(c->dx, c->x, NSb, hipMemcpyDeviceToDevice, c->stream));
   bool ok = false;
   double prev = 1e300, ratio = 1e300;
   for (int it = 1; it <= c->max_refine; ++it) {
     XOD_HIP(launch_residual(one, 1, c->N, c->S, c->R, c->dx, c->w, c->stream));
-    XOD_HIP(launch_solve_mixed(one, 1, c->N, c->ld, c->stream));
+    if (cr)
+      XOD_TRY(c->cr32->solve(c));
+    else
+      XOD_HIP(launch_solve_mixed(one, 1, c->N, c->ld, c->stream));
     XOD_HIP(launch_axpy_ratio(one, 1, c->N, c->dx, c->ratio, c->rmax, c->stream));
     XOD_HIP(hipMemcpyAsync(c->stats_host, c->rmax, sizeof(double), hipMemcpyDeviceToHost,
                            c->stream));

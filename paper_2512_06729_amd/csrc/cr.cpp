@@ -1,0 +1,299 @@
+// Block cyclic reduction of one column's block-tridiagonal step system.
+//
+// Level l (h = 2^l) works on the layers that are multiples of h.  Those with
+// k/h odd are eliminated: their diagonal blocks are inverted (all of them in
+// one batched Gauss-Jordan launch sequence) and folded into their kept
+// neighbours k -+ h:
+//   D_k <- D_k - A_k E_{k-h} C_{k-h} - C_k E_{k+h} A_{k+h}
+//   A_k <- -A_k E_{k-h} A_{k-h},   C_k <- -C_k E_{k+h} C_{k+h}
+//   g_k <- g_k - A_k E_{k-h} g_{k-h} - C_k E_{k+h} g_{k+h}
+// until layer 0 alone remains.  Back substitution runs the levels in reverse:
+//   x_k = E_k (g_k - A_k x_{k-h} - C_k x_{k+h})  for the eliminated layers.
+// The result is the solution of the same block system as block Thomas (both
+// are block Gaussian elimination, in different orders); the critical path is
+// ceil(log2 N) + 1 block inversions instead of N.
+//
+// Storage besides the blocks themselves: dense A / C blocks for the even
+// layers (levels >= 1 have dense couplings), the products T1 = A_k E_{k-h}
+// and T2 = C_k E_{k+h} of every level >= 1 (kept for the right-hand-side
+// reduction), and a padded solution vector.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <memory>
+#include <vector>
+
+#include "cr.h"
+
+namespace xod {
+
+template <class T>
+static T *col_blocks(xod_column *c);
+template <>
+double *col_blocks<double>(xod_column *c) { return c->B; }
+template <>
+float *col_blocks<float>(xod_column *c) { return c->Bf; }
+
+template <class T>
+template <class U>
+xod_status CrPlan<T>::upload(U **dst, const std::vector<U> &v) {
+  *dst = nullptr;
+  if (v.empty()) return XOD_OK;
+  XOD_HIP(hipMalloc((void **)dst, v.size() * sizeof(U)));
+  owned.push_back(*dst);
+  XOD_HIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(U), hipMemcpyHostToDevice));
+  return XOD_OK;
+}
+
+template <class T>
+CrPlan<T>::~CrPlan() {
+  for (void *p : owned) (void)hipFree(p);
+}
+
+std::vector<CrLevel> cr_levels(int N) {
+  std::vector<CrLevel> out;
+  std::vector<int> rem(N);
+  for (int k = 0; k < N; ++k) rem[k] = k;
+  int h = 1;
+  while (rem.size() > 1) {
+    CrLevel L;
+    L.h = h;
+    for (int k : rem) ((k / h) % 2 ? L.elim : L.kept).push_back(k);
+    rem = L.kept;
+    out.push_back(L);
+    h *= 2;
+  }
+  return out;
+}
+
+size_t cr_extra_blocks(int N) {
+  size_t n = 2 * (size_t)((N + 1) / 2);   // A and C of the even layers
+  for (const CrLevel &L : cr_levels(N)) {
+    if (L.h == 1) continue;
+    for (int k : L.kept) n += (k - L.h >= 0) + (k + L.h <= N - 1);
+  }
+  return n;
+}
+
+template <class T>
+xod_status CrPlan<T>::build(xod_column *c) {
+  N = c->N;
+  ld = c->ld;
+  levels = cr_levels(N);
+  const size_t bs = (size_t)ld * ld;
+  T *blk0 = col_blocks<T>(c);
+  auto blk = [&](int k) { return blk0 + (size_t)k * bs; };
+  auto pv = [&](int k) { return c->piv + (size_t)k * ld; };
+  auto rq = [&](int k) { return c->rstep + (size_t)k * ld; };
+  auto av = [&](int k) { return c->a + (size_t)k * ld; };
+  auto cv = [&](int k) { return c->c + (size_t)k * ld; };
+  auto gsv = [&](int k) { return c->gs + (size_t)k * ld; };
+
+  const size_t nslot = cr_extra_blocks(N);
+  XOD_HIP(hipMalloc((void **)&slots, std::max<size_t>(nslot, 1) * bs * sizeof(T)));
+  owned.push_back(slots);
+  XOD_HIP(hipMalloc((void **)&xs, (size_t)N * ld * sizeof(double)));
+  owned.push_back(xs);
+  auto aslot = [&](int k) { return slots + (size_t)(k / 2) * 2 * bs; };
+  auto cslot = [&](int k) { return slots + ((size_t)(k / 2) * 2 + 1) * bs; };
+  size_t next_t = 2 * (size_t)((N + 1) / 2);
+  auto xsv = [&](int k) { return xs + (size_t)k * ld; };
+
+  std::vector<MatRef<T>> inv;
+  std::vector<CrLevel0Op<T>> l0;
+  std::vector<GemmOp<T>> gops;
+  std::vector<MvOp<T>> mv;
+  const int nlev = (int)levels.size();
+  inv_off.assign(nlev + 1, 0);
+  inv_cnt.assign(nlev + 1, 0);
+  g1_off.assign(nlev, 0);
+  g1_cnt.assign(nlev, 0);
+  g2_off.assign(nlev, 0);
+  g2_cnt.assign(nlev, 0);
+  fwd_off.assign(nlev, 0);
+  fwd_cnt.assign(nlev, 0);
+  bwd1_off.assign(nlev, 0);
+  bwd1_cnt.assign(nlev, 0);
+  bwd2_off.assign(nlev, 0);
+  bwd2_cnt.assign(nlev, 0);
+  // T1 / T2 slot of (level, kept layer)
+  std::vector<std::vector<T *>> t1(nlev, std::vector<T *>(N, nullptr)),
+      t2(nlev, std::vector<T *>(N, nullptr));
+
+  for (int l = 0; l < nlev; ++l) {
+    const CrLevel &L = levels[l];
+    const int h = L.h;
+    inv_off[l] = (int)inv.size();
+    for (int k : L.elim) inv.push_back(MatRef<T>{blk(k), pv(k), rq(k), c->flag, k});
+    inv_cnt[l] = (int)L.elim.size();
+    if (l == 0) {
+      for (int k : L.kept) {
+        const bool hl = k - 1 >= 0, hr = k + 1 <= N - 1;
+        if (!hl && !hr) continue;
+        CrLevel0Op<T> o{};
+        o.D = blk(k);
+        o.A = (k - 2 >= 0) ? aslot(k) : nullptr;
+        o.C = (k + 2 <= N - 1) ? cslot(k) : nullptr;
+        o.ak = av(k);
+        o.ck = cv(k);
+        if (hl) {
+          o.Wl = blk(k - 1);
+          o.pl = pv(k - 1);
+          o.ql = rq(k - 1);
+          o.al = av(k - 1);
+          o.cl = cv(k - 1);
+        }
+        if (hr) {
+          o.Wr = blk(k + 1);
+          o.pr = pv(k + 1);
+          o.qr = rq(k + 1);
+          o.ar = av(k + 1);
+          o.cr = cv(k + 1);
+        }
+        l0.push_back(o);
+      }
+    } else {
+      g1_off[l] = (int)gops.size();
+      for (int k : L.kept) {
+        if (k - h >= 0) {
+          t1[l][k] = slots + next_t++ * bs;
+          gops.push_back(GemmOp<T>{aslot(k), blk(k - h), pv(k - h), nullptr, nullptr, nullptr,
+                                   t1[l][k], 1.0, 0});
+        }
+        if (k + h <= N - 1) {
+          t2[l][k] = slots + next_t++ * bs;
+          gops.push_back(GemmOp<T>{cslot(k), blk(k + h), pv(k + h), nullptr, nullptr, nullptr,
+                                   t2[l][k], 1.0, 0});
+        }
+      }
+      g1_cnt[l] = (int)gops.size() - g1_off[l];
+      g2_off[l] = (int)gops.size();
+      for (int k : L.kept) {
+        const int kl = k - h, kr = k + h;
+        const bool hl = kl >= 0, hr = kr <= N - 1;
+        if (hl && hr)
+          gops.push_back(GemmOp<T>{t1[l][k], cslot(kl), pv(kl), t2[l][k], aslot(kr), pv(kr),
+                                   blk(k), -1.0, 1});
+        else if (hl)
+          gops.push_back(GemmOp<T>{t1[l][k], cslot(kl), pv(kl), nullptr, nullptr, nullptr, blk(k),
+                                   -1.0, 1});
+        else if (hr)
+          gops.push_back(GemmOp<T>{t2[l][k], aslot(kr), pv(kr), nullptr, nullptr, nullptr, blk(k),
+                                   -1.0, 1});
+        if (k - 2 * h >= 0)
+          gops.push_back(GemmOp<T>{t1[l][k], aslot(kl), pv(kl), nullptr, nullptr, nullptr,
+                                   aslot(k), -1.0, 0});
+        if (k + 2 * h <= N - 1)
+          gops.push_back(GemmOp<T>{t2[l][k], cslot(kr), pv(kr), nullptr, nullptr, nullptr,
+                                   cslot(k), -1.0, 0});
+      }
+      g2_cnt[l] = (int)gops.size() - g2_off[l];
+    }
+    // right-hand-side reduction of this level
+    fwd_off[l] = (int)mv.size();
+    for (int k : L.kept) {
+      const int kl = k - h, kr = k + h;
+      MvOp<T> o{};
+      o.b = gsv(k);
+      o.y = gsv(k);
+      if (kl >= 0) {
+        o.t[o.nterm++] = (l == 0)
+            ? MvTerm<T>{blk(kl), pv(kl), pv(kl), gsv(kl), av(k), -1.0}
+            : MvTerm<T>{t1[l][k], nullptr, pv(kl), gsv(kl), nullptr, -1.0};
+      }
+      if (kr <= N - 1) {
+        o.t[o.nterm++] = (l == 0)
+            ? MvTerm<T>{blk(kr), pv(kr), pv(kr), gsv(kr), cv(k), -1.0}
+            : MvTerm<T>{t2[l][k], nullptr, pv(kr), gsv(kr), nullptr, -1.0};
+      }
+      if (o.nterm) mv.push_back(o);
+    }
+    fwd_cnt[l] = (int)mv.size() - fwd_off[l];
+  }
+  // root
+  inv_off[nlev] = (int)inv.size();
+  inv.push_back(MatRef<T>{blk(0), pv(0), rq(0), c->flag, 0});
+  inv_cnt[nlev] = 1;
+  root_off = (int)mv.size();
+  {
+    MvOp<T> o{};
+    o.y = xsv(0);
+    o.t[o.nterm++] = MvTerm<T>{blk(0), pv(0), pv(0), gsv(0), nullptr, 1.0};
+    mv.push_back(o);
+  }
+  // back substitution, per level
+  for (int l = 0; l < nlev; ++l) {
+    const CrLevel &L = levels[l];
+    const int h = L.h;
+    bwd1_off[l] = (int)mv.size();
+    for (int k : L.elim) {
+      MvOp<T> o{};
+      o.b = gsv(k);
+      o.y = gsv(k);
+      o.t[o.nterm++] = (l == 0) ? MvTerm<T>{nullptr, nullptr, nullptr, xsv(k - 1), av(k), -1.0}
+                                : MvTerm<T>{aslot(k), nullptr, nullptr, xsv(k - h), nullptr, -1.0};
+      if (k + h <= N - 1)
+        o.t[o.nterm++] = (l == 0)
+            ? MvTerm<T>{nullptr, nullptr, nullptr, xsv(k + 1), cv(k), -1.0}
+            : MvTerm<T>{cslot(k), nullptr, nullptr, xsv(k + h), nullptr, -1.0};
+      mv.push_back(o);
+    }
+    bwd1_cnt[l] = (int)mv.size() - bwd1_off[l];
+    bwd2_off[l] = (int)mv.size();
+    for (int k : L.elim) {
+      MvOp<T> o{};
+      o.y = xsv(k);
+      o.t[o.nterm++] = MvTerm<T>{blk(k), pv(k), pv(k), gsv(k), nullptr, 1.0};
+      mv.push_back(o);
+    }
+    bwd2_cnt[l] = (int)mv.size() - bwd2_off[l];
+  }
+  l0_cnt = (int)l0.size();
+  XOD_TRY(upload(&d_inv, inv));
+  XOD_TRY(upload(&d_l0, l0));
+  XOD_TRY(upload(&d_g, gops));
+  XOD_TRY(upload(&d_mv, mv));
+  return XOD_OK;
+}
+
+template <class T>
+xod_status CrPlan<T>::factor(xod_column *c) {
+  hipStream_t s = c->stream;
+  XOD_HIP(launch_cr_reset(c->rstep, (size_t)N * ld, c->flag, s));
+  const int nlev = (int)levels.size();
+  for (int l = 0; l < nlev; ++l) {
+    XOD_HIP(launch_invert_list<T>(d_inv + inv_off[l], inv_cnt[l], ld, s));
+    if (l == 0) {
+      XOD_HIP(launch_cr_level0<T>(d_l0, l0_cnt, ld, s));
+    } else {
+      XOD_HIP(launch_gemm<T>(d_g + g1_off[l], g1_cnt[l], ld, s));
+      XOD_HIP(launch_gemm<T>(d_g + g2_off[l], g2_cnt[l], ld, s));
+    }
+  }
+  XOD_HIP(launch_invert_list<T>(d_inv + inv_off[nlev], 1, ld, s));
+  return XOD_OK;
+}
+
+template <class T>
+xod_status CrPlan<T>::solve(xod_column *c) {
+  hipStream_t s = c->stream;
+  XOD_HIP(launch_pad_copy(c->x, c->gs, N, c->S, ld, true, s));
+  const int nlev = (int)levels.size();
+  for (int l = 0; l < nlev; ++l) XOD_HIP(launch_mv<T>(d_mv + fwd_off[l], fwd_cnt[l], ld, s));
+  XOD_HIP(launch_mv<T>(d_mv + root_off, 1, ld, s));
+  for (int l = nlev - 1; l >= 0; --l) {
+    XOD_HIP(launch_mv<T>(d_mv + bwd1_off[l], bwd1_cnt[l], ld, s));
+    XOD_HIP(launch_mv<T>(d_mv + bwd2_off[l], bwd2_cnt[l], ld, s));
+  }
+  XOD_HIP(launch_pad_copy(xs, c->x, N, c->S, ld, false, s));
+  return XOD_OK;
+}
+
+template struct CrPlan<double>;
+template struct CrPlan<float>;
+
+void cr_destroy(CrPlan<double> *p) { delete p; }
+void cr_destroy(CrPlan<float> *p) { delete p; }
+
+}  // namespace xod

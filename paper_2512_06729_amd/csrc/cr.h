@@ -1,0 +1,56 @@
+// Block cyclic reduction plan of one column (host side).
+#pragma once
+
+#include <vector>
+
+#include "handles.h"
+
+#ifndef XOD_TRY
+#define XOD_TRY(expr)            \
+  do {                           \
+    xod_status s_ = (expr);      \
+    if (s_ != XOD_OK) return s_; \
+  } while (0)
+#endif
+
+namespace xod {
+
+struct CrLevel {
+  int h;                       // layer stride of the level
+  std::vector<int> elim, kept; // layers eliminated / kept at this level
+};
+
+// Levels of the reduction of N layers (empty for N = 1); layer 0 is the root.
+std::vector<CrLevel> cr_levels(int N);
+// Dense blocks the reduction needs besides the N diagonal blocks.
+size_t cr_extra_blocks(int N);
+
+template <class T>
+struct CrPlan {
+  int N = 0, ld = 0;
+  std::vector<CrLevel> levels;
+  std::vector<void *> owned;
+  T *slots = nullptr;    // dense A / C blocks of even layers, then T1 / T2 products
+  double *xs = nullptr;  // padded solution [N*ld]
+  MatRef<T> *d_inv = nullptr;
+  CrLevel0Op<T> *d_l0 = nullptr;
+  GemmOp<T> *d_g = nullptr;
+  MvOp<T> *d_mv = nullptr;
+  int l0_cnt = 0, root_off = 0;
+  std::vector<int> inv_off, inv_cnt, g1_off, g1_cnt, g2_off, g2_cnt;
+  std::vector<int> fwd_off, fwd_cnt, bwd1_off, bwd1_cnt, bwd2_off, bwd2_cnt;
+
+  ~CrPlan();
+  // Device descriptors for the column's buffers (blocks, couplings, pivots).
+  xod_status build(xod_column *c);
+  // Factor the blocks in place (enqueued on the column's stream).
+  xod_status factor(xod_column *c);
+  // Solve with the factors: c->x [N*S] in, solution out.
+  xod_status solve(xod_column *c);
+
+ private:
+  template <class U>
+  xod_status upload(U **dst, const std::vector<U> &v);
+};
+
+}  // namespace xod

@@ -5,6 +5,12 @@
 
 #include "xod_internal.h"
 
+namespace xod {
+template <class T> struct CrPlan;
+void cr_destroy(CrPlan<double> *p);
+void cr_destroy(CrPlan<float> *p);
+}  // namespace xod
+
 using xod::ColArgs;
 using xod::RedArgs;
 using xod::UpdArgs;
@@ -50,7 +56,12 @@ struct xod_column {
   RedArgs *red_dev = nullptr;
   double t = 0.0, dt = 0.0;
   bool in_batch = false;
+  xod_solver solver = XOD_SOLVER_THOMAS;
+  xod::CrPlan<double> *cr64 = nullptr;   // block cyclic reduction (FP64 column)
+  xod::CrPlan<float> *cr32 = nullptr;    // block cyclic reduction (mixed column)
   ~xod_column() {
+    xod::cr_destroy(cr64);
+    xod::cr_destroy(cr32);
     if (stats_host) (void)hipHostFree(stats_host);
     for (void *p : owned) (void)hipFree(p);
   }

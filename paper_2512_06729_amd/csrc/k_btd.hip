@@ -11,13 +11,15 @@
 //   k_prologue   D'_k from B_k and the previous layer's inverse (gather)
 //   per panel of kNB columns:
 //     k_panel    one work-group factors the ld x kNB panel in registers
-//                (argmax over unused rows, first maximum wins)
+//                (pivot: largest magnitude among unused rows, compared to
+//                42 mantissa bits, lowest row among equals)
 //     k_update   Schur update of every other column strip:
 //                C <- mask * C + W[:, J] U,  U = W[piv[J], strip]
 //                (rows that became pivots in this panel are replaced, the
 //                others accumulate), FP64 MFMA 16x16x4 or VALU FMA.
 // The solve is a chain of matrix-vector products with the stored inverses.
 #include "xod_internal.h"
+#include "mfma.h"
 
 #include <climits>
 
@@ -68,27 +70,57 @@ __global__ void __launch_bounds__(256) k_prologue(Acc acc, int k) {
 }
 
 // ---------------------------------------------------------------------------
-// Panel factorisation: Gauss-Jordan on the ld x kNB panel of one Schur
-// complement, with implicit partial pivoting.
+// The blocks a Gauss-Jordan launch works on.  Block Thomas: layer k of each
+// column in the launch (work-group index b = column).  Lists: entry base + b
+// of a device array of MatRef (the layers of one cyclic-reduction level).
+template <class Acc, class T>
+struct ThomasMats {
+  Acc acc;
+  __device__ __forceinline__ bool operator()(int b, int k, MatRef<T> &m) const {
+    const ColArgs &c = acc(b);
+    if (k >= c.N) return false;
+    const size_t ld = c.ld;
+    m.W = blocks<T>(c) + (size_t)k * ld * ld;
+    m.piv = c.piv + (size_t)k * ld;
+    m.rstep = c.rstep + (size_t)k * ld;
+    m.flag = c.flag;
+    m.id = k;
+    return true;
+  }
+};
+template <class T>
+struct ListMats {
+  const MatRef<T> *list;
+  __device__ __forceinline__ bool operator()(int b, int base, MatRef<T> &m) const {
+    m = list[base + b];
+    return true;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Panel factorisation: Gauss-Jordan on the ld x kNB panel of one block, with
+// implicit partial pivoting.
 //
-// Four waves (one per SIMD) of 64 lanes; thread t owns the R contiguous rows
-// R*t .. R*t+R-1 (R = ceil(ld/256) <= 4), each held as a 32-wide register
-// vector indexed by the uniform column number.  Row order (thread, chunk
-// index) is the global row order, so "first maximum wins" is exact: the local
-// pick keeps the lowest chunk index, the ballot the lowest lane, the cross-wave
-// pick the lowest wave.
-//
-// One barrier per column: each wave finds its best candidate with a DPP max
-// and a ballot and publishes (value, row) and the row's panel values in LDS
-// (double-buffered by column parity).  The loop touches no global memory.
-constexpr int kPanelRows = 2;      // rows per thread (kept in registers)
-constexpr int kPanelWaves = kMaxLd / (64 * kPanelRows);   // up to 8 waves
-constexpr int kGroup = 8;          // columns per unrolled group
+// Thread t owns rows R*t .. R*t+R-1 as register vectors (64*ceil(ld/128)
+// threads).  Per column, one barrier:
+//   - every unused row forms a key: |x| with its 10 lowest mantissa bits
+//     replaced by (1023 - row), so the largest key is the largest magnitude
+//     (to 42 mantissa bits) and, among equals, the lowest row;
+//   - a DPP max gives each wave's best key; the owning lane publishes its
+//     row in LDS (double-buffered by column parity), lane 0 the key;
+//   - after the barrier, 16 lanes read the wave keys and a second DPP max
+//     gives the pivot row, whose values every thread reads from LDS.
+// Pivot rows are kept unscaled while the panel runs (the elimination update
+// is linear in each row, so scaling commutes with it): the pivot row's own
+// column is set to 1 and the row is multiplied by its reciprocal pivot when
+// the panel is written back.  The loop touches no global memory.
+constexpr int kPanelRows = 2;                               // rows per thread
+constexpr int kPanelWaves = kMaxLd / (64 * kPanelRows);     // up to 8 waves
+constexpr int kGroup = 8;                                   // columns per unrolled group
 
 struct PanelShared {
   double cand[2][kPanelWaves][kNB];
-  double val[2][kPanelWaves];
-  int idx[2][kPanelWaves];
+  double key[2][16];
   int piv[kNB];
   int bad;
 };
@@ -100,65 +132,74 @@ __device__ __forceinline__ double dpp_move(double v) {
   return __hiloint2double(hi, lo);
 }
 
-// Maximum over the 64 lanes (quad_perm, row_ror, row_bcast:15/31), read from
-// the last lane and returned to every lane.
-__device__ __forceinline__ double wave_max(double v) {
-  v = fmax(v, dpp_move<0xb1>(v));    // quad_perm [1,0,3,2]
-  v = fmax(v, dpp_move<0x4e>(v));    // quad_perm [2,3,0,1]
-  v = fmax(v, dpp_move<0x124>(v));   // row_ror:4
-  v = fmax(v, dpp_move<0x128>(v));   // row_ror:8
-  v = fmax(v, dpp_move<0x142>(v));   // row_bcast:15
-  v = fmax(v, dpp_move<0x143>(v));   // row_bcast:31
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
   return __hiloint2double(hi, lo);
+}
+
+// Maximum over each row of 16 lanes (quad_perm [1,0,3,2], [2,3,0,1],
+// row_ror:4, row_ror:8): every lane of the row holds it afterwards.
+__device__ __forceinline__ double row16_max(double v) {
+  v = fmax(v, dpp_move<0xb1>(v));
+  v = fmax(v, dpp_move<0x4e>(v));
+  v = fmax(v, dpp_move<0x124>(v));
+  v = fmax(v, dpp_move<0x128>(v));
+  return v;
+}
+
+// Maximum over the 64 lanes (row maxima, then row_bcast:15 / row_bcast:31),
+// read from the last lane.
+__device__ __forceinline__ double wave_max(double v) {
+  v = row16_max(v);
+  v = fmax(v, dpp_move<0x142>(v));
+  v = fmax(v, dpp_move<0x143>(v));
+  return read_lane(v, 63);
+}
+
+__device__ __forceinline__ double pivot_key(double x, int row) {
+  const double a = fmin(fabs(x), 1e300);   // NaN / Inf -> 1e300: chosen, then reported
+  unsigned long long b = (unsigned long long)__double_as_longlong(a);
+  b = (b & ~1023ull) | (unsigned long long)(1023 - row);
+  return __longlong_as_double((long long)b);
+}
+__device__ __forceinline__ int key_row(double k) {
+  return 1023 - (int)((unsigned long long)__double_as_longlong(k) & 1023ull);
 }
 
 // One Gauss-Jordan column at static position U of the (rotated) rows.
 template <int R, int U>
-__device__ __forceinline__ void gj_col(double (&row)[R][kNB], bool (&used)[R], int (&mystep)[R],
-                                       PanelShared &sh, int t, int ld, int jcol, int j0) {
+__device__ __forceinline__ void gj_col(double (&row)[R][kNB], double (&sig)[R], bool (&used)[R],
+                                       int (&mystep)[R], PanelShared &sh, int t, int jcol,
+                                       int j0) {
   const int lane = t & 63, wid = t >> 6;
   const int buf = jcol & 1;
-  // best candidate of this thread (lowest chunk index among equals)
-  double v = -1.0;
+  double key = 0.0;
   int ib = 0;
 #pragma unroll
   for (int i = 0; i < R; ++i) {
-    if (!used[i]) {
-      const double av = fabs(row[i][U]);
-      const double a2 = (av == av) ? av : -2.0;   // NaN never wins (flagged below)
-      if (a2 > v) { v = a2; ib = i; }
-    }
+    const double k = used[i] ? 0.0 : pivot_key(row[i][U], R * t + i);
+    if (k > key) { key = k; ib = i; }
   }
-  const double m = wave_max(v);
-  const unsigned long long hit = __ballot(v == m);
-  const int first = __ffsll((long long)hit) - 1;
-  if (lane == first) {
+  const double m = wave_max(key);
+  if (m > 0.0 && key == m) {
 #pragma unroll
     for (int i = 0; i < R; ++i)
       if (i == ib) {
 #pragma unroll
         for (int q = 0; q < kNB; ++q) sh.cand[buf][wid][q] = row[i][q];
       }
-    sh.val[buf][wid] = m;
-    sh.idx[buf][wid] = m >= 0.0 ? R * t + ib : INT_MAX;
   }
+  if (lane == 0) sh.key[buf][wid] = m;
   __syncthreads();
   const int nw = blockDim.x >> 6;
-  double bv = sh.val[buf][0];
-  int wb = 0;
-#pragma unroll
-  for (int q = 1; q < kPanelWaves; ++q) {
-    const double ov = q < nw ? sh.val[buf][q] : -3.0;
-    if (ov > bv) { bv = ov; wb = q; }                // ties keep the lower wave
-  }
-  const int r = sh.idx[buf][wb];
-  if (r >= ld) {                                       // no candidate row at all
+  const double M = read_lane(row16_max(lane < nw ? sh.key[buf][lane & 15] : 0.0), 0);
+  if (!(M > 0.0)) {                                   // no unused row left
     if (t == 0) { sh.piv[jcol] = 0; if (sh.bad < 0) sh.bad = jcol; }
     return;
   }
-  const double *prow = sh.cand[buf][wb];
+  const int r = key_row(M);
+  const double *prow = sh.cand[buf][r / (64 * R)];
   double pv = prow[U];
   if (!(fabs(pv) > 0.0) || !isfinite(pv)) {
     if (t == 0 && sh.bad < 0) sh.bad = jcol;
@@ -167,47 +208,45 @@ __device__ __forceinline__ void gj_col(double (&row)[R][kNB], bool (&used)[R], i
   const double npiv = 1.0 / pv;
   double fm[R];
 #pragma unroll
-  for (int i = 0; i < R; ++i) fm[i] = row[i][U] * npiv;
+  for (int i = 0; i < R; ++i) fm[i] = (R * t + i == r) ? 0.0 : row[i][U] * npiv;
 #pragma unroll
   for (int q = 0; q < kNB; ++q) {
+    if (q == U) continue;
     const double pq = prow[q];
 #pragma unroll
-    for (int i = 0; i < R; ++i) row[i][q] = (R * t + i == r) ? pq * npiv : row[i][q] - fm[i] * pq;
+    for (int i = 0; i < R; ++i) row[i][q] = fma(-fm[i], pq, row[i][q]);
   }
 #pragma unroll
   for (int i = 0; i < R; ++i) {
-    if (R * t + i == r) {
-      row[i][U] = npiv;
+    const bool me = (R * t + i == r);
+    row[i][U] = me ? 1.0 : -fm[i];
+    if (me) {
       used[i] = true;
+      sig[i] = npiv;
       mystep[i] = j0 + jcol;
-    } else {
-      row[i][U] = -fm[i];
     }
   }
   if (t == 0) sh.piv[jcol] = r;
 }
 
 template <int R, int U>
-__device__ __forceinline__ void gj_group(double (&row)[R][kNB], bool (&used)[R],
-                                         int (&mystep)[R], PanelShared &sh, int t, int ld,
-                                         int jbase, int j0) {
-  gj_col<R, U>(row, used, mystep, sh, t, ld, jbase + U, j0);
-  if constexpr (U + 1 < kGroup) gj_group<R, U + 1>(row, used, mystep, sh, t, ld, jbase, j0);
+__device__ __forceinline__ void gj_group(double (&row)[R][kNB], double (&sig)[R],
+                                         bool (&used)[R], int (&mystep)[R], PanelShared &sh,
+                                         int t, int jbase, int j0) {
+  gj_col<R, U>(row, sig, used, mystep, sh, t, jbase + U, j0);
+  if constexpr (U + 1 < kGroup) gj_group<R, U + 1>(row, sig, used, mystep, sh, t, jbase, j0);
 }
 
-template <class Acc, class T, int R>
-__global__ void __launch_bounds__(64 * kPanelWaves) k_panel(Acc acc, int k, int p) {
-  const ColArgs &c = acc(blockIdx.x);
-  if (k >= c.N) return;
-  const int ld = c.ld;
+template <class MA, class T, int R>
+__global__ void __launch_bounds__(64 * kPanelWaves) k_panel(MA ma, int k, int p, int ld) {
+  MatRef<T> mat;
+  if (!ma(blockIdx.x, k, mat)) return;
   const int t = threadIdx.x;
-  T *W = blocks<T>(c) + (size_t)k * ld * ld;
-  int *rstep = c.rstep + (size_t)k * ld;
-  int *piv = c.piv + (size_t)k * ld;
+  T *W = mat.W;
   const int j0 = p * kNB;
   __shared__ PanelShared sh;
 
-  double row[R][kNB];
+  double row[R][kNB], sig[R];
   bool used[R];
   int mystep[R];
 #pragma unroll
@@ -215,11 +254,12 @@ __global__ void __launch_bounds__(64 * kPanelWaves) k_panel(Acc acc, int k, int 
     const int g = R * t + i;
     used[i] = true;
     mystep[i] = INT_MAX;
+    sig[i] = 1.0;
     if (g < ld) {
       const T *src = W + (size_t)g * ld + j0;
 #pragma unroll
       for (int q = 0; q < kNB; ++q) row[i][q] = (double)src[q];
-      mystep[i] = rstep[g];
+      mystep[i] = mat.rstep[g];
       used[i] = mystep[i] < j0;
     } else {
 #pragma unroll
@@ -228,12 +268,12 @@ __global__ void __launch_bounds__(64 * kPanelWaves) k_panel(Acc acc, int k, int 
   }
   if (t == 0) sh.bad = -1;
 
-  // Columns in groups of kGroup: the group's columns sit at static positions
-  // 0..kGroup-1; afterwards every row rotates left by kGroup, so after the
-  // last group the rows are back in panel order.
+  // Columns in groups of kGroup at static positions 0..kGroup-1; afterwards
+  // every row rotates left by kGroup, so after the last group the rows are
+  // back in panel order.
 #pragma unroll 1
   for (int jb = 0; jb < kNB; jb += kGroup) {
-    gj_group<R, 0>(row, used, mystep, sh, t, ld, jb, j0);
+    gj_group<R, 0>(row, sig, used, mystep, sh, t, jb, j0);
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       double tmp[kGroup];
@@ -246,65 +286,47 @@ __global__ void __launch_bounds__(64 * kPanelWaves) k_panel(Acc acc, int k, int 
     }
   }
   __syncthreads();
-  if (t < kNB) piv[j0 + t] = sh.piv[t];
-  if (t == 0 && sh.bad >= 0 && atomicCAS(c.flag, -1, k) == -1) c.flag[1] = j0 + sh.bad;
+  if (t < kNB) mat.piv[j0 + t] = sh.piv[t];
+  if (t == 0 && sh.bad >= 0 && atomicCAS(mat.flag, -1, mat.id) == -1) mat.flag[1] = j0 + sh.bad;
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     const int g = R * t + i;
     if (g < ld) {
       T *dst = W + (size_t)g * ld + j0;
 #pragma unroll
-      for (int q = 0; q < kNB; ++q) dst[q] = (T)row[i][q];
-      rstep[g] = mystep[i];
+      for (int q = 0; q < kNB; ++q) dst[q] = (T)(row[i][q] * sig[i]);
+      mat.rstep[g] = mystep[i];
     }
   }
 }
 
-template <class Acc, class T>
-void launch_panel(const Acc &acc, int ncols, int ld, int k, int p, hipStream_t s) {
+template <class MA, class T>
+void launch_panel(const MA &ma, int nmat, int ld, int k, int p, hipStream_t s) {
   const int threads = 64 * ((ld + 64 * kPanelRows - 1) / (64 * kPanelRows));
-  hipLaunchKernelGGL((k_panel<Acc, T, kPanelRows>), dim3(ncols), dim3(threads), 0, s, acc, k, p);
+  hipLaunchKernelGGL((k_panel<MA, T, kPanelRows>), dim3(nmat), dim3(threads), 0, s, ma, k, p,
+                     ld);
 }
 
 // ---------------------------------------------------------------------------
 // Schur update of the column strips outside the panel.  One work-group per
-// (strip, column); each owns all ld rows of its strip, so reading the pivot
+// (strip, block); each owns all ld rows of its strip, so reading the pivot
 // rows (U) before overwriting them is race-free.
-typedef double double4_t __attribute__((ext_vector_type(4)));
-typedef float float4_t __attribute__((ext_vector_type(4)));
-
-// One 16x16 output tile += A[16 x kNB] U[kNB x 16] on the matrix cores.
-// v_mfma_f64_16x16x4f64: lane holds D[l/16 + 4i][l%16];
-// v_mfma_f32_16x16x4f32: lane holds D[4(l/16) + i][l%16] (checked on gfx950).
-__device__ __forceinline__ int mfma_row(double, int lane, int i) { return (lane >> 4) + 4 * i; }
-__device__ __forceinline__ int mfma_row(float, int lane, int i) { return 4 * (lane >> 4) + i; }
-__device__ __forceinline__ double4_t mfma16(double a, double b, double4_t c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ float4_t mfma16(float a, float b, float4_t c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-template <class T> struct Vec4;
-template <> struct Vec4<double> { typedef double4_t type; };
-template <> struct Vec4<float> { typedef float4_t type; };
-
 constexpr int kUpdThreads = 1024;   // 16 waves share the row tiles of a strip
 
-template <class Acc, class T, bool kMfma>
-__global__ void __launch_bounds__(kUpdThreads) k_update(Acc acc, int k, int p) {
-  const ColArgs &c = acc(blockIdx.y);
-  if (k >= c.N) return;
-  const int ld = c.ld;
+template <class MA, class T, bool kMfma>
+__global__ void __launch_bounds__(kUpdThreads) k_update(MA ma, int k, int p, int ld) {
+  MatRef<T> mat;
+  if (!ma(blockIdx.y, k, mat)) return;
   const int j0 = p * kNB;
   // Strip s is always work-group s of the launch (all ld/16 strips are
   // launched, the panel's own strips return), so a strip stays on the same
-  // XCD for every panel and layer.
+  // XCD for every panel.
   const int s = blockIdx.x;
   const int c0 = s * kStrip;
   if (c0 >= ld || (c0 >= j0 && c0 < j0 + kNB)) return;
-  T *W = blocks<T>(c) + (size_t)k * ld * ld;
-  const int *piv = c.piv + (size_t)k * ld + j0;
-  const int *rstep = c.rstep + (size_t)k * ld;
+  T *W = mat.W;
+  const int *piv = mat.piv + j0;
+  const int *rstep = mat.rstep;
 
   __shared__ T sU[kNB][kStrip];               // U = W[piv[J], strip]
   const int t = threadIdx.x;
@@ -379,12 +401,23 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(Acc acc, int k, int p) {
   }
 }
 
+template <class MA, class T>
+void launch_update(const MA &ma, int nmat, int ld, int k, int p, hipStream_t s) {
+  const int nupd = ld / kStrip;   // every strip; the panel's own return
+  if (options().gemm_mfma)
+    hipLaunchKernelGGL((k_update<MA, T, true>), dim3(nupd, nmat), dim3(kUpdThreads), 0, s, ma, k,
+                       p, ld);
+  else
+    hipLaunchKernelGGL((k_update<MA, T, false>), dim3(nupd, nmat), dim3(kUpdThreads), 0, s, ma,
+                       k, p, ld);
+}
+
 template <class Acc, class T>
 hipError_t launch_factor(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s) {
   if (maxN <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_rstep_init<Acc>, dim3(64, ncols), dim3(256), 0, s, acc, maxN);
   const int npanel = ld / kNB;
-  const int nupd = ld / kStrip;   // every strip; the panel's own return
+  const ThomasMats<Acc, T> ma{acc};
   for (int k = 0; k < maxN; ++k) {
     const bool prof = prof_layer(k);
     if (k > 0) {
@@ -394,22 +427,34 @@ hipError_t launch_factor(const Acc &acc, int ncols, int maxN, int ld, hipStream_
     }
     for (int p = 0; p < npanel; ++p) {
       if (prof) prof_begin(kProfPanel, s);
-      launch_panel<Acc, T>(acc, ncols, ld, k, p, s);
+      launch_panel<ThomasMats<Acc, T>, T>(ma, ncols, ld, k, p, s);
       if (prof) prof_end(kProfPanel, s);
-      if (nupd > 0) {
-        if (prof) prof_begin(kProfUpdate, s);
-        if (options().gemm_mfma)
-          hipLaunchKernelGGL((k_update<Acc, T, true>), dim3(nupd, ncols), dim3(kUpdThreads), 0, s,
-                             acc, k, p);
-        else
-          hipLaunchKernelGGL((k_update<Acc, T, false>), dim3(nupd, ncols), dim3(kUpdThreads), 0, s,
-                             acc, k, p);
-        if (prof) prof_end(kProfUpdate, s);
-      }
+      if (prof) prof_begin(kProfUpdate, s);
+      launch_update<ThomasMats<Acc, T>, T>(ma, ncols, ld, k, p, s);
+      if (prof) prof_end(kProfUpdate, s);
     }
   }
   return hipGetLastError();
 }
+
+template <class T>
+hipError_t launch_invert_list(const MatRef<T> *dlist, int count, int ld, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const ListMats<T> ma{dlist};
+  const int npanel = ld / kNB;
+  const bool prof = options().profile != 0;
+  for (int p = 0; p < npanel; ++p) {
+    if (prof) prof_begin(kProfPanel, s);
+    launch_panel<ListMats<T>, T>(ma, count, ld, 0, p, s);
+    if (prof) prof_end(kProfPanel, s);
+    if (prof) prof_begin(kProfUpdate, s);
+    launch_update<ListMats<T>, T>(ma, count, ld, 0, p, s);
+    if (prof) prof_end(kProfUpdate, s);
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_invert_list<double>(const MatRef<double> *, int, int, hipStream_t);
+template hipError_t launch_invert_list<float>(const MatRef<float> *, int, int, hipStream_t);
 
 template <class Acc>
 hipError_t launch_factor_fp64(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s) {

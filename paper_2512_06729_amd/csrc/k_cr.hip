@@ -1,0 +1,228 @@
+// Kernels of block cyclic reduction for the block-tridiagonal step system
+//   A_k x_{k-h} + D_k x_k + C_k x_{k+h} = g_k
+// (level 0: h = 1, A_k = diag(a_k), C_k = diag(c_k), D_k = B_k).
+//
+//   k_gemm       batched dense block products on the matrix cores (the
+//                Schur terms A_k E C of levels >= 1), FP64 or FP32 MFMA
+//   k_cr_level0  the level-0 Schur terms, where the couplings are diagonal
+//                and every term is an elementwise product with E
+//   k_mv         batched matrix-vector terms of the reduction / substitution
+//   k_pad_copy   compact [N*S] <-> padded [N*ld] vectors
+//
+// Inverses come from the Gauss-Jordan kernels in their permuted form,
+// E[i][j] = W[piv[i]][rstep[j]].  A product X E is formed as X (W[piv,:])
+// with its columns in pivot-step order; later products with that result
+// gather the rows of their right operand by piv instead of permuting back.
+#include "xod_internal.h"
+#include "mfma.h"
+
+#include <climits>
+
+namespace xod {
+
+// Permutation entries index rows / columns of an ld x ld block; a complete
+// inversion leaves every entry in range, the clamp keeps a failed one (flagged
+// singular, results discarded) from addressing outside the block.
+__device__ __forceinline__ int in_block(int i, int ld) {
+  return (int)min((unsigned)i, (unsigned)(ld - 1));
+}
+
+// ---------------------------------------------------------------------------
+// Block products.  One work-group of 16 waves per 64 x 64 output tile; wave w
+// owns the 16 x 16 tile (w/4, w%4).  K is staged through LDS in steps of 16
+// (double-buffered: the next step's global loads are issued before the MFMAs
+// of the current one).  Rows / columns beyond ld are never touched: ld is a
+// multiple of 32, so a tile is either full or its second half is outside.
+constexpr int kGemmTile = 64;
+constexpr int kGemmK = 16;
+constexpr int kGemmThreads = 1024;
+
+template <class T>
+__global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmOp<T> *ops, int ld) {
+  const GemmOp<T> g = ops[blockIdx.z];
+  const int tm0 = blockIdx.y * kGemmTile, tn0 = blockIdx.x * kGemmTile;
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int wr = wid >> 2, wc = wid & 3;
+  __shared__ T As[2][kGemmTile][kGemmK + 1];
+  __shared__ T Bs[2][kGemmK][kGemmTile + 2];
+  typename Vec4<T>::type acc = {0, 0, 0, 0};
+  const int nk1 = ld / kGemmK;
+  const int nk = g.A2 ? 2 * nk1 : nk1;
+  // this thread's staging element: A (row t/16, k t%16), B (k t/64, col t%64)
+  const int ar = t / kGemmK, ak = t % kGemmK;
+  const int bk = t / kGemmTile, bc = t % kGemmTile;
+  const bool arow_ok = tm0 + ar < ld, bcol_ok = tn0 + bc < ld;
+  T ra, rb;
+  auto gload = [&](int kt) {
+    const bool second = kt >= nk1;
+    const T *A = second ? g.A2 : g.A;
+    const T *B = second ? g.B2 : g.B;
+    const int *bg = second ? g.bg2 : g.bg;
+    const int k0 = (second ? kt - nk1 : kt) * kGemmK;
+    ra = arow_ok ? A[(size_t)(tm0 + ar) * ld + k0 + ak] : T(0);
+    const int brow = bg ? in_block(bg[k0 + bk], ld) : k0 + bk;
+    rb = bcol_ok ? B[(size_t)brow * ld + tn0 + bc] : T(0);
+  };
+  gload(0);
+  As[0][ar][ak] = ra;
+  Bs[0][bk][bc] = rb;
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload(kt + 1);
+#pragma unroll
+    for (int kk = 0; kk < kGemmK / 4; ++kk) {
+      const T av = As[buf][wr * 16 + (lane & 15)][kk * 4 + (lane >> 4)];
+      const T bv = Bs[buf][kk * 4 + (lane >> 4)][wc * 16 + (lane & 15)];
+      acc = mfma16(av, bv, acc);
+    }
+    if (kt + 1 < nk) {
+      As[buf ^ 1][ar][ak] = ra;
+      Bs[buf ^ 1][bk][bc] = rb;
+    }
+    __syncthreads();
+  }
+  const int c = tn0 + wc * 16 + (lane & 15);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = tm0 + wr * 16 + mfma_row(T(0), lane, i);
+    if (r < ld && c < ld) {
+      T *p = g.C + (size_t)r * ld + c;
+      const double v = g.alpha * (double)acc[i];
+      *p = (T)(g.beta ? (double)*p + v : v);
+    }
+  }
+}
+
+template <class T>
+hipError_t launch_gemm(const GemmOp<T> *dops, int count, int ld, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int nt = (ld + kGemmTile - 1) / kGemmTile;
+  const bool prof = options().profile != 0;
+  if (prof) prof_begin(kProfGemm, s);
+  hipLaunchKernelGGL((k_gemm<T>), dim3(nt, nt, count), dim3(kGemmThreads), 0, s, dops, ld);
+  if (prof) prof_end(kProfGemm, s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Level-0 Schur terms.  One work-group per (row r, kept layer).
+template <class T>
+__global__ void __launch_bounds__(256) k_cr_level0(const CrLevel0Op<T> *ops, int ld) {
+  const CrLevel0Op<T> &o = ops[blockIdx.y];
+  const int r = blockIdx.x;
+  const T *wl = o.Wl ? o.Wl + (size_t)in_block(o.pl[r], ld) * ld : nullptr;
+  const T *wr = o.Wr ? o.Wr + (size_t)in_block(o.pr[r], ld) * ld : nullptr;
+  const double akr = o.ak[r], ckr = o.ck[r];
+  T *D = o.D + (size_t)r * ld;
+  for (int j = threadIdx.x; j < ld; j += blockDim.x) {
+    double d = (double)D[j];
+    if (wl) {
+      const double el = (double)wl[in_block(o.ql[j], ld)];
+      d -= akr * el * o.cl[j];
+      if (o.A) o.A[(size_t)r * ld + j] = (T)(-akr * el * o.al[j]);
+    }
+    if (wr) {
+      const double er = (double)wr[in_block(o.qr[j], ld)];
+      d -= ckr * er * o.ar[j];
+      if (o.C) o.C[(size_t)r * ld + j] = (T)(-ckr * er * o.cr[j]);
+    }
+    D[j] = (T)d;
+  }
+}
+
+template <class T>
+hipError_t launch_cr_level0(const CrLevel0Op<T> *dops, int count, int ld, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_cr_level0<T>), dim3(ld, count), dim3(256), 0, s, dops, ld);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-vector terms.  One work-group per 16 output rows of one op; the
+// (gathered) input vectors are staged in LDS, each wave reduces 4 rows.
+template <class T>
+__global__ void __launch_bounds__(256) k_mv(const MvOp<T> *ops, int ld) {
+  const MvOp<T> &o = ops[blockIdx.y];
+  __shared__ double xs[2][kMaxLd];
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  for (int q = 0; q < o.nterm; ++q) {
+    const MvTerm<T> &tm = o.t[q];
+    for (int m = t; m < ld; m += blockDim.x) xs[q][m] = tm.x[tm.xm ? in_block(tm.xm[m], ld) : m];
+  }
+  __syncthreads();
+  for (int rr = 0; rr < 4; ++rr) {
+    const int j = blockIdx.x * 16 + wid * 4 + rr;
+    if (j >= ld) break;
+    double y = o.b ? o.b[j] : 0.0;
+    for (int q = 0; q < o.nterm; ++q) {
+      const MvTerm<T> &tm = o.t[q];
+      double v;
+      if (tm.M) {
+        const T *row = tm.M + (size_t)(tm.rm ? in_block(tm.rm[j], ld) : j) * ld;
+        double z = 0.0;
+        for (int m = lane; m < ld; m += 64) z = fma((double)row[m], xs[q][m], z);
+        for (int off = 32; off > 0; off >>= 1) z += __shfl_xor(z, off, 64);
+        v = z;
+      } else {
+        v = xs[q][j];
+      }
+      y += tm.sgn * (tm.s ? tm.s[j] : 1.0) * v;
+    }
+    if (lane == 0) o.y[j] = y;
+  }
+}
+
+template <class T>
+hipError_t launch_mv(const MvOp<T> *dops, int count, int ld, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const bool prof = options().profile != 0;
+  if (prof) prof_begin(kProfSolve, s);
+  hipLaunchKernelGGL((k_mv<T>), dim3((ld + 15) / 16, count), dim3(256), 0, s, dops, ld);
+  if (prof) prof_end(kProfSolve, s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_pad_copy(const double *src, double *dst, int N, int S, int ld, int to_padded) {
+  const size_t total = (size_t)N * ld;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const size_t k = e / ld;
+    const int y = (int)(e % ld);
+    if (to_padded)
+      dst[e] = y < S ? src[k * S + y] : 0.0;
+    else if (y < S)
+      dst[k * S + y] = src[e];
+  }
+}
+
+hipError_t launch_pad_copy(const double *src, double *dst, int N, int S, int ld, bool to_padded,
+                           hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pad_copy, dim3(64), dim3(256), 0, s, src, dst, N, S, ld,
+                     to_padded ? 1 : 0);
+  return hipGetLastError();
+}
+
+// rstep <- INT_MAX for all N*ld entries, flags <- -1.
+__global__ void k_cr_reset(int *rstep, size_t n, int *flag) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    rstep[e] = INT_MAX;
+  if (blockIdx.x == 0 && threadIdx.x < 4) flag[threadIdx.x] = -1;
+}
+
+hipError_t launch_cr_reset(int *rstep, size_t n, int *flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_cr_reset, dim3(64), dim3(256), 0, s, rstep, n, flag);
+  return hipGetLastError();
+}
+
+template hipError_t launch_gemm<double>(const GemmOp<double> *, int, int, hipStream_t);
+template hipError_t launch_gemm<float>(const GemmOp<float> *, int, int, hipStream_t);
+template hipError_t launch_cr_level0<double>(const CrLevel0Op<double> *, int, int, hipStream_t);
+template hipError_t launch_cr_level0<float>(const CrLevel0Op<float> *, int, int, hipStream_t);
+template hipError_t launch_mv<double>(const MvOp<double> *, int, int, hipStream_t);
+template hipError_t launch_mv<float>(const MvOp<float> *, int, int, hipStream_t);
+
+}  // namespace xod

@@ -85,7 +85,7 @@ Options &options();
 
 // Event-based launch timing (enabled with the "profile" option).  Kinds:
 enum ProfKind { kProfPanel = 0, kProfUpdate, kProfPrologue, kProfSolve, kProfJac,
-                kProfRates, kProfRhs, kProfNum };
+                kProfRates, kProfRhs, kProfGemm, kProfNum };
 // Record an event pair around the next launch of `kind` on stream s.
 void prof_begin(int kind, hipStream_t s);
 void prof_end(int kind, hipStream_t s);
@@ -118,6 +118,83 @@ hipError_t launch_axpy_ratio(const Acc &acc, int ncols, int maxN, double *delta,
                              double *out, hipStream_t s);
 template <class Acc>
 hipError_t launch_solve_mixed(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s);
+
+// One square block inverted in place by Gauss-Jordan elimination: its
+// storage, pivot bookkeeping (piv[j] = row chosen for column j, rstep = the
+// inverse permutation) and the id reported with a singular pivot.
+template <class T>
+struct MatRef {
+  T *W;
+  int *piv, *rstep, *flag;
+  int id;
+};
+
+// Invert `count` ld x ld blocks listed in dlist (device array).  rstep of
+// every listed block must hold INT_MAX on entry.
+template <class T>
+hipError_t launch_invert_list(const MatRef<T> *dlist, int count, int ld, hipStream_t s);
+
+// Batched dense product on ld x ld row-major blocks:
+//   C = (beta ? C : 0) + alpha * (A * B[bg] + A2 * B2[bg2])
+// where B[bg] gathers B's rows (row m of the operand is B row bg[m]; bg may
+// be null for the identity).  A2 may be null (single product).
+template <class T>
+struct GemmOp {
+  const T *A, *B;
+  const int *bg;
+  const T *A2, *B2;
+  const int *bg2;
+  T *C;
+  double alpha;
+  int beta;
+};
+template <class T>
+hipError_t launch_gemm(const GemmOp<T> *dops, int count, int ld, hipStream_t s);
+
+// Batched matrix-vector terms on padded vectors of length ld:
+//   y[j] = (b ? b[j] : 0) + sum_t sgn_t * (s_t ? s_t[j] : 1) * v_t[j]
+//   v_t[j] = M_t ? sum_m M_t[rm_t ? rm_t[j] : j][m] * x_t[xm_t ? xm_t[m] : m]
+//               : x_t[j]                       (diagonal term)
+// y may alias b; no x_t may alias y.
+template <class T>
+struct MvTerm {
+  const T *M;
+  const int *rm, *xm;
+  const double *x, *s;
+  double sgn;
+};
+template <class T>
+struct MvOp {
+  MvTerm<T> t[2];
+  int nterm;
+  const double *b;
+  double *y;
+};
+template <class T>
+hipError_t launch_mv(const MvOp<T> *dops, int count, int ld, hipStream_t s);
+
+// First level of block cyclic reduction (diagonal couplings a, c): for every
+// kept layer k with eliminated neighbours k-1 / k+1 (E = their inverses,
+// E[i][j] = W[piv[i]][rstep[j]]):
+//   D_k -= a_k E_{k-1} c_{k-1} + c_k E_{k+1} a_{k+1}
+//   A_k  = -a_k E_{k-1} a_{k-1}     (if layer k-2 exists)
+//   C_k  = -c_k E_{k+1} c_{k+1}     (if layer k+2 exists)
+template <class T>
+struct CrLevel0Op {
+  T *D, *A, *C;                    // A / C null when the new coupling is absent
+  const T *Wl, *Wr;                // null when the neighbour is absent
+  const int *pl, *ql, *pr, *qr;    // piv / rstep of the neighbours
+  const double *ak, *ck, *al, *cl, *ar, *cr;
+};
+template <class T>
+hipError_t launch_cr_level0(const CrLevel0Op<T> *dops, int count, int ld, hipStream_t s);
+
+// rstep <- INT_MAX for n entries, flag[0..3] <- -1.
+hipError_t launch_cr_reset(int *rstep, size_t n, int *flag, hipStream_t s);
+
+// Copy between the compact [N*S] layout and the padded [N*ld] layout.
+hipError_t launch_pad_copy(const double *src, double *dst, int N, int S, int ld, bool to_padded,
+                           hipStream_t s);
 
 // Column set-up arguments (k_setup).
 struct SetupArgs {

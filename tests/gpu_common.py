@@ -83,5 +83,11 @@ def assert_state_agrees(n, ref, delta, rel=1e-10, frac=1e-6):
     the rounding of n0 + delta itself (a few eps of |n|)."""
     lm = np.abs(delta).max(axis=-1, keepdims=True)
     allowed = rel * np.maximum(np.abs(delta), frac * lm) + 4 * EPS * np.abs(ref)
-    worst = float(np.max(np.abs(n - ref) / (allowed + 1e-300)))
-    assert worst <= 1.0, f"state disagreement {worst:.3e} x allowed"
+    ratio = np.abs(n - ref) / (allowed + 1e-300)
+    k, y = np.unravel_index(int(np.argmax(ratio)), ratio.shape)
+    worst = float(ratio[k, y])
+    msg = (f"state disagreement {worst:.3e} x allowed at layer {k} species {y}: "
+           f"n {n[k, y]:.17e} ref {ref[k, y]:.17e} delta {delta[k, y]:.3e} "
+           f"layer max |delta| {lm[k, 0]:.3e}")
+    print(msg)
+    assert worst <= 1.0, msg

@@ -1,0 +1,163 @@
+"""GPU parity of the block cyclic-reduction factorisation (xod_column_set_solver
+XOD_SOLVER_CR) against the oracle's block-Thomas / dense solves: the same
+block system, eliminated in a different order.
+
+Tolerance: cyclic reduction combines layers up to 2^l apart at level l, so
+the rounding of a layer's smallest increments is relative to the magnitudes
+of layers several pressure decades away, not only to its own.  The
+per-layer floor of the block-Thomas tests (1e-10 x 1e-6 x the layer's
+largest increment, i.e. about one unit roundoff of it) is therefore taken
+ten times wider here (rel = 1e-9)."""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import synth  # noqa: E402
+from oracle import integrate, equilibrium, linalg  # noqa: E402
+from tests import gpu_common as G  # noqa: E402
+from tests.helpers import balanced_c1_network  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    import paper_2512_06729_amd  # noqa: F401  (fails loudly if not built)
+
+
+def cr_pair(net, col, precision=0):
+    import paper_2512_06729_amd as xod
+    prob, gnet, gcol = G.make_pair(net, col, precision)
+    gcol.set_solver(xod.XOD_SOLVER_CR)
+    return prob, gnet, gcol
+
+
+# Layer counts with ragged reduction trees: 1 (root only), 2, 3, powers of
+# two and their neighbours, and the 20 layers of the small configuration.
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 7, 8, 9, 16, 17, 20])
+@pytest.mark.parametrize("dt", [1e-6, 1e2])
+def test_cr_step_matches_oracle_ragged(N, dt):
+    """Small dt: per-layer agreement of the new state.  Large dt (the step
+    matrix has cond ~1e10 here): the increment against a dense solve within
+    the backward-stability bound 50 cond(M) eps, and the residual bound."""
+    import paper_2512_06729_amd as xod
+    print(f"cr step N={N} dt={dt}", flush=True)
+    net = synth.make_network("c1", seed=1001)
+    col = synth.make_column("c1", net, seed=300 + N, N=N)
+    prob, gnet, gcol = cr_pair(net, col)
+    st = xod.xod_step(gcol, dt)
+    assert st["nonfinite"] == 0
+    n = gcol.state()
+    if dt <= 1e-3:
+        ref, delta = integrate.be_step(prob, col.n0, dt)
+        G.assert_state_agrees(n, ref, delta, rel=1e-9)
+        return
+    f = prob.rhs(col.n0)
+    B, a, c = prob.step_matrix(col.n0, dt)
+    M = linalg.assemble(B, a, c)
+    ref = np.linalg.solve(M, f.ravel())
+    kappa = np.linalg.cond(M)
+    x = (n - col.n0).ravel()
+    scale = np.abs(ref).max() + 4 * G.EPS * np.abs(n).max()
+    print(f"cond {kappa:.2e} err {np.abs(x - ref).max() / (kappa * G.EPS * scale):.2e} x cond eps")
+    assert np.abs(x - ref).max() <= 50 * kappa * G.EPS * scale
+    r = M @ x - f.ravel()
+    assert np.abs(r).max() <= 50 * kappa * G.EPS * (np.abs(M) @ np.abs(x) + np.abs(f.ravel())).max()
+
+
+@pytest.mark.parametrize("cfg,dt", [(2, 1e-6), (2, 1e-8), (3, 1e-8)])
+def test_cr_single_step_matches_oracle(cfg, dt):
+    import paper_2512_06729_amd as xod
+    print(f"cr step config {cfg} dt={dt}", flush=True)
+    net, col = synth.make_config(cfg)
+    prob, gnet, gcol = cr_pair(net, col)
+    ref, delta = integrate.be_step(prob, col.n0, dt)
+    xod.xod_step(gcol, dt)
+    G.assert_state_agrees(gcol.state(), ref, delta, rel=1e-9)
+
+
+def test_cr_fixed_schedule_config1_matches_oracle():
+    import paper_2512_06729_amd as xod
+    net, col = synth.make_config(1)
+    prob, gnet, gcol = cr_pair(net, col)
+    sched = integrate.fixed_schedule(200)
+    ref = integrate.run_fixed(prob, col.n0, sched)
+    for dt in sched:
+        assert xod.xod_step(gcol, dt)["nonfinite"] == 0
+    n = gcol.state()
+    keep = np.abs(ref) > 1e-30 * prob.grid.ngas[:, None]
+    np.testing.assert_allclose(n[keep], ref[keep], rtol=1e-10)
+
+
+def test_cr_agrees_with_thomas_config3():
+    """Three steps of the 594 x 150 column, both factorisations on the GPU."""
+    import paper_2512_06729_amd as xod
+    net, col = synth.make_config(3)
+    stream = torch.cuda.current_stream().cuda_stream
+    gnet = xod.Network(net)
+    gt = xod.Column(gnet, col, stream=stream)
+    gc = xod.Column(gnet, col, stream=stream, solver=xod.XOD_SOLVER_CR)
+    n0 = gt.state()
+    for dt in (1e-7, 1e-6, 1e-5):
+        xod.xod_step(gt, dt)
+        xod.xod_step(gc, dt)
+    a, b = gc.state(), gt.state()
+    G.assert_state_agrees(a, b, b - n0, rel=1e-9)
+
+
+def test_cr_closed_layer_steady_state():
+    import paper_2512_06729_amd as xod
+    net = balanced_c1_network()
+    col = synth.make_column("c1", net, seed=77, N=3)
+    col.T_K = np.array([1900.0, 1500.0, 1100.0])
+    col.Kzz = np.zeros(3)
+    prob, gnet, gcol = cr_pair(net, col)
+    res = xod.xod_integrate_to_steady_state(gcol, tol_rel=1e-13, t_end=1e30, max_steps=4000)
+    assert res["converged"] == 1
+    n = gcol.state()
+    A = net.elem_comp.astype(float)
+    for k in range(3):
+        b = A @ n[k]
+        on = b > 0
+        lam0 = equilibrium.initial_potentials(net.nasa7, net.t_mid, A[on], col.T_K[k], n[k])
+        neq, _ = equilibrium.equilibrium_layer(net.nasa7, net.t_mid, A[on], col.T_K[k], b[on], lam0)
+        keep = neq > 1e-30 * prob.grid.ngas[k]
+        np.testing.assert_allclose(n[k, keep], neq[keep], rtol=1e-8)
+
+
+@pytest.mark.parametrize("cfg,dt", [(1, 1e-6), (2, 1e-6), (3, 1e-7)])
+def test_cr_mixed_step_matches_fp64_oracle(cfg, dt):
+    import paper_2512_06729_amd as xod
+    print(f"cr mixed config {cfg} dt={dt}", flush=True)
+    net, col = synth.make_config(cfg)
+    prob, gnet, gcol = cr_pair(net, col, precision=xod.XOD_MIXED)
+    ref, delta = integrate.be_step(prob, col.n0, dt)
+    st = xod.xod_step(gcol, dt)
+    assert st["fp64_fallback"] == 0 and st["refine_iters"] >= 1
+    n = gcol.state()
+    keep = np.abs(ref) > 1e-30 * prob.grid.ngas[:, None]
+    rel = np.abs(n - ref)[keep] / np.abs(ref)[keep]
+    assert rel.max() <= 1e-6, rel.max()
+    G.assert_state_agrees(n, ref, delta, rel=1e-8)
+
+
+def test_cr_solver_switch_and_errors():
+    import paper_2512_06729_amd as xod
+    net, col = synth.make_config(1)
+    prob, gnet, gcol = G.make_pair(net, col)
+    with pytest.raises(xod.XodError) as e:
+        gcol.set_solver(7)
+    assert e.value.status == xod.XOD_EINVAL
+    dt = 1e-4
+    gcol.set_solver(xod.XOD_SOLVER_CR)
+    xod.xod_step(gcol, dt)
+    a = gcol.state()
+    gcol.set_state(col.n0)
+    gcol.set_solver(xod.XOD_SOLVER_THOMAS)
+    xod.xod_step(gcol, dt)
+    b = gcol.state()
+    G.assert_state_agrees(a, b, b - col.n0, rel=1e-9)
