@@ -172,12 +172,14 @@ def main():
         xod.xod_step(gcol, args.dt)
     torch.cuda.synchronize()
 
-    # timed region: kernel events on (profile_every thins the per-layer
-    # block-Thomas events; cyclic reduction records every launch)
+    # timed region: the steps alone
+    el = timed_steps(xod, torch, gcol, args.dt, args.steps)
+    # kernel breakdown: the same number of steps again with HIP events around
+    # every launch (profile_every thins the per-layer block-Thomas events)
     xod.profile_reset()
     xod.set_option("profile_every", args.profile_every)
     xod.set_option("profile", 1)
-    el = timed_steps(xod, torch, gcol, args.dt, args.steps)
+    el_prof = timed_steps(xod, torch, gcol, args.dt, args.steps)
     xod.set_option("profile", 0)
 
     kern = {}
@@ -245,6 +247,7 @@ def main():
         "roofline": dict(rl),
         "roofline_schur_gemm": gemm_rl,
         "kernels": kern,
+        "ms_per_step_with_kernel_events": 1e3 * el_prof / args.steps,
     }
     gcol.close()
     if not args.skip_thomas and args.solver == "cr":

@@ -169,8 +169,9 @@ xod_status xod_column_grid(const xod_column *col, double *ngas, double *tau,
  * xod_integrate_to_steady_state on this column (default XOD_SOLVER_THOMAS).
  * XOD_SOLVER_CR allocates its workspace on first selection (XOD_ENOMEM if
  * it does not fit).  The explicit-block calls xod_btd_factor / xod_btd_solve
- * always use block Thomas.  The FP64 fallback of a mixed-precision solve is
- * block Thomas as well. */
+ * always use block Thomas.  The FP64 fallback of a mixed-precision solve
+ * uses the column's solver in FP64 (a mixed column with XOD_SOLVER_CR holds
+ * FP64 and FP32 cyclic-reduction workspaces). */
 xod_status xod_column_set_solver(xod_column *col, xod_solver solver);
 
 /* ---- hot-path calls (device pointers, asynchronous on the column stream) */
@@ -263,6 +264,10 @@ xod_status xod_last_error(char *buf, size_t len);
 
 /* Kernel options (process-wide; for tests and tuning).
  *   "gemm": 0 = VALU FMA Schur update, 1 = MFMA Schur update (default).
+ *   "graph": 1 = the cyclic-reduction factor and solve launch sequences of a
+ *            column are captured once into HIP graphs (kernel nodes only)
+ *            and replayed (default); 0 = launched one by one.  Graphs are
+ *            not used while "profile" is on.
  *   "profile": 1 = record HIP events on the launching stream around each
  *              profiled kernel launch (default 0).
  *   "profile_every": profile layer k only when k % value == 0 (default 1). */

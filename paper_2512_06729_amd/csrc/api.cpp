@@ -107,6 +107,11 @@ extern "C" xod_status xod_set_option(const char *name, int64_t value) {
     options().gemm_mfma = (int)value;
     return XOD_OK;
   }
+  if (std::strcmp(name, "graph") == 0) {
+    XOD_CHECK(value == 0 || value == 1, "xod_set_option: graph must be 0 or 1");
+    options().graph = (int)value;
+    return XOD_OK;
+  }
   if (std::strcmp(name, "profile") == 0) {
     XOD_CHECK(value == 0 || value == 1, "xod_set_option: profile must be 0 or 1");
     options().profile = (int)value;
@@ -479,7 +484,7 @@ extern "C" xod_status xod_column_set_solver(xod_column *col, xod_solver solver) 
             "xod_column_set_solver: unknown solver");
   XOD_CHECK(!col->in_batch, "xod_column_set_solver: column belongs to a batch");
   if (solver == XOD_SOLVER_CR) {
-    if (col->prec == XOD_FP64 && !col->cr64) {
+    if (!col->cr64) {   // FP64 columns, and the FP64 fallback of mixed ones
       std::unique_ptr<xod::CrPlan<double>> p(new xod::CrPlan<double>());
       const xod_status st = p->build(col);
       if (st != XOD_OK) return st == XOD_EHIP ? XOD_ENOMEM : st;
@@ -639,9 +644,15 @@ xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, do
   }
   *fallback = 1;
   XOD_HIP(launch_jacobian(one, 1, c->N, c->ld, false, c->stream));
-  XOD_HIP(launch_factor_fp64(one, 1, c->N, c->ld, c->stream));
+  if (cr)
+    XOD_TRY(c->cr64->factor(c));
+  else
+    XOD_HIP(launch_factor_fp64(one, 1, c->N, c->ld, c->stream));
   XOD_HIP(hipMemcpyAsync(c->x, c->f, NSb, hipMemcpyDeviceToDevice, c->stream));
-  XOD_HIP(launch_solve_fp64(one, 1, c->N, c->ld, c->stream));
+  if (cr)
+    XOD_TRY(c->cr64->solve(c));
+  else
+    XOD_HIP(launch_solve_fp64(one, 1, c->N, c->ld, c->stream));
   return XOD_OK;
 }
 

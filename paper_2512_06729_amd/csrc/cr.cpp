@@ -48,6 +48,9 @@ xod_status CrPlan<T>::upload(U **dst, const std::vector<U> &v) {
 
 template <class T>
 CrPlan<T>::~CrPlan() {
+  if (gfactor) (void)hipGraphExecDestroy(gfactor);
+  if (gsolve) (void)hipGraphExecDestroy(gsolve);
+  if (cap) (void)hipStreamDestroy(cap);
   for (void *p : owned) (void)hipFree(p);
 }
 
@@ -80,6 +83,8 @@ template <class T>
 xod_status CrPlan<T>::build(xod_column *c) {
   N = c->N;
   ld = c->ld;
+  rstep_all = c->rstep;
+  flag = c->flag;
   levels = cr_levels(N);
   const size_t bs = (size_t)ld * ld;
   T *blk0 = col_blocks<T>(c);
@@ -258,9 +263,8 @@ xod_status CrPlan<T>::build(xod_column *c) {
 }
 
 template <class T>
-xod_status CrPlan<T>::factor(xod_column *c) {
-  hipStream_t s = c->stream;
-  XOD_HIP(launch_cr_reset(c->rstep, (size_t)N * ld, c->flag, s));
+xod_status CrPlan<T>::enqueue_factor(hipStream_t s) {
+  XOD_HIP(launch_cr_reset(rstep_all, (size_t)N * ld, flag, s));
   const int nlev = (int)levels.size();
   for (int l = 0; l < nlev; ++l) {
     XOD_HIP(launch_invert_list<T>(d_inv + inv_off[l], inv_cnt[l], ld, s));
@@ -276,8 +280,7 @@ xod_status CrPlan<T>::factor(xod_column *c) {
 }
 
 template <class T>
-xod_status CrPlan<T>::solve(xod_column *c) {
-  hipStream_t s = c->stream;
+xod_status CrPlan<T>::enqueue_solve(hipStream_t s, xod_column *c) {
   XOD_HIP(launch_pad_copy(c->x, c->gs, N, c->S, ld, true, s));
   const int nlev = (int)levels.size();
   for (int l = 0; l < nlev; ++l) XOD_HIP(launch_mv<T>(d_mv + fwd_off[l], fwd_cnt[l], ld, s));
@@ -288,6 +291,48 @@ xod_status CrPlan<T>::solve(xod_column *c) {
   }
   XOD_HIP(launch_pad_copy(xs, c->x, N, c->S, ld, false, s));
   return XOD_OK;
+}
+
+// Capture the launch sequence once on a private stream (capture needs a
+// stream other than the legacy default one), then replay it on the column's
+// stream.  The graphs hold kernel nodes only.
+template <class T>
+xod_status CrPlan<T>::replay(hipGraphExec_t *g, bool factor, xod_column *c) {
+  if (graph_gemm != options().gemm_mfma) {
+    if (gfactor) XOD_HIP(hipGraphExecDestroy(gfactor));
+    if (gsolve) XOD_HIP(hipGraphExecDestroy(gsolve));
+    gfactor = gsolve = nullptr;
+    graph_gemm = options().gemm_mfma;
+  }
+  if (!*g) {
+    if (!cap) XOD_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    XOD_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    const xod_status st = factor ? enqueue_factor(cap) : enqueue_solve(cap, c);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(cap, &graph);
+    if (st != XOD_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    XOD_HIP(e);
+    const hipError_t ei = hipGraphInstantiate(g, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    XOD_HIP(ei);
+  }
+  XOD_HIP(hipGraphLaunch(*g, c->stream));
+  return XOD_OK;
+}
+
+template <class T>
+xod_status CrPlan<T>::factor(xod_column *c) {
+  if (options().graph && !options().profile) return replay(&gfactor, true, c);
+  return enqueue_factor(c->stream);
+}
+
+template <class T>
+xod_status CrPlan<T>::solve(xod_column *c) {
+  if (options().graph && !options().profile) return replay(&gsolve, false, c);
+  return enqueue_solve(c->stream, c);
 }
 
 template struct CrPlan<double>;

@@ -28,6 +28,7 @@ size_t cr_extra_blocks(int N);
 template <class T>
 struct CrPlan {
   int N = 0, ld = 0;
+  int *rstep_all = nullptr, *flag = nullptr;   // the column's pivot steps and flags
   std::vector<CrLevel> levels;
   std::vector<void *> owned;
   T *slots = nullptr;    // dense A / C blocks of even layers, then T1 / T2 products
@@ -40,6 +41,12 @@ struct CrPlan {
   std::vector<int> inv_off, inv_cnt, g1_off, g1_cnt, g2_off, g2_cnt;
   std::vector<int> fwd_off, fwd_cnt, bwd1_off, bwd1_cnt, bwd2_off, bwd2_cnt;
 
+  // captured launch sequences (kernel nodes only), replayed on the
+  // column's stream; built on first use with the options then in force
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gfactor = nullptr, gsolve = nullptr;
+  int graph_gemm = -1;   // the "gemm" option the graphs were captured with
+
   ~CrPlan();
   // Device descriptors for the column's buffers (blocks, couplings, pivots).
   xod_status build(xod_column *c);
@@ -51,6 +58,9 @@ struct CrPlan {
  private:
   template <class U>
   xod_status upload(U **dst, const std::vector<U> &v);
+  xod_status enqueue_factor(hipStream_t s);
+  xod_status enqueue_solve(hipStream_t s, xod_column *c);
+  xod_status replay(hipGraphExec_t *g, bool factor, xod_column *c);
 };
 
 }  // namespace xod

@@ -78,6 +78,7 @@ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 // Process-wide kernel options.
 struct Options {
   int gemm_mfma = 1;
+  int graph = 1;          // replay captured launch sequences (cyclic reduction)
   int profile = 0;        // record HIP events around profiled launches
   int profile_every = 1;  // profile layers k with k % profile_every == 0
 };
