@@ -126,6 +126,100 @@ def bench_mixed(xod, torch, gnet, col, args, solver):
             "first_step_max_rel_err_vs_fp64": err, "first_step_refine_iters": st["refine_iters"]}
 
 
+def bench_batch(xod, torch, args):
+    """Ragged batch of independent columns (60-200 layers; 90-, 250- and
+    594-species networks, three of each; per-column T offset and Kzz scale),
+    stepped together: columns with the same padded block size share every
+    launch (block Thomas across columns, FP64)."""
+    import numpy as np
+    import synth
+    stream = torch.cuda.current_stream().cuda_stream
+    t0 = time.perf_counter()
+    cols = synth.make_batch(args.batch_cols)
+    gnets, gcols = {}, []
+    for net, col in cols:
+        if id(net) not in gnets:
+            gnets[id(net)] = xod.Network(net)
+        gcols.append(xod.Column(gnets[id(net)], col, stream=stream))
+    batch = xod.Batch(gcols)
+    setup = time.perf_counter() - t0
+    dts = np.full(len(gcols), args.dt)
+    batch.step(dts)
+    torch.cuda.synchronize()
+    k = args.batch_steps
+    t0 = time.perf_counter()
+    for _ in range(k):
+        batch.step(dts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    layers = sum(c.N for c in gcols)
+    flops = sum(2.0 * c.S ** 3 * c.N for c in gcols)
+    sizes = {}
+    for c in gcols:
+        sizes[c.S] = sizes.get(c.S, 0) + 1
+    out = {"value": k * len(gcols) / el, "unit": "column-steps/s",
+           "batched_steps_per_s": k / el, "ms_per_batched_step": 1e3 * el / k,
+           "columns": len(gcols), "columns_per_species_count": sizes, "layers": layers,
+           "gauss_jordan_tflops": flops * k / el / 1e12, "setup_s": setup, "steps": k,
+           "solver": "block Thomas across columns", "precision": "fp64"}
+    batch.close()
+    for c in gcols:
+        c.close()
+    return out
+
+
+def bench_serve(xod, torch, args, precision, gnet, net):
+    """Poisson arrivals of steady-state solves (594 species x 150 layers,
+    per-request T offset / Kzz scale / initial state, t_end 1e12 s,
+    max |dn/n| < 1e-4), served by the continuous-batching loop: p50 / p99
+    latency (submission to completion) and completed solves per second."""
+    import numpy as np
+    import synth
+    stream = torch.cuda.current_stream().cuda_stream
+    n = args.serve_requests
+    arrivals = synth.poisson_arrivals(n, args.serve_rate)
+    cols = [synth.make_request(j, net) for j in range(n)]
+    fp = xod.Server.footprint(gnet, cols[0].N, precision)
+    srv = xod.Server(hbm_budget_bytes=args.serve_slots * fp, max_slots=args.serve_slots,
+                     precision=precision, stream=stream)
+    opts = dict(tol_rel=1e-4, t_end=1e12, max_steps=3000)
+    ids, done, lat, steps, states = [], {}, [], [], {}
+    t0 = time.perf_counter()
+    nsub = 0
+    while len(done) < n:
+        now = time.perf_counter() - t0
+        while nsub < n and arrivals[nsub] <= now:
+            ids.append(srv.submit(gnet, cols[nsub], **opts))
+            nsub += 1
+        if nsub == len(done):             # idle until the next arrival
+            time.sleep(max(0.0, min(0.01, arrivals[nsub] - now)))
+            continue
+        srv.step()
+        for j, rid in enumerate(ids):
+            if rid in done:
+                continue
+            o = srv.poll(rid)
+            if o["state"] >= xod.Server.DONE:
+                done[rid] = o
+                lat.append(o["latency_s"])
+                steps.append(o["steps"])
+                states[j] = o["n"]
+                srv.release(rid)
+        if time.perf_counter() - t0 > args.serve_timeout:
+            break
+    wall = time.perf_counter() - t0
+    srv.close()
+    lat = np.array(lat)
+    ok = sum(1 for o in done.values() if o["state"] == xod.Server.DONE)
+    return {"requests": n, "completed": len(done), "converged": ok,
+            "rate_per_s": args.serve_rate, "slots": args.serve_slots,
+            "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
+            "solves_per_s": len(done) / wall, "wall_s": wall,
+            "mean_steps_per_solve": float(np.mean(steps)) if steps else None,
+            "precision": "fp64" if precision == xod.XOD_FP64 else "mixed"}, states
+
+
 def timed_steps(xod, torch, gcol, dt, steps):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -149,6 +243,14 @@ def main():
     ap.add_argument("--profile-every", type=int, default=1)
     ap.add_argument("--skip-mixed", action="store_true")
     ap.add_argument("--skip-thomas", action="store_true")
+    ap.add_argument("--skip-batch", action="store_true")
+    ap.add_argument("--batch-cols", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--skip-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=8)
+    ap.add_argument("--serve-rate", type=float, default=5.0)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-timeout", type=float, default=150.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): columns are "
@@ -260,6 +362,21 @@ def main():
         gt.close()
     if not args.skip_mixed:
         line["mixed"] = bench_mixed(xod, torch, gnet, col, args, solver)
+    if not args.skip_serve:
+        s64, n64 = bench_serve(xod, torch, args, xod.XOD_FP64, gnet, net)
+        smx, nmx = bench_serve(xod, torch, args, xod.XOD_MIXED, gnet, net)
+        diffs = {}
+        for floor in (1e-30, 1e-20, 1e-10):
+            errs = []
+            for j, a in n64.items():
+                if j in nmx:
+                    keep = np.abs(a) > floor * np.abs(a).sum(axis=1, keepdims=True)
+                    errs.append(float(np.max(np.abs(nmx[j] - a)[keep] / np.abs(a)[keep])))
+            diffs[f"y>{floor:g}"] = max(errs) if errs else None
+        smx["max_rel_diff_vs_fp64_steady_state"] = diffs
+        line["serve"] = {"fp64": s64, "mixed": smx}
+    if not args.skip_batch:
+        line["batch"] = bench_batch(xod, torch, args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(net, col)
     print(json.dumps(line), flush=True)

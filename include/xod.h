@@ -296,12 +296,20 @@ xod_status xod_batch_step(xod_batch *b, const double *dt_per_col,
 /* ---- serving: continuous batching of steady-state solves -------------- */
 
 /* hbm_budget_bytes bounds the device memory held by resident requests;
- * max_slots bounds their number.  All work goes to hip_stream. */
+ * max_slots bounds their number.  With the default solver (block cyclic
+ * reduction) each slot owns a HIP stream created here (default priority);
+ * with block Thomas all work goes to hip_stream. */
 xod_status xod_serve_create(size_t hbm_budget_bytes, int32_t max_slots,
                             xod_precision prec, void *hip_stream,
                             xod_server **out);
 xod_status xod_serve_destroy(xod_server *srv);
-/* Device bytes one request of this network and layer count occupies. */
+/* Factorisation used for the requests (default XOD_SOLVER_CR).  Only before
+ * the first submit (XOD_EINVAL afterwards).  XOD_SOLVER_THOMAS steps all
+ * resident FP64 requests in shared batched launches. */
+xod_status xod_serve_set_solver(xod_server *srv, xod_solver solver);
+/* Device bytes one request of this network and layer count occupies with
+ * the default solver (column state and blocks plus the cyclic-reduction
+ * workspace; an upper bound for block Thomas). */
 xod_status xod_serve_footprint(const xod_network *net, int32_t N,
                                xod_precision prec, size_t *bytes);
 /* Queue a steady-state solve (host arrays copied; opts as for
@@ -313,7 +321,9 @@ xod_status xod_serve_submit(xod_server *srv, const xod_network *net,
                             const xod_ss_opts *opts, uint64_t *req_id);
 /* One iteration: admit queued requests (arrival order) while a slot is free
  * and the footprint fits, advance every resident request by one adaptive BE
- * step (FP64 requests share batched launches), retire converged / failed
+ * step (cyclic reduction: FP64 requests' steps are enqueued on their slot
+ * streams before any is awaited, so they overlap on the device; block
+ * Thomas: FP64 requests share batched launches), retire converged / failed
  * ones (state copied to the host, slot and memory freed).  Synchronous. */
 xod_status xod_serve_step(xod_server *srv, int32_t *n_active, int32_t *n_queued);
 /* state: 0 queued, 1 running, 2 converged, 3 failed.  n_out (host [N*S],

@@ -130,6 +130,7 @@ _f = {
     "xod_serve_create": _sig("xod_serve_create", ctypes.c_size_t, c_int32, c_int32, c_void_p,
                              ctypes.POINTER(c_void_p)),
     "xod_serve_destroy": _sig("xod_serve_destroy", c_void_p),
+    "xod_serve_set_solver": _sig("xod_serve_set_solver", c_void_p, c_int32),
     "xod_serve_footprint": _sig("xod_serve_footprint", c_void_p, c_int32, c_int32,
                                 ctypes.POINTER(ctypes.c_size_t)),
     "xod_serve_submit": _sig("xod_serve_submit", c_void_p, c_void_p, ctypes.POINTER(Profile),
@@ -386,12 +387,15 @@ class Server:
 
     QUEUED, RUNNING, DONE, FAILED = 0, 1, 2, 3
 
-    def __init__(self, hbm_budget_bytes, max_slots, precision=XOD_FP64, stream=None):
+    def __init__(self, hbm_budget_bytes, max_slots, precision=XOD_FP64, stream=None,
+                 solver=XOD_SOLVER_CR):
         h = c_void_p()
         _check(_f["xod_serve_create"](int(hbm_budget_bytes), int(max_slots), int(precision),
                                       c_void_p(stream or 0), ctypes.byref(h)))
         self.handle = h
         self.precision = precision
+        if solver != XOD_SOLVER_CR:
+            _check(_f["xod_serve_set_solver"](h, int(solver)))
         self._shapes = {}
 
     @staticmethod

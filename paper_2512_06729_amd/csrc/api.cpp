@@ -346,6 +346,8 @@ extern "C" xod_status xod_column_create(const xod_network *net, const xod_profil
   XOD_TRY(calloc_(c, &c->upd_dev, 1));
   XOD_TRY(calloc_(c, &c->red_dev, 1));
   XOD_HIP(hipHostMalloc((void **)&c->stats_host, kStatLen * sizeof(double), hipHostMallocDefault));
+  XOD_HIP(hipHostMalloc((void **)&c->upd_host, sizeof(UpdArgs), hipHostMallocDefault));
+  XOD_HIP(hipHostMalloc((void **)&c->red_host, sizeof(RedArgs), hipHostMallocDefault));
 
   SetupArgs sa{};
   sa.N = N;
@@ -551,8 +553,9 @@ size_t column_footprint(const xod_network *net, int N, xod_precision prec) {
   return b;
 }
 
-xod_status run_update(xod_column *c, bool clip, double y_floor, double y_sig, double *out) {
-  UpdArgs u{};
+xod_status enqueue_update(xod_column *c, bool clip, double y_floor, double y_sig) {
+  UpdArgs &u = *c->upd_host;
+  u = UpdArgs{};
   u.n = c->n;
   u.x = c->x;
   u.ngas = c->ngas;
@@ -563,12 +566,19 @@ xod_status run_update(xod_column *c, bool clip, double y_floor, double y_sig, do
   u.clip = clip ? 1 : 0;
   u.y_floor = y_floor;
   u.y_sig = y_sig;
-  RedArgs r{c->partial, c->flag, c->stats_dev};
-  XOD_HIP(hipMemcpyAsync(c->upd_dev, &u, sizeof(u), hipMemcpyHostToDevice, c->stream));
-  XOD_HIP(hipMemcpyAsync(c->red_dev, &r, sizeof(r), hipMemcpyHostToDevice, c->stream));
+  *c->red_host = RedArgs{c->partial, c->flag, c->stats_dev};
+  XOD_HIP(hipMemcpyAsync(c->upd_dev, c->upd_host, sizeof(UpdArgs), hipMemcpyHostToDevice,
+                         c->stream));
+  XOD_HIP(hipMemcpyAsync(c->red_dev, c->red_host, sizeof(RedArgs), hipMemcpyHostToDevice,
+                         c->stream));
   XOD_HIP(launch_update_state(c->upd_dev, c->red_dev, 1, c->stream));
   XOD_HIP(hipMemcpyAsync(c->stats_host, c->stats_dev, kStatLen * sizeof(double),
                          hipMemcpyDeviceToHost, c->stream));
+  return XOD_OK;
+}
+
+xod_status run_update(xod_column *c, bool clip, double y_floor, double y_sig, double *out) {
+  XOD_TRY(enqueue_update(c, clip, y_floor, y_sig));
   XOD_HIP(hipStreamSynchronize(c->stream));
   std::memcpy(out, c->stats_host, kStatLen * sizeof(double));
   return XOD_OK;

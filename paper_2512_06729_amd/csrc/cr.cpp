@@ -79,6 +79,15 @@ size_t cr_extra_blocks(int N) {
   return n;
 }
 
+size_t cr_footprint(const xod_network *net, int N, xod_precision prec) {
+  const size_t ld = net->ld, bs = ld * ld;
+  const size_t nblk = std::max<size_t>(cr_extra_blocks(N), 1);
+  const size_t per = (size_t)N * ld * sizeof(double) + 1024 * (size_t)N + 64 * 1024;
+  size_t b = nblk * bs * sizeof(double) + per;                   // FP64 workspace
+  if (prec == XOD_MIXED) b += nblk * bs * sizeof(float) + per;   // + FP32 workspace
+  return b;
+}
+
 template <class T>
 xod_status CrPlan<T>::build(xod_column *c) {
   N = c->N;

@@ -52,8 +52,8 @@ struct xod_column {
   double *partial = nullptr, *stats_dev = nullptr, *stats_host = nullptr;
   double *ratio = nullptr, *rmax = nullptr;   // refinement convergence measure
   int max_refine = 10;
-  UpdArgs *upd_dev = nullptr;
-  RedArgs *red_dev = nullptr;
+  UpdArgs *upd_dev = nullptr, *upd_host = nullptr;   // host side pinned
+  RedArgs *red_dev = nullptr, *red_host = nullptr;
   double t = 0.0, dt = 0.0;
   bool in_batch = false;
   xod_solver solver = XOD_SOLVER_THOMAS;
@@ -63,6 +63,8 @@ struct xod_column {
     xod::cr_destroy(cr64);
     xod::cr_destroy(cr32);
     if (stats_host) (void)hipHostFree(stats_host);
+    if (upd_host) (void)hipHostFree(upd_host);
+    if (red_host) (void)hipHostFree(red_host);
     for (void *p : owned) (void)hipFree(p);
   }
   ColArgs args() const {
@@ -122,6 +124,11 @@ namespace xod {
 xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, double *resid);
 // n_new = n + delta into col->ntmp plus statistics (host copy, kStatLen).
 xod_status run_update(xod_column *c, bool clip, double y_floor, double y_sig, double *out);
+// The same, enqueued only: the statistics land in c->stats_host once the
+// column's stream has reached them.
+xod_status enqueue_update(xod_column *c, bool clip, double y_floor, double y_sig);
+// Device bytes of the cyclic-reduction workspace of a column.
+size_t cr_footprint(const xod_network *net, int N, xod_precision prec);
 // Device bytes a column of this network with N layers allocates.
 size_t column_footprint(const xod_network *net, int N, xod_precision prec);
 }  // namespace xod

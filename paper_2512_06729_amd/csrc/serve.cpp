@@ -6,8 +6,11 @@
 //      request's device footprint fits in the HBM budget (state and
 //      workspace stay resident on the device until the request retires);
 //   2. advances every resident request by one adaptive backward-Euler step
-//      with its own dt - FP64 requests share batched launches, mixed
-//      requests run their refined steps back to back on the stream;
+//      with its own dt.  With the cyclic-reduction solver (default) every
+//      slot has its own HIP stream: all FP64 steps are enqueued first and
+//      then awaited, so the requests' kernels overlap on the device; mixed
+//      requests run their refinement loops one after another.  With block
+//      Thomas, FP64 requests share batched launches on the server stream;
 //   3. applies each request's step control and retires converged or failed
 //      requests: the final state is copied to the host, the slot and its
 //      memory are freed, and the latency (completion - submission) recorded.
@@ -35,6 +38,7 @@ double now_s() {
 struct Req {
   uint64_t id = 0;
   const xod_network *net = nullptr;
+  int slot = -1;
   std::vector<double> P, T, K, D, alpha, n0;
   bool hasD = false, hasA = false;
   double mbar = 2.3, g = 2000.0, sigma = 1e-22;
@@ -67,9 +71,17 @@ struct xod_server {
   std::vector<uint64_t> active;
   BatchRunner runner;
   int64_t iterations = 0;
+  xod_solver solver = XOD_SOLVER_CR;
+  std::vector<hipStream_t> slot_stream;   // one per slot (cyclic reduction)
+  std::vector<char> slot_busy;
+  size_t footprint(const xod_network *net, int N) const {
+    return column_footprint(net, N, prec) +
+           (solver == XOD_SOLVER_CR ? cr_footprint(net, N, prec) : 0);
+  }
   ~xod_server() {
     for (auto &kv : reqs)
       if (kv.second.col) xod_column_destroy(kv.second.col);
+    for (hipStream_t st : slot_stream) (void)hipStreamDestroy(st);
   }
 };
 
@@ -91,7 +103,22 @@ extern "C" xod_status xod_serve_create(size_t hbm_budget_bytes, int32_t max_slot
   s->prec = prec;
   s->stream = (hipStream_t)stream;
   XOD_TRY_B(s->runner.init(max_slots));
+  s->slot_busy.assign(max_slots, 0);
+  for (int i = 0; i < max_slots; ++i) {
+    hipStream_t st = nullptr;
+    XOD_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    s->slot_stream.push_back(st);
+  }
   *out = s.release();
+  return XOD_OK;
+}
+
+extern "C" xod_status xod_serve_set_solver(xod_server *s, xod_solver solver) {
+  SCHECK(s, "xod_serve_set_solver: null server");
+  SCHECK(solver == XOD_SOLVER_THOMAS || solver == XOD_SOLVER_CR,
+         "xod_serve_set_solver: unknown solver");
+  SCHECK(s->reqs.empty(), "xod_serve_set_solver: requests already submitted");
+  s->solver = solver;
   return XOD_OK;
 }
 
@@ -105,7 +132,7 @@ extern "C" xod_status xod_serve_destroy(xod_server *s) {
 extern "C" xod_status xod_serve_footprint(const xod_network *net, int32_t N, xod_precision prec,
                                           size_t *bytes) {
   SCHECK(net && bytes && N >= 1, "xod_serve_footprint: bad arguments");
-  *bytes = column_footprint(net, N, prec);
+  *bytes = column_footprint(net, N, prec) + cr_footprint(net, N, prec);
   return XOD_OK;
 }
 
@@ -144,7 +171,7 @@ extern "C" xod_status xod_serve_submit(xod_server *s, const xod_network *net,
     if (o->max_consec_rejects > 0) r.maxrej = o->max_consec_rejects;
     r.mixrule = o->use_mix_rule;
   }
-  r.footprint = column_footprint(net, N, s->prec);
+  r.footprint = s->footprint(net, N);
   if (r.footprint > s->budget) {
     set_error("xod_serve_submit: request footprint exceeds the whole HBM budget");
     return XOD_EINVAL;
@@ -166,6 +193,8 @@ static void finish(xod_server *s, Req &r, int state, xod_status st) {
     xod_column_destroy(r.col);
     r.col = nullptr;
   }
+  if (r.slot >= 0) s->slot_busy[r.slot] = 0;
+  r.slot = -1;
   s->used -= r.footprint;
 }
 
@@ -186,13 +215,22 @@ extern "C" xod_status xod_serve_step(xod_server *s, int32_t *n_active, int32_t *
     p.g_cgs = r.g;
     p.sigma_tau = r.sigma;
     s->queue.pop_front();
-    xod_status st = xod_column_create(r.net, &p, r.n0.data(), s->prec, s->stream, &r.col);
+    int slot = 0;
+    while (s->slot_busy[slot]) ++slot;   // a slot is free: active < max_slots
+    const bool cr = s->solver == XOD_SOLVER_CR;
+    xod_status st = xod_column_create(r.net, &p, r.n0.data(), s->prec,
+                                      cr ? s->slot_stream[slot] : s->stream, &r.col);
+    if (st == XOD_OK && cr) st = xod_column_set_solver(r.col, XOD_SOLVER_CR);
     if (st != XOD_OK) {
+      if (r.col) xod_column_destroy(r.col);
+      r.col = nullptr;
       r.state = 3;
       r.status = st;
       r.t_done = now_s();
       continue;
     }
+    s->slot_busy[slot] = 1;
+    r.slot = slot;
     s->used += r.footprint;
     double mix = 0.0;
     (void)xod_column_grid(r.col, nullptr, nullptr, nullptr, &mix);
@@ -213,10 +251,25 @@ extern "C" xod_status xod_serve_step(xod_server *s, int32_t *n_active, int32_t *
       cols[i] = r.col;
       dts[i] = r.dt;
     }
-    if (s->prec == XOD_FP64) {
+    if (s->prec == XOD_FP64 && s->solver == XOD_SOLVER_THOMAS) {
       // driver semantics: clipping, control statistics; y floors per request
       const Req &r0 = s->reqs.at(s->active[0]);
       XOD_TRY_B(s->runner.step(cols, dts.data(), true, r0.yfl, r0.ysig, s->stream, stats));
+    } else if (s->prec == XOD_FP64) {
+      // every request on its own stream: enqueue all, then wait for each
+      stats.assign(na * kStatLen, 0.0);
+      for (size_t i = 0; i < na; ++i) {
+        Req &r = s->reqs.at(s->active[i]);
+        int it, fb;
+        double res;
+        XOD_TRY_B(enqueue_solve(r.col, r.dt, &it, &fb, &res));
+        XOD_TRY_B(enqueue_update(r.col, true, r.yfl, r.ysig));
+      }
+      for (size_t i = 0; i < na; ++i) {
+        Req &r = s->reqs.at(s->active[i]);
+        XOD_HIP(hipStreamSynchronize(r.col->stream));
+        std::memcpy(&stats[i * kStatLen], r.col->stats_host, kStatLen * sizeof(double));
+      }
     } else {
       stats.assign(na * kStatLen, 0.0);
       for (size_t i = 0; i < na; ++i) {

@@ -13,7 +13,9 @@ at their shapes and sizes.
 """
 
 from .network import make_network, NETWORK_PRESETS
-from .column import make_column, COLUMN_PRESETS, make_config, make_batch
+from .column import (make_column, COLUMN_PRESETS, make_config, make_batch, make_request,
+                     poisson_arrivals)
 
-__all__ = ["make_network", "make_column", "make_config", "make_batch",
+__all__ = ["make_network", "make_column", "make_config", "make_batch", "make_request",
+           "poisson_arrivals",
            "NETWORK_PRESETS", "COLUMN_PRESETS"]

@@ -137,3 +137,19 @@ def make_batch(ncols=256, sizes=(90, 250, 594), pool=3, seed=4000,
                           Kzz_scale=ks)
         cols.append((net, col))
     return cols
+
+
+def make_request(j, net):
+    """Serving request j on the 594-species network `net`: the 150-layer
+    column of the largest configuration with its own T offset ~ U[-300, 300]
+    K, Kzz scale ~ log-U[0.1, 10] and initial abundances (seed 5,000,000 + j)."""
+    rng = np.random.default_rng(5_000_000 + j)
+    dT = float(rng.uniform(-300.0, 300.0))
+    ks = float(10.0 ** rng.uniform(-1.0, 1.0))
+    return make_column("c3", net, seed=5_000_000 + j, T_offset=dT, Kzz_scale=ks)
+
+
+def poisson_arrivals(n, rate, seed=5_000_000):
+    """Arrival times (s) of n requests at a Poisson rate (per second)."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))

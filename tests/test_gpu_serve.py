@@ -23,8 +23,9 @@ def _requests():
     return net, cols
 
 
+@pytest.mark.parametrize("solver", [0, 1])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_serve_results_equal_alone_and_in_the_mix(precision):
+def test_serve_results_equal_alone_and_in_the_mix(precision, solver):
     import paper_2512_06729_amd as xod
     stream = torch.cuda.current_stream().cuda_stream
     net, cols = _requests()
@@ -32,12 +33,13 @@ def test_serve_results_equal_alone_and_in_the_mix(precision):
     opts = dict(tol_rel=1e-6, t_end=1e14, max_steps=3000)
     alone = []
     for col in cols:
-        c = xod.Column(gnet, col, precision=precision, stream=stream)
+        c = xod.Column(gnet, col, precision=precision, stream=stream, solver=solver)
         r = xod.xod_integrate_to_steady_state(c, **opts)
         alone.append((c.state(), r))
         c.close()
     fp = xod.Server.footprint(gnet, max(c.N for c in cols), precision)
-    srv = xod.Server(hbm_budget_bytes=3 * fp, max_slots=2, precision=precision, stream=stream)
+    srv = xod.Server(hbm_budget_bytes=3 * fp, max_slots=2, precision=precision, stream=stream,
+                     solver=solver)
     ids = [srv.submit(gnet, cols[0], **opts), srv.submit(gnet, cols[1], **opts)]
     max_active = 0
     it = 0
