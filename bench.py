@@ -136,16 +136,20 @@ def bench_batch(xod, torch, args):
     stream = torch.cuda.current_stream().cuda_stream
     t0 = time.perf_counter()
     cols = synth.make_batch(args.batch_cols)
+    progress(f"batch: {len(cols)} columns generated")
     gnets, gcols = {}, []
-    for net, col in cols:
+    for i, (net, col) in enumerate(cols):
         if id(net) not in gnets:
             gnets[id(net)] = xod.Network(net)
         gcols.append(xod.Column(gnets[id(net)], col, stream=stream))
+        if (i + 1) % 64 == 0:
+            progress(f"batch: {i + 1} columns on the device")
     batch = xod.Batch(gcols)
     setup = time.perf_counter() - t0
     dts = np.full(len(gcols), args.dt)
     batch.step(dts)
     torch.cuda.synchronize()
+    progress("batch: warm-up step done")
     k = args.batch_steps
     t0 = time.perf_counter()
     for _ in range(k):
@@ -200,6 +204,8 @@ def bench_serve(xod, torch, args, precision, gnet, net):
                 continue
             o = srv.poll(rid)
             if o["state"] >= xod.Server.DONE:
+                progress(f"serve ({'fp64' if precision == xod.XOD_FP64 else 'mixed'}): request "
+                         f"{j} done after {o['steps']} steps, latency {o['latency_s']:.2f} s")
                 done[rid] = o
                 lat.append(o["latency_s"])
                 steps.append(o["steps"])
@@ -230,6 +236,12 @@ def timed_steps(xod, torch, gcol, dt, steps):
 
 
 KERNELS = ("panel", "update", "gemm", "prologue", "solve", "jacobian", "rates", "rhs")
+T_START = time.perf_counter()
+
+
+def progress(msg):
+    """One line per finished stage on stderr (the result line is stdout)."""
+    print(f"[bench {time.perf_counter() - T_START:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -247,10 +259,11 @@ def main():
     ap.add_argument("--batch-cols", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--skip-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=8)
+    ap.add_argument("--serve-requests", type=int, default=4)
     ap.add_argument("--serve-rate", type=float, default=5.0)
-    ap.add_argument("--serve-slots", type=int, default=8)
-    ap.add_argument("--serve-timeout", type=float, default=150.0)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-timeout", type=float, default=70.0)
+    ap.add_argument("--serve-fp64-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): columns are "
@@ -270,6 +283,7 @@ def main():
     solver = xod.XOD_SOLVER_CR if args.solver == "cr" else xod.XOD_SOLVER_THOMAS
     gcol = xod.Column(gnet, col, precision=xod.XOD_FP64, stream=stream, solver=solver)
 
+    progress("config-3 column on the device")
     for _ in range(args.warmup):
         xod.xod_step(gcol, args.dt)
     torch.cuda.synchronize()
@@ -352,6 +366,7 @@ def main():
         "ms_per_step_with_kernel_events": 1e3 * el_prof / args.steps,
     }
     gcol.close()
+    progress(f"FP64 steps: {steps_per_s:.2f} steps/s")
     if not args.skip_thomas and args.solver == "cr":
         gt = xod.Column(gnet, col, precision=xod.XOD_FP64, stream=stream)
         xod.xod_step(gt, args.dt)
@@ -362,9 +377,13 @@ def main():
         gt.close()
     if not args.skip_mixed:
         line["mixed"] = bench_mixed(xod, torch, gnet, col, args, solver)
+        progress(f"mixed steps: {line['mixed']['value']:.2f} steps/s")
     if not args.skip_serve:
         s64, n64 = bench_serve(xod, torch, args, xod.XOD_FP64, gnet, net)
-        smx, nmx = bench_serve(xod, torch, args, xod.XOD_MIXED, gnet, net)
+        if args.serve_fp64_only:
+            smx, nmx = {}, {}
+        else:
+            smx, nmx = bench_serve(xod, torch, args, xod.XOD_MIXED, gnet, net)
         diffs = {}
         for floor in (1e-30, 1e-20, 1e-10):
             errs = []
@@ -373,12 +392,15 @@ def main():
                     keep = np.abs(a) > floor * np.abs(a).sum(axis=1, keepdims=True)
                     errs.append(float(np.max(np.abs(nmx[j] - a)[keep] / np.abs(a)[keep])))
             diffs[f"y>{floor:g}"] = max(errs) if errs else None
-        smx["max_rel_diff_vs_fp64_steady_state"] = diffs
-        line["serve"] = {"fp64": s64, "mixed": smx}
+        if smx:
+            smx["max_rel_diff_vs_fp64_steady_state"] = diffs
+        line["serve"] = {"fp64": s64, "mixed": smx or None}
     if not args.skip_batch:
         line["batch"] = bench_batch(xod, torch, args)
+        progress(f"batch: {line['batch']['value']:.1f} column-steps/s")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(net, col)
+        progress("oracle timed")
     print(json.dumps(line), flush=True)
 
 

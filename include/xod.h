@@ -264,6 +264,11 @@ xod_status xod_last_error(char *buf, size_t len);
 
 /* Kernel options (process-wide; for tests and tuning).
  *   "gemm": 0 = VALU FMA Schur update, 1 = MFMA Schur update (default).
+ *   "update32": 1 = MFMA trailing update in 32-column strips by four-wave
+ *            work-groups when a launch updates many blocks (default);
+ *            0 = always 16-column strips by 16-wave work-groups.
+ *   "lookahead": 1 = captured cyclic-reduction inversions run panel p+1 on
+ *            a second branch beside the rest of update p (default 0).
  *   "graph": 1 = the cyclic-reduction factor and solve launch sequences of a
  *            column are captured once into HIP graphs (kernel nodes only)
  *            and replayed (default); 0 = launched one by one.  Graphs are

@@ -107,6 +107,16 @@ extern "C" xod_status xod_set_option(const char *name, int64_t value) {
     options().gemm_mfma = (int)value;
     return XOD_OK;
   }
+  if (std::strcmp(name, "lookahead") == 0) {
+    XOD_CHECK(value == 0 || value == 1, "xod_set_option: lookahead must be 0 or 1");
+    options().lookahead = (int)value;
+    return XOD_OK;
+  }
+  if (std::strcmp(name, "update32") == 0) {
+    XOD_CHECK(value == 0 || value == 1, "xod_set_option: update32 must be 0 or 1");
+    options().update32 = (int)value;
+    return XOD_OK;
+  }
   if (std::strcmp(name, "graph") == 0) {
     XOD_CHECK(value == 0 || value == 1, "xod_set_option: graph must be 0 or 1");
     options().graph = (int)value;
@@ -197,7 +207,10 @@ extern "C" xod_status xod_network_create(const xod_network_desc *d, xod_network 
 
   // Jacobian pattern: entry (y, x) collects (r, nu_{y,r}) for every reaction
   // r in which x takes part and y changes.
+  // A contribution names the derivative slot 6 r + u of reaction r with
+  // respect to its u-th distinct species (rsp lists them, -1 padded).
   std::map<std::pair<int, int>, std::vector<std::pair<int, double>>> ent;
+  std::vector<int> rsp((size_t)R * 6, -1);
   for (int r = 0; r < R; ++r) {
     std::vector<int> xs;
     for (int j = 0; j < XOD_MAX_REAC; ++j) {
@@ -208,23 +221,25 @@ extern "C" xod_status xod_network_create(const xod_network_desc *d, xod_network 
       const int y = d->prod[r * XOD_MAX_PROD + j];
       if (y >= 0 && std::find(xs.begin(), xs.end(), y) == xs.end()) xs.push_back(y);
     }
+    for (size_t u = 0; u < xs.size(); ++u) rsp[(size_t)r * 6 + u] = xs[u];
     for (auto &kv : nu_r[r]) {
       if (kv.second == 0.0) continue;
-      for (int x : xs) ent[{kv.first, x}].push_back({r, kv.second});
+      for (size_t u = 0; u < xs.size(); ++u)
+        ent[{kv.first, xs[u]}].push_back({6 * r + (int)u, kv.second});
     }
   }
-  std::vector<int> jmap((size_t)S * S, -1), jptr(1, 0), jc_r;
+  std::vector<int> jmap((size_t)S * S, -1), jptr(1, 0), jc_ru;
   std::vector<double> jc_nu;
   for (auto &kv : ent) {
     jmap[(size_t)kv.first.first * S + kv.first.second] = (int)jptr.size() - 1;
     for (auto &e : kv.second) {
-      jc_r.push_back(e.first);
+      jc_ru.push_back(e.first);
       jc_nu.push_back(e.second);
     }
-    jptr.push_back((int)jc_r.size());
+    jptr.push_back((int)jc_ru.size());
   }
   net->nnz = (int)jptr.size() - 1;
-  net->ncontrib = (int)jc_r.size();
+  net->ncontrib = (int)jc_ru.size();
 
   xod_network *n = net.get();
   XOD_TRY(nalloc(n, &n->rtype, R, d->rtype));
@@ -241,7 +256,8 @@ extern "C" xod_status xod_network_create(const xod_network_desc *d, xod_network 
   XOD_TRY(nalloc(n, &n->inc_nu, inc_nu.size(), inc_nu.data()));
   XOD_TRY(nalloc(n, &n->jmap, jmap.size(), jmap.data()));
   XOD_TRY(nalloc(n, &n->jptr, jptr.size(), jptr.data()));
-  XOD_TRY(nalloc(n, &n->jc_r, jc_r.size(), jc_r.data()));
+  XOD_TRY(nalloc(n, &n->jc_ru, jc_ru.size(), jc_ru.data()));
+  XOD_TRY(nalloc(n, &n->rsp, rsp.size(), rsp.data()));
   XOD_TRY(nalloc(n, &n->jc_nu, jc_nu.size(), jc_nu.data()));
   *out = net.release();
   return XOD_OK;
@@ -326,6 +342,7 @@ extern "C" xod_status xod_column_create(const xod_network *net, const xod_profil
   XOD_TRY(calloc_(c, &c->kf, NR));
   XOD_TRY(calloc_(c, &c->kr, NR));
   XOD_TRY(calloc_(c, &c->w, NR));
+  XOD_TRY(calloc_(c, &c->dwd, 6 * NR));
   XOD_TRY(calloc_(c, &c->gs, NL));
   XOD_TRY(calloc_(c, &c->a, NL));
   XOD_TRY(calloc_(c, &c->c, NL));
@@ -466,7 +483,7 @@ extern "C" xod_status xod_jacobian(xod_column *col, const double *kf, const doub
   a.B = B;
   a.a = av;
   a.c = cv;
-  XOD_HIP(launch_jacobian(OneCol{a}, 1, col->N, col->ld, false, col->stream));
+  XOD_HIP(launch_jacobian(OneCol{a}, 1, col->N, col->R, col->ld, false, col->stream));
   return XOD_OK;
 }
 
@@ -545,7 +562,7 @@ size_t column_footprint(const xod_network *net, int N, xod_precision prec) {
   size_t b = 0;
   b += 8 * (6 * n + 4 * n * S);                 // profile + grid vectors
   b += 8 * (6 * n * S);                         // n, ntmp, f, x, resid, dx
-  b += 8 * (3 * n * R);                         // kf, kr, w
+  b += 8 * (9 * n * R);                         // kf, kr, w, rate derivatives
   b += 8 * (4 * n * ld) + 4 * (2 * n * ld);     // gs, a, c, rs, piv, rstep
   b += 8 * n * ld * ld;                         // FP64 blocks
   if (prec == XOD_MIXED) b += 4 * n * ld * ld + 8 * 2 * n * ld;
@@ -595,7 +612,7 @@ xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, do
   XOD_HIP(launch_rhs(one, 1, c->N, c->R, c->S, c->stream));
   const bool cr = c->solver == XOD_SOLVER_CR;
   if (c->prec == XOD_FP64) {
-    XOD_HIP(launch_jacobian(one, 1, c->N, c->ld, false, c->stream));
+    XOD_HIP(launch_jacobian(one, 1, c->N, c->R, c->ld, false, c->stream));
     if (cr)
       XOD_TRY(c->cr64->factor(c));
     else
@@ -611,7 +628,7 @@ xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, do
   // Mixed precision: row-scaled FP32 Schur complements, FP64 refinement with a
   // matrix-free FP64 residual; FP64 refactorisation if refinement stalls.
   const size_t NSb = (size_t)c->N * c->S * sizeof(double);
-  XOD_HIP(launch_jacobian(one, 1, c->N, c->ld, true, c->stream));
+  XOD_HIP(launch_jacobian(one, 1, c->N, c->R, c->ld, true, c->stream));
   if (cr)
     XOD_TRY(c->cr32->factor(c));
   else
@@ -653,7 +670,7 @@ xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, do
     return XOD_OK;
   }
   *fallback = 1;
-  XOD_HIP(launch_jacobian(one, 1, c->N, c->ld, false, c->stream));
+  XOD_HIP(launch_jacobian(one, 1, c->N, c->R, c->ld, false, c->stream));
   if (cr)
     XOD_TRY(c->cr64->factor(c));
   else

@@ -99,7 +99,7 @@ xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double
     ManyCols acc{d_args + base};
     XOD_HIP(launch_rates(acc, nc, maxN, maxR, s));
     XOD_HIP(launch_rhs(acc, nc, maxN, maxR, maxS, s));
-    XOD_HIP(launch_jacobian(acc, nc, maxN, ld, false, s));
+    XOD_HIP(launch_jacobian(acc, nc, maxN, maxR, ld, false, s));
     XOD_HIP(launch_factor_fp64(acc, nc, maxN, ld, s));
     for (int j = 0; j < nc; ++j) {
       xod_column *c = cols[idx[j]];

@@ -24,7 +24,7 @@ struct xod_network {
   double *params = nullptr, *nasa7 = nullptr, *mass = nullptr;
   int *inc_ptr = nullptr, *inc_r = nullptr;
   double *inc_nu = nullptr;
-  int *jmap = nullptr, *jptr = nullptr, *jc_r = nullptr;
+  int *jmap = nullptr, *jptr = nullptr, *jc_ru = nullptr, *rsp = nullptr;
   double *jc_nu = nullptr;
   std::vector<double> mass_h;
   int nnz = 0, ncontrib = 0;
@@ -43,6 +43,7 @@ struct xod_column {
   double *ngas = nullptr, *tau = nullptr, *lnpref = nullptr, *g = nullptr, *trl = nullptr,
          *trd = nullptr, *tru = nullptr, *dz = nullptr, *dzh = nullptr, *mix = nullptr;
   double mix_time = 0.0;
+  double *dwd = nullptr;   // [N*R*6] reaction-rate derivatives of the last Jacobian
   double *n = nullptr, *ntmp = nullptr, *kf = nullptr, *kr = nullptr, *w = nullptr,
          *f = nullptr, *x = nullptr, *gs = nullptr, *resid = nullptr, *dx = nullptr;
   double *B = nullptr;
@@ -86,8 +87,10 @@ struct xod_column {
     a_.inc_nu = net->inc_nu;
     a_.jmap = net->jmap;
     a_.jptr = net->jptr;
-    a_.jc_r = net->jc_r;
+    a_.jc_ru = net->jc_ru;
     a_.jc_nu = net->jc_nu;
+    a_.rsp = net->rsp;
+    a_.dwd = dwd;
     a_.T = T;
     a_.ngas = ngas;
     a_.tau = tau;

@@ -313,17 +313,18 @@ void launch_panel(const MA &ma, int nmat, int ld, int k, int p, hipStream_t s) {
 // rows (U) before overwriting them is race-free.
 constexpr int kUpdThreads = 1024;   // 16 waves share the row tiles of a strip
 
+// Strips s0 + blockIdx.x are updated, except the panel's own and those in
+// [skip0, skip1).  A full launch (s0 = 0) keeps strip s on work-group s, so a
+// strip stays on the same XCD for every panel.
 template <class MA, class T, bool kMfma>
-__global__ void __launch_bounds__(kUpdThreads) k_update(MA ma, int k, int p, int ld) {
+__global__ void __launch_bounds__(kUpdThreads) k_update(MA ma, int k, int p, int ld, int s0,
+                                                        int skip0, int skip1) {
   MatRef<T> mat;
   if (!ma(blockIdx.y, k, mat)) return;
   const int j0 = p * kNB;
-  // Strip s is always work-group s of the launch (all ld/16 strips are
-  // launched, the panel's own strips return), so a strip stays on the same
-  // XCD for every panel.
-  const int s = blockIdx.x;
+  const int s = s0 + blockIdx.x;
   const int c0 = s * kStrip;
-  if (c0 >= ld || (c0 >= j0 && c0 < j0 + kNB)) return;
+  if (c0 >= ld || (c0 >= j0 && c0 < j0 + kNB) || (s >= skip0 && s < skip1)) return;
   T *W = mat.W;
   const int *piv = mat.piv + j0;
   const int *rstep = mat.rstep;
@@ -401,15 +402,106 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(MA ma, int k, int p, int
   }
 }
 
+// Trailing update in 32-column strips (the panel width): one work-group of
+// four waves per (strip, block); each wave walks the 16-row tiles
+// wid, wid+4, ... of the strip, loading the next tile's operands before the
+// current tile's MFMAs.  The strip's pivot rows U (32 x 32) are read into
+// LDS and then into registers before any row of the strip is written.
+constexpr int kUpd32Threads = 256;
+
 template <class MA, class T>
-void launch_update(const MA &ma, int nmat, int ld, int k, int p, hipStream_t s) {
-  const int nupd = ld / kStrip;   // every strip; the panel's own return
-  if (options().gemm_mfma)
-    hipLaunchKernelGGL((k_update<MA, T, true>), dim3(nupd, nmat), dim3(kUpdThreads), 0, s, ma, k,
-                       p, ld);
+__global__ void __launch_bounds__(kUpd32Threads) k_update32(MA ma, int k, int p, int ld, int q0,
+                                                            int skip) {
+  MatRef<T> mat;
+  if (!ma(blockIdx.y, k, mat)) return;
+  const int q = q0 + blockIdx.x;
+  const int c0 = q * kNB;
+  if (q == p || q == skip || c0 >= ld) return;
+  const int j0 = p * kNB;
+  T *W = mat.W;
+  const int *piv = mat.piv + j0;
+  const int *rstep = mat.rstep;
+  __shared__ T sU[kNB][kNB + 1];
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  for (int e = t; e < kNB * kNB; e += blockDim.x) {
+    const int r = e / kNB, col = e % kNB;
+    sU[r][col] = W[(size_t)piv[r] * ld + c0 + col];
+  }
+  __syncthreads();
+  // B operand of the two 16-column halves, 8 k-steps each: U[4kk + l/16][16h + l%16]
+  T bf[2][kNB / 4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int kk = 0; kk < kNB / 4; ++kk) bf[h][kk] = sU[4 * kk + (lane >> 4)][16 * h + (lane & 15)];
+  __syncthreads();   // every wave holds U before any pivot row of the strip is rewritten
+
+  const int ntile = ld / 16;
+  T av[kNB / 4], cv[2][4];
+  auto load = [&](int tile) {
+    const int rbase = tile * 16;
+    const T *Arow = W + (size_t)(rbase + (lane & 15)) * ld + j0;
+#pragma unroll
+    for (int kk = 0; kk < kNB / 4; ++kk) av[kk] = Arow[4 * kk + (lane >> 4)];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = rbase + mfma_row(T(0), lane, i);
+      const int st = rstep[row];
+      const bool piv_here = st >= j0 && st < j0 + kNB;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        cv[h][i] = piv_here ? T(0) : W[(size_t)row * ld + c0 + 16 * h + (lane & 15)];
+    }
+  };
+  int tile = wid;
+  if (tile < ntile) load(tile);
+  while (tile < ntile) {
+    typename Vec4<T>::type acc[2];
+    T a_now[kNB / 4];
+#pragma unroll
+    for (int kk = 0; kk < kNB / 4; ++kk) a_now[kk] = av[kk];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[h][i] = cv[h][i];
+    const int cur = tile;
+    tile += 4;
+    if (tile < ntile) load(tile);   // next tile's operands in flight during the MFMAs
+#pragma unroll
+    for (int kk = 0; kk < kNB / 4; ++kk)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) acc[h] = mfma16(a_now[kk], bf[h][kk], acc[h]);
+    const int rbase = cur * 16;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = rbase + mfma_row(T(0), lane, i);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) W[(size_t)row * ld + c0 + 16 * h + (lane & 15)] = acc[h][i];
+    }
+  }
+}
+
+// Strips [s0, s0 + nstrip) minus [skip0, skip1) (and the panel's own).
+template <class MA, class T>
+void launch_update(const MA &ma, int nmat, int ld, int k, int p, hipStream_t s, int s0 = 0,
+                   int nstrip = -1, int skip0 = 0, int skip1 = 0) {
+  if (nstrip < 0) nstrip = ld / kStrip;
+  if (nstrip <= 0) return;
+  constexpr int spp = kNB / kStrip;
+  // Four-wave 32-column strips when the launch has work-groups enough to
+  // fill the chip (many blocks); 16-wave 16-column strips keep more waves
+  // per block in flight when only a few blocks are updated.
+  const bool many = (size_t)nmat * (ld / kNB) >= 512;
+  if (options().gemm_mfma && options().update32 && many && s0 % spp == 0 &&
+      nstrip % spp == 0 && skip0 % spp == 0 && skip1 - skip0 <= spp)
+    hipLaunchKernelGGL((k_update32<MA, T>), dim3(nstrip / spp, nmat), dim3(kUpd32Threads), 0, s,
+                       ma, k, p, ld, s0 / spp, skip1 > skip0 ? skip0 / spp : -1);
+  else if (options().gemm_mfma)
+    hipLaunchKernelGGL((k_update<MA, T, true>), dim3(nstrip, nmat), dim3(kUpdThreads), 0, s, ma,
+                       k, p, ld, s0, skip0, skip1);
   else
-    hipLaunchKernelGGL((k_update<MA, T, false>), dim3(nupd, nmat), dim3(kUpdThreads), 0, s, ma,
-                       k, p, ld);
+    hipLaunchKernelGGL((k_update<MA, T, false>), dim3(nstrip, nmat), dim3(kUpdThreads), 0, s,
+                       ma, k, p, ld, s0, skip0, skip1);
 }
 
 template <class Acc, class T>
@@ -438,23 +530,54 @@ hipError_t launch_factor(const Acc &acc, int ncols, int maxN, int ld, hipStream_
 }
 
 template <class T>
-hipError_t launch_invert_list(const MatRef<T> *dlist, int count, int ld, hipStream_t s) {
+hipError_t launch_invert_list(const MatRef<T> *dlist, int count, int ld, hipStream_t s,
+                              hipStream_t s2, hipEvent_t e1, hipEvent_t e2) {
   if (count <= 0) return hipSuccess;
   const ListMats<T> ma{dlist};
   const int npanel = ld / kNB;
   const bool prof = options().profile != 0;
+  if (!s2 || prof) {
+    for (int p = 0; p < npanel; ++p) {
+      if (prof) prof_begin(kProfPanel, s);
+      launch_panel<ListMats<T>, T>(ma, count, ld, 0, p, s);
+      if (prof) prof_end(kProfPanel, s);
+      if (prof) prof_begin(kProfUpdate, s);
+      launch_update<ListMats<T>, T>(ma, count, ld, 0, p, s);
+      if (prof) prof_end(kProfUpdate, s);
+    }
+    return hipGetLastError();
+  }
+  // Look-ahead: after panel p, first update the strips of panel p+1 (on s),
+  // then factor panel p+1 on s while the remaining strips of update p run on
+  // s2.  Update p+1 waits for both.  The two branches touch disjoint columns;
+  // the only shared state they read is the pivot bookkeeping of panel p,
+  // which neither changes.
+  const int spp = kNB / kStrip;   // strips per panel
   for (int p = 0; p < npanel; ++p) {
-    if (prof) prof_begin(kProfPanel, s);
-    launch_panel<ListMats<T>, T>(ma, count, ld, 0, p, s);
-    if (prof) prof_end(kProfPanel, s);
-    if (prof) prof_begin(kProfUpdate, s);
-    launch_update<ListMats<T>, T>(ma, count, ld, 0, p, s);
-    if (prof) prof_end(kProfUpdate, s);
+    if (p == 0) launch_panel<ListMats<T>, T>(ma, count, ld, 0, 0, s);
+    if (p + 1 < npanel) {
+      launch_update<ListMats<T>, T>(ma, count, ld, 0, p, s, (p + 1) * spp, spp);
+      hipError_t e = hipEventRecord(e1, s);
+      if (e != hipSuccess) return e;
+      e = hipStreamWaitEvent(s2, e1, 0);
+      if (e != hipSuccess) return e;
+      launch_update<ListMats<T>, T>(ma, count, ld, 0, p, s2, 0, -1, (p + 1) * spp,
+                                    (p + 2) * spp);
+      e = hipEventRecord(e2, s2);
+      if (e != hipSuccess) return e;
+      launch_panel<ListMats<T>, T>(ma, count, ld, 0, p + 1, s);
+      e = hipStreamWaitEvent(s, e2, 0);
+      if (e != hipSuccess) return e;
+    } else {
+      launch_update<ListMats<T>, T>(ma, count, ld, 0, p, s);
+    }
   }
   return hipGetLastError();
 }
-template hipError_t launch_invert_list<double>(const MatRef<double> *, int, int, hipStream_t);
-template hipError_t launch_invert_list<float>(const MatRef<float> *, int, int, hipStream_t);
+template hipError_t launch_invert_list<double>(const MatRef<double> *, int, int, hipStream_t,
+                                               hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_invert_list<float>(const MatRef<float> *, int, int, hipStream_t,
+                                              hipStream_t, hipEvent_t, hipEvent_t);
 
 template <class Acc>
 hipError_t launch_factor_fp64(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s) {

@@ -251,6 +251,23 @@ __device__ __forceinline__ double dwdn(const ColArgs &c, int k, int r, int x) {
   return c.kf_in[o] * df - c.kr_in[o] * dr;
 }
 
+// dw_r/dn_x for every reaction and each of its distinct species x = rsp[6r+u]
+// (zero for unused slots): the Jacobian entries then gather one value per
+// contribution.
+template <class Acc>
+__global__ void __launch_bounds__(256) k_dwd(Acc acc) {
+  const ColArgs &c = acc(blockIdx.z);
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (r >= c.R || k >= c.N) return;
+  double *out = c.dwd + ((size_t)k * c.R + r) * 6;
+#pragma unroll
+  for (int u = 0; u < 6; ++u) {
+    const int x = c.rsp[r * 6 + u];
+    out[u] = x >= 0 ? dwdn(c, k, r, x) : 0.0;
+  }
+}
+
 constexpr int kJacMaxPer = kMaxLd / 64;
 
 template <class Acc, bool kMixed>
@@ -276,7 +293,8 @@ __global__ void __launch_bounds__(256) k_jac(Acc acc) {
         const int idx = c.jmap[(size_t)i * S + j];
         if (idx >= 0) {
           double s = 0.0;
-          for (int e = c.jptr[idx]; e < c.jptr[idx + 1]; ++e) s += c.jc_nu[e] * dwdn(c, k, c.jc_r[e], j);
+          const double *dk = c.dwd + (size_t)k * c.R * 6;
+          for (int e = c.jptr[idx]; e < c.jptr[idx + 1]; ++e) s += c.jc_nu[e] * dk[c.jc_ru[e]];
           v = -s;
         }
         if (i == j) v += 1.0 / c.dt - c.trd[so];
@@ -308,10 +326,13 @@ __global__ void __launch_bounds__(256) k_jac(Acc acc) {
 }
 
 template <class Acc>
-hipError_t launch_jacobian(const Acc &acc, int ncols, int maxN, int ld, bool mixed, hipStream_t s) {
+hipError_t launch_jacobian(const Acc &acc, int ncols, int maxN, int maxR, int ld, bool mixed,
+                           hipStream_t s) {
   if (maxN <= 0) return hipSuccess;
   dim3 grid((ld + 3) / 4, maxN, ncols);
   if (options().profile) prof_begin(kProfJac, s);
+  if (maxR > 0)
+    hipLaunchKernelGGL(k_dwd<Acc>, dim3((maxR + 255) / 256, maxN, ncols), dim3(256), 0, s, acc);
   if (mixed)
     hipLaunchKernelGGL((k_jac<Acc, true>), grid, dim3(256), 0, s, acc);
   else
@@ -324,7 +345,9 @@ template hipError_t launch_rates<OneCol>(const OneCol &, int, int, int, hipStrea
 template hipError_t launch_rates<ManyCols>(const ManyCols &, int, int, int, hipStream_t);
 template hipError_t launch_rhs<OneCol>(const OneCol &, int, int, int, int, hipStream_t);
 template hipError_t launch_rhs<ManyCols>(const ManyCols &, int, int, int, int, hipStream_t);
-template hipError_t launch_jacobian<OneCol>(const OneCol &, int, int, int, bool, hipStream_t);
-template hipError_t launch_jacobian<ManyCols>(const ManyCols &, int, int, int, bool, hipStream_t);
+template hipError_t launch_jacobian<OneCol>(const OneCol &, int, int, int, int, bool,
+                                            hipStream_t);
+template hipError_t launch_jacobian<ManyCols>(const ManyCols &, int, int, int, int, bool,
+                                              hipStream_t);
 
 }  // namespace xod

@@ -45,9 +45,15 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmOp<T> *ops, int
   const int wr = wid >> 2, wc = wid & 3;
   __shared__ T As[2][kGemmTile][kGemmK + 1];
   __shared__ T Bs[2][kGemmK][kGemmTile + 2];
+  __shared__ int sbg[2][kMaxLd];   // the row gathers of B and B2
   typename Vec4<T>::type acc = {0, 0, 0, 0};
   const int nk1 = ld / kGemmK;
   const int nk = g.A2 ? 2 * nk1 : nk1;
+  for (int m = threadIdx.x; m < ld; m += blockDim.x) {
+    sbg[0][m] = g.bg ? in_block(g.bg[m], ld) : m;
+    sbg[1][m] = g.bg2 ? in_block(g.bg2[m], ld) : m;
+  }
+  __syncthreads();
   // this thread's staging element: A (row t/16, k t%16), B (k t/64, col t%64)
   const int ar = t / kGemmK, ak = t % kGemmK;
   const int bk = t / kGemmTile, bc = t % kGemmTile;
@@ -57,10 +63,9 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmOp<T> *ops, int
     const bool second = kt >= nk1;
     const T *A = second ? g.A2 : g.A;
     const T *B = second ? g.B2 : g.B;
-    const int *bg = second ? g.bg2 : g.bg;
     const int k0 = (second ? kt - nk1 : kt) * kGemmK;
     ra = arow_ok ? A[(size_t)(tm0 + ar) * ld + k0 + ak] : T(0);
-    const int brow = bg ? in_block(bg[k0 + bk], ld) : k0 + bk;
+    const int brow = sbg[second ? 1 : 0][k0 + bk];
     rb = bcol_ok ? B[(size_t)brow * ld + tn0 + bc] : T(0);
   };
   gload(0);

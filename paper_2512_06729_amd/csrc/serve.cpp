@@ -7,10 +7,11 @@
 //      workspace stay resident on the device until the request retires);
 //   2. advances every resident request by one adaptive backward-Euler step
 //      with its own dt.  With the cyclic-reduction solver (default) every
-//      slot has its own HIP stream: all FP64 steps are enqueued first and
-//      then awaited, so the requests' kernels overlap on the device; mixed
-//      requests run their refinement loops one after another.  With block
-//      Thomas, FP64 requests share batched launches on the server stream;
+//      slot has its own HIP stream and each resident request's step is
+//      driven by its own host thread, so the requests' kernels overlap on
+//      the device (mixed-precision refinement waits only on its own
+//      stream).  With block Thomas, FP64 requests share batched launches on
+//      the server stream and mixed ones run one after another;
 //   3. applies each request's step control and retires converged or failed
 //      requests: the final state is copied to the host, the slot and its
 //      memory are freed, and the latency (completion - submission) recorded.
@@ -20,6 +21,9 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <future>
+#include <string>
+#include <utility>
 #include <map>
 #include <memory>
 #include <vector>
@@ -255,20 +259,35 @@ extern "C" xod_status xod_serve_step(xod_server *s, int32_t *n_active, int32_t *
       // driver semantics: clipping, control statistics; y floors per request
       const Req &r0 = s->reqs.at(s->active[0]);
       XOD_TRY_B(s->runner.step(cols, dts.data(), true, r0.yfl, r0.ysig, s->stream, stats));
-    } else if (s->prec == XOD_FP64) {
-      // every request on its own stream: enqueue all, then wait for each
+    } else if (s->solver == XOD_SOLVER_CR) {
+      // every request on its own stream, driven by its own host thread (the
+      // mixed-precision refinement waits on its stream between iterations),
+      // so the requests' kernels overlap on the device
       stats.assign(na * kStatLen, 0.0);
+      std::vector<std::future<std::pair<xod_status, std::string>>> tasks;
       for (size_t i = 0; i < na; ++i) {
-        Req &r = s->reqs.at(s->active[i]);
-        int it, fb;
-        double res;
-        XOD_TRY_B(enqueue_solve(r.col, r.dt, &it, &fb, &res));
-        XOD_TRY_B(enqueue_update(r.col, true, r.yfl, r.ysig));
+        Req *r = &s->reqs.at(s->active[i]);
+        double *out = &stats[i * kStatLen];
+        tasks.push_back(std::async(std::launch::async, [r, out]() {
+          int it, fb;
+          double res;
+          xod_status st = enqueue_solve(r->col, r->dt, &it, &fb, &res);
+          if (st == XOD_OK) st = run_update(r->col, true, r->yfl, r->ysig, out);
+          return std::make_pair(st, st == XOD_OK ? std::string() : last_error());
+        }));
       }
-      for (size_t i = 0; i < na; ++i) {
-        Req &r = s->reqs.at(s->active[i]);
-        XOD_HIP(hipStreamSynchronize(r.col->stream));
-        std::memcpy(&stats[i * kStatLen], r.col->stats_host, kStatLen * sizeof(double));
+      xod_status first = XOD_OK;
+      std::string msg;
+      for (auto &t : tasks) {
+        auto res = t.get();
+        if (res.first != XOD_OK && first == XOD_OK) {
+          first = res.first;
+          msg = res.second;
+        }
+      }
+      if (first != XOD_OK) {
+        set_error(msg);
+        return first;
       }
     } else {
       stats.assign(na * kStatLen, 0.0);

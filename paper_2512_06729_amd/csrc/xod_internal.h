@@ -31,8 +31,9 @@ struct ColArgs {
   const double *params;
   const int *inc_ptr, *inc_r;
   const double *inc_nu;
-  const int *jmap, *jptr, *jc_r;
+  const int *jmap, *jptr, *jc_ru;   // contribution e: slot jc_ru[e] = 6 r + u
   const double *jc_nu;
+  const int *rsp;                   // [R*6] distinct species of each reaction
   // grid (device, owned by the column)
   const double *T, *ngas, *tau, *lnpref, *g, *trl, *trd, *tru;
   // operands
@@ -45,6 +46,7 @@ struct ColArgs {
   int *piv;          // [N*ld] pivot row of each column
   int *rstep;        // [N*ld] pivot step of each row (inverse of piv)
   double *x;         // solve vector [N*S] (in/out)
+  double *dwd;       // [N*R*6] dw_r/dn_x for the distinct species x = rsp[6r+u]
   double *gs;        // solve scratch [N*ld]
   int *flag;         // [4]: singular layer, singular column, nonfinite, spare
 };
@@ -78,6 +80,8 @@ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 // Process-wide kernel options.
 struct Options {
   int gemm_mfma = 1;
+  int update32 = 1;       // trailing update in panel-wide strips (0: 16-wide)
+  int lookahead = 0;      // captured inversions overlap panel p+1 with update p
   int graph = 1;          // replay captured launch sequences (cyclic reduction)
   int profile = 0;        // record HIP events around profiled launches
   int profile_every = 1;  // profile layers k with k % profile_every == 0
@@ -101,7 +105,7 @@ hipError_t launch_rates(const Acc &acc, int ncols, int maxN, int maxR, hipStream
 template <class Acc>
 hipError_t launch_rhs(const Acc &acc, int ncols, int maxN, int maxR, int maxS, hipStream_t s);
 template <class Acc>
-hipError_t launch_jacobian(const Acc &acc, int ncols, int maxN, int ld, bool mixed,
+hipError_t launch_jacobian(const Acc &acc, int ncols, int maxN, int maxR, int ld, bool mixed,
                            hipStream_t s);
 template <class Acc>
 hipError_t launch_factor_fp64(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s);
@@ -131,9 +135,14 @@ struct MatRef {
 };
 
 // Invert `count` ld x ld blocks listed in dlist (device array).  rstep of
-// every listed block must hold INT_MAX on entry.
+// every listed block must hold INT_MAX on entry.  With a second stream s2
+// (and two events), the trailing update of each panel is split so that the
+// next panel's factorisation overlaps the rest of the update (s2 joins s
+// before the call returns its last launch).
 template <class T>
-hipError_t launch_invert_list(const MatRef<T> *dlist, int count, int ld, hipStream_t s);
+hipError_t launch_invert_list(const MatRef<T> *dlist, int count, int ld, hipStream_t s,
+                              hipStream_t s2 = nullptr, hipEvent_t e1 = nullptr,
+                              hipEvent_t e2 = nullptr);
 
 // Batched dense product on ld x ld row-major blocks:
 //   C = (beta ? C : 0) + alpha * (A * B[bg] + A2 * B2[bg2])

@@ -185,3 +185,25 @@ def test_cr_graph_replay_matches_direct_launches(precision):
             np.testing.assert_array_equal(ga.state(), gb.state())
     finally:
         xod.set_option("graph", 1)
+
+
+def test_update_kernels_agree():
+    """The 32-column-strip trailing update (used for launches over many
+    blocks: the first cyclic-reduction levels of the 594 x 150 column) gives
+    the same bits as the 16-column-strip one: the same MFMA accumulation
+    order per element."""
+    import paper_2512_06729_amd as xod
+    net, col = synth.make_config(3)
+    stream = torch.cuda.current_stream().cuda_stream
+    gnet = xod.Network(net)
+    out = []
+    try:
+        for u32 in (0, 1):
+            xod.set_option("update32", u32)
+            g = xod.Column(gnet, col, stream=stream, solver=xod.XOD_SOLVER_CR)
+            xod.xod_step(g, 1e-5)
+            out.append(g.state())
+            g.close()
+    finally:
+        xod.set_option("update32", 1)
+    np.testing.assert_array_equal(out[0], out[1])
