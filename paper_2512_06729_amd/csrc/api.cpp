@@ -107,8 +107,13 @@ extern "C" xod_status xod_set_option(const char *name, int64_t value) {
     options().gemm_mfma = (int)value;
     return XOD_OK;
   }
+  if (std::strcmp(name, "gemm_large") == 0) {
+    XOD_CHECK(value == 0 || value == 1, "xod_set_option: gemm_large must be 0 or 1");
+    options().gemm_large = (int)value;
+    return XOD_OK;
+  }
   if (std::strcmp(name, "lookahead") == 0) {
-    XOD_CHECK(value == 0 || value == 1, "xod_set_option: lookahead must be 0 or 1");
+    XOD_CHECK(value >= 0 && value <= 2, "xod_set_option: lookahead must be 0, 1 or 2");
     options().lookahead = (int)value;
     return XOD_OK;
   }

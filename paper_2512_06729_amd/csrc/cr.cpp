@@ -310,7 +310,8 @@ xod_status CrPlan<T>::enqueue_solve(hipStream_t s, xod_column *c) {
 // stream.  The graphs hold kernel nodes only.
 template <class T>
 xod_status CrPlan<T>::replay(hipGraphExec_t *g, bool factor, xod_column *c) {
-  const int key = options().gemm_mfma * 4 + options().update32 * 2 + options().lookahead;
+  const int key = options().gemm_large * 8 + options().gemm_mfma * 4 + options().update32 * 2 +
+                  options().lookahead;
   if (graph_gemm != key) {
     if (gfactor) XOD_HIP(hipGraphExecDestroy(gfactor));
     if (gsolve) XOD_HIP(hipGraphExecDestroy(gsolve));
@@ -326,7 +327,7 @@ xod_status CrPlan<T>::replay(hipGraphExec_t *g, bool factor, xod_column *c) {
     }
     XOD_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
     const xod_status st = factor ? enqueue_factor(cap, options().lookahead ? cap2 : nullptr)
-                                 : enqueue_solve(cap, c);
+                                 : enqueue_solve(cap, c);   // lookahead 2: small levels only
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(cap, &graph);
     if (st != XOD_OK) {

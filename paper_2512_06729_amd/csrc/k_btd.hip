@@ -536,7 +536,8 @@ hipError_t launch_invert_list(const MatRef<T> *dlist, int count, int ld, hipStre
   const ListMats<T> ma{dlist};
   const int npanel = ld / kNB;
   const bool prof = options().profile != 0;
-  if (!s2 || prof) {
+  const bool overlap = s2 && !prof && (options().lookahead == 1 || count <= 8);
+  if (!overlap) {
     for (int p = 0; p < npanel; ++p) {
       if (prof) prof_begin(kProfPanel, s);
       launch_panel<ListMats<T>, T>(ma, count, ld, 0, p, s);

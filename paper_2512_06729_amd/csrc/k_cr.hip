@@ -99,13 +99,105 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmOp<T> *ops, int
   }
 }
 
+// The same product with 128 x 128 output tiles for large batches: 16 waves
+// in a 4 x 4 grid, each owning a 32 x 32 sub-tile (2 x 2 MFMA accumulators),
+// so each LDS fragment feeds two MFMAs and a K step holds 16 MFMAs per wave.
+constexpr int kGemmTileL = 128;
+
+template <class T>
+__global__ void __launch_bounds__(kGemmThreads) k_gemm_l(const GemmOp<T> *ops, int ld) {
+  const GemmOp<T> g = ops[blockIdx.z];
+  const int tm0 = blockIdx.y * kGemmTileL, tn0 = blockIdx.x * kGemmTileL;
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int wr = wid >> 2, wc = wid & 3;
+  __shared__ T As[2][kGemmTileL][kGemmK + 1];
+  __shared__ T Bs[2][kGemmK][kGemmTileL + 2];
+  __shared__ int sbg[2][kMaxLd];
+  typename Vec4<T>::type acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = {0, 0, 0, 0};
+  const int nk1 = ld / kGemmK;
+  const int nk = g.A2 ? 2 * nk1 : nk1;
+  for (int m = threadIdx.x; m < ld; m += blockDim.x) {
+    sbg[0][m] = g.bg ? in_block(g.bg[m], ld) : m;
+    sbg[1][m] = g.bg2 ? in_block(g.bg2[m], ld) : m;
+  }
+  __syncthreads();
+  // staging: two A elements (rows t/16 and t/16 + 64, k t%16) and two B
+  // elements (k t/128 and t/128 + 8, column t%128) per thread
+  const int ar = t / kGemmK, ak = t % kGemmK;
+  const int bk = t / kGemmTileL, bc = t % kGemmTileL;
+  const bool a0 = tm0 + ar < ld, a1 = tm0 + ar + 64 < ld, bok = tn0 + bc < ld;
+  T ra[2], rb[2];
+  auto gload = [&](int kt) {
+    const bool second = kt >= nk1;
+    const T *A = second ? g.A2 : g.A;
+    const T *B = second ? g.B2 : g.B;
+    const int k0 = (second ? kt - nk1 : kt) * kGemmK;
+    ra[0] = a0 ? A[(size_t)(tm0 + ar) * ld + k0 + ak] : T(0);
+    ra[1] = a1 ? A[(size_t)(tm0 + ar + 64) * ld + k0 + ak] : T(0);
+    const int *gb = sbg[second ? 1 : 0];
+    rb[0] = bok ? B[(size_t)gb[k0 + bk] * ld + tn0 + bc] : T(0);
+    rb[1] = bok ? B[(size_t)gb[k0 + bk + 8] * ld + tn0 + bc] : T(0);
+  };
+  auto sstore = [&](int buf) {
+    As[buf][ar][ak] = ra[0];
+    As[buf][ar + 64][ak] = ra[1];
+    Bs[buf][bk][bc] = rb[0];
+    Bs[buf][bk + 8][bc] = rb[1];
+  };
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload(kt + 1);
+#pragma unroll
+    for (int kk = 0; kk < kGemmK / 4; ++kk) {
+      T av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) av[i] = As[buf][wr * 32 + i * 16 + (lane & 15)][kk * 4 + (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bv[j] = Bs[buf][kk * 4 + (lane >> 4)][wc * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma16(av[i], bv[j], acc[i][j]);
+    }
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = tn0 + wc * 32 + j * 16 + (lane & 15);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = tm0 + wr * 32 + i * 16 + mfma_row(T(0), lane, q);
+        if (r < ld && c < ld) {
+          T *p = g.C + (size_t)r * ld + c;
+          const double v = g.alpha * (double)acc[i][j][q];
+          *p = (T)(g.beta ? (double)*p + v : v);
+        }
+      }
+    }
+}
+
 template <class T>
 hipError_t launch_gemm(const GemmOp<T> *dops, int count, int ld, hipStream_t s) {
   if (count <= 0) return hipSuccess;
+  const int ntl = (ld + kGemmTileL - 1) / kGemmTileL;
   const int nt = (ld + kGemmTile - 1) / kGemmTile;
   const bool prof = options().profile != 0;
   if (prof) prof_begin(kProfGemm, s);
-  hipLaunchKernelGGL((k_gemm<T>), dim3(nt, nt, count), dim3(kGemmThreads), 0, s, dops, ld);
+  // large tiles when the batch alone gives every CU two work-groups
+  if (options().gemm_large && (size_t)count * ntl * ntl >= 512)
+    hipLaunchKernelGGL((k_gemm_l<T>), dim3(ntl, ntl, count), dim3(kGemmThreads), 0, s, dops, ld);
+  else
+    hipLaunchKernelGGL((k_gemm<T>), dim3(nt, nt, count), dim3(kGemmThreads), 0, s, dops, ld);
   if (prof) prof_end(kProfGemm, s);
   return hipGetLastError();
 }

@@ -82,6 +82,7 @@ struct Options {
   int gemm_mfma = 1;
   int update32 = 1;       // trailing update in panel-wide strips (0: 16-wide)
   int lookahead = 0;      // captured inversions overlap panel p+1 with update p
+  int gemm_large = 1;     // 128 x 128 product tiles for large batches
   int graph = 1;          // replay captured launch sequences (cyclic reduction)
   int profile = 0;        // record HIP events around profiled launches
   int profile_every = 1;  // profile layers k with k % profile_every == 0
