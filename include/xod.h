@@ -269,9 +269,11 @@ xod_status xod_last_error(char *buf, size_t len);
  *            0 = always 16-column strips by 16-wave work-groups.
  *   "gemm_large": 1 = cyclic-reduction block products of large batches use
  *            128 x 128 output tiles (default); 0 = always 64 x 64.
- *   "lookahead": 1 = captured cyclic-reduction inversions run panel p+1 on
- *            a second branch beside the rest of update p; 2 = only for
- *            levels of at most 8 blocks; 0 = never (default).
+ *   "outer": Gauss-Jordan outer panel width, 32 (default), 64, 96 or 128:
+ *            with a width above 32 the 32-column panels of an outer panel
+ *            update only its own columns, then one rank-width update covers
+ *            the rest of the block (fewer passes over the block, more
+ *            launches); 32 = every panel updates the whole block.
  *   "graph": 1 = the cyclic-reduction factor and solve launch sequences of a
  *            column are captured once into HIP graphs (kernel nodes only)
  *            and replayed (default); 0 = launched one by one.  Graphs are

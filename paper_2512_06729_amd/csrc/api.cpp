@@ -112,9 +112,10 @@ extern "C" xod_status xod_set_option(const char *name, int64_t value) {
     options().gemm_large = (int)value;
     return XOD_OK;
   }
-  if (std::strcmp(name, "lookahead") == 0) {
-    XOD_CHECK(value >= 0 && value <= 2, "xod_set_option: lookahead must be 0, 1 or 2");
-    options().lookahead = (int)value;
+  if (std::strcmp(name, "outer") == 0) {
+    XOD_CHECK(value == 32 || value == 64 || value == 96 || value == 128,
+              "xod_set_option: outer must be 32, 64, 96 or 128");
+    options().outer = (int)value;
     return XOD_OK;
   }
   if (std::strcmp(name, "update32") == 0) {

@@ -50,9 +50,6 @@ template <class T>
 CrPlan<T>::~CrPlan() {
   if (gfactor) (void)hipGraphExecDestroy(gfactor);
   if (gsolve) (void)hipGraphExecDestroy(gsolve);
-  if (ev1) (void)hipEventDestroy(ev1);
-  if (ev2) (void)hipEventDestroy(ev2);
-  if (cap2) (void)hipStreamDestroy(cap2);
   if (cap) (void)hipStreamDestroy(cap);
   for (void *p : owned) (void)hipFree(p);
 }
@@ -275,11 +272,11 @@ xod_status CrPlan<T>::build(xod_column *c) {
 }
 
 template <class T>
-xod_status CrPlan<T>::enqueue_factor(hipStream_t s, hipStream_t s2) {
+xod_status CrPlan<T>::enqueue_factor(hipStream_t s) {
   XOD_HIP(launch_cr_reset(rstep_all, (size_t)N * ld, flag, s));
   const int nlev = (int)levels.size();
   for (int l = 0; l < nlev; ++l) {
-    XOD_HIP(launch_invert_list<T>(d_inv + inv_off[l], inv_cnt[l], ld, s, s2, ev1, ev2));
+    XOD_HIP(launch_invert_list<T>(d_inv + inv_off[l], inv_cnt[l], ld, s));
     if (l == 0) {
       XOD_HIP(launch_cr_level0<T>(d_l0, l0_cnt, ld, s));
     } else {
@@ -287,7 +284,7 @@ xod_status CrPlan<T>::enqueue_factor(hipStream_t s, hipStream_t s2) {
       XOD_HIP(launch_gemm<T>(d_g + g2_off[l], g2_cnt[l], ld, s));
     }
   }
-  XOD_HIP(launch_invert_list<T>(d_inv + inv_off[nlev], 1, ld, s, s2, ev1, ev2));
+  XOD_HIP(launch_invert_list<T>(d_inv + inv_off[nlev], 1, ld, s));
   return XOD_OK;
 }
 
@@ -310,8 +307,8 @@ xod_status CrPlan<T>::enqueue_solve(hipStream_t s, xod_column *c) {
 // stream.  The graphs hold kernel nodes only.
 template <class T>
 xod_status CrPlan<T>::replay(hipGraphExec_t *g, bool factor, xod_column *c) {
-  const int key = options().gemm_large * 8 + options().gemm_mfma * 4 + options().update32 * 2 +
-                  options().lookahead;
+  const int key = options().outer * 8 + options().gemm_large * 4 + options().gemm_mfma * 2 +
+                  options().update32;
   if (graph_gemm != key) {
     if (gfactor) XOD_HIP(hipGraphExecDestroy(gfactor));
     if (gsolve) XOD_HIP(hipGraphExecDestroy(gsolve));
@@ -319,15 +316,9 @@ xod_status CrPlan<T>::replay(hipGraphExec_t *g, bool factor, xod_column *c) {
     graph_gemm = key;
   }
   if (!*g) {
-    if (!cap) {
-      XOD_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-      XOD_HIP(hipStreamCreateWithFlags(&cap2, hipStreamNonBlocking));
-      XOD_HIP(hipEventCreateWithFlags(&ev1, hipEventDisableTiming));
-      XOD_HIP(hipEventCreateWithFlags(&ev2, hipEventDisableTiming));
-    }
+    if (!cap) XOD_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     XOD_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    const xod_status st = factor ? enqueue_factor(cap, options().lookahead ? cap2 : nullptr)
-                                 : enqueue_solve(cap, c);   // lookahead 2: small levels only
+    const xod_status st = factor ? enqueue_factor(cap) : enqueue_solve(cap, c);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(cap, &graph);
     if (st != XOD_OK) {

@@ -43,10 +43,9 @@ struct CrPlan {
 
   // captured launch sequences (kernel nodes only), replayed on the
   // column's stream; built on first use with the options then in force
-  hipStream_t cap = nullptr, cap2 = nullptr;   // capture streams (fork / join)
-  hipEvent_t ev1 = nullptr, ev2 = nullptr;
+  hipStream_t cap = nullptr;   // capture stream
   hipGraphExec_t gfactor = nullptr, gsolve = nullptr;
-  int graph_gemm = -1;   // the "gemm" / "update32" options the graphs were captured with
+  int graph_gemm = -1;   // the kernel options the graphs were captured with
 
   ~CrPlan();
   // Device descriptors for the column's buffers (blocks, couplings, pivots).
@@ -59,7 +58,7 @@ struct CrPlan {
  private:
   template <class U>
   xod_status upload(U **dst, const std::vector<U> &v);
-  xod_status enqueue_factor(hipStream_t s, hipStream_t s2 = nullptr);
+  xod_status enqueue_factor(hipStream_t s);
   xod_status enqueue_solve(hipStream_t s, xod_column *c);
   xod_status replay(hipGraphExec_t *g, bool factor, xod_column *c);
 };

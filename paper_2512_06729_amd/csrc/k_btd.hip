@@ -21,6 +21,7 @@
 #include "xod_internal.h"
 #include "mfma.h"
 
+#include <algorithm>
 #include <climits>
 
 namespace xod {
@@ -504,11 +505,102 @@ void launch_update(const MA &ma, int nmat, int ld, int k, int p, hipStream_t s, 
                        ma, k, p, ld, s0, skip0, skip1);
 }
 
+// Outer update: the rank-wo product of an outer panel (wo = 64, 96 or 128
+// columns eliminated by its 32-column panels) applied to every 32-column
+// strip outside it:  C <- mask * C + W[:, Jo] U,  U = W[piv[Jo], strip],
+// mask zeroing the rows pivoted in Jo.  Same strip ownership as k_update32.
+template <class MA, class T, int WO>
+__global__ void __launch_bounds__(kUpd32Threads) k_update_outer(MA ma, int k, int jo, int ld) {
+  MatRef<T> mat;
+  if (!ma(blockIdx.y, k, mat)) return;
+  const int c0 = blockIdx.x * kNB;
+  if (c0 >= ld || (c0 >= jo && c0 < jo + WO)) return;
+  T *W = mat.W;
+  const int *piv = mat.piv + jo;
+  const int *rstep = mat.rstep;
+  __shared__ T sU[WO][kNB + 1];
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  for (int e = t; e < WO * kNB; e += blockDim.x) {
+    const int r = e / kNB, col = e % kNB;
+    sU[r][col] = W[(size_t)piv[r] * ld + c0 + col];
+  }
+  __syncthreads();
+  const int ntile = ld / 16;
+  for (int tile = wid; tile < ntile; tile += 4) {
+    const int rbase = tile * 16;
+    T av[WO / 4];
+    const T *Arow = W + (size_t)(rbase + (lane & 15)) * ld + jo;
+#pragma unroll
+    for (int kk = 0; kk < WO / 4; ++kk) av[kk] = Arow[4 * kk + (lane >> 4)];
+    typename Vec4<T>::type acc[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = rbase + mfma_row(T(0), lane, i);
+      const int st = rstep[row];
+      const bool piv_here = st >= jo && st < jo + WO;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        acc[h][i] = piv_here ? T(0) : W[(size_t)row * ld + c0 + 16 * h + (lane & 15)];
+    }
+#pragma unroll
+    for (int kk = 0; kk < WO / 4; ++kk)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        acc[h] = mfma16(av[kk], sU[4 * kk + (lane >> 4)][16 * h + (lane & 15)], acc[h]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = rbase + mfma_row(T(0), lane, i);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) W[(size_t)row * ld + c0 + 16 * h + (lane & 15)] = acc[h][i];
+    }
+  }
+}
+
+// Gauss-Jordan inversion of the blocks of one launch.  Columns are taken in
+// outer panels of up to options().outer columns; inside an outer panel each
+// 32-column panel is factored and its update applied to the rest of the
+// outer panel only, then one rank-(outer width) update covers every other
+// column.  With outer = 32 every panel updates the whole block.
+template <class MA, class T>
+void invert_blocks(const MA &ma, int nmat, int ld, int k, hipStream_t s, bool prof) {
+  const int wmax = options().outer;
+  for (int jo = 0; jo < ld; jo += wmax) {
+    const int wo = std::min(wmax, ld - jo);
+    for (int p = jo / kNB; p < (jo + wo) / kNB; ++p) {
+      if (prof) prof_begin(kProfPanel, s);
+      launch_panel<MA, T>(ma, nmat, ld, k, p, s);
+      if (prof) prof_end(kProfPanel, s);
+      if (wo == kNB) {
+        if (prof) prof_begin(kProfUpdate, s);
+        launch_update<MA, T>(ma, nmat, ld, k, p, s);
+        if (prof) prof_end(kProfUpdate, s);
+      } else if (wo > kNB) {
+        if (prof) prof_begin(kProfUpdate, s);
+        launch_update<MA, T>(ma, nmat, ld, k, p, s, jo / kStrip, wo / kStrip);
+        if (prof) prof_end(kProfUpdate, s);
+      }
+    }
+    if (wo > kNB && ld > wo) {
+      if (prof) prof_begin(kProfUpdate, s);
+      const dim3 grid(ld / kNB, nmat);
+      if (wo == 64)
+        hipLaunchKernelGGL((k_update_outer<MA, T, 64>), grid, dim3(kUpd32Threads), 0, s, ma, k,
+                           jo, ld);
+      else if (wo == 96)
+        hipLaunchKernelGGL((k_update_outer<MA, T, 96>), grid, dim3(kUpd32Threads), 0, s, ma, k,
+                           jo, ld);
+      else
+        hipLaunchKernelGGL((k_update_outer<MA, T, 128>), grid, dim3(kUpd32Threads), 0, s, ma, k,
+                           jo, ld);
+      if (prof) prof_end(kProfUpdate, s);
+    }
+  }
+}
+
 template <class Acc, class T>
 hipError_t launch_factor(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s) {
   if (maxN <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_rstep_init<Acc>, dim3(64, ncols), dim3(256), 0, s, acc, maxN);
-  const int npanel = ld / kNB;
   const ThomasMats<Acc, T> ma{acc};
   for (int k = 0; k < maxN; ++k) {
     const bool prof = prof_layer(k);
@@ -517,68 +609,19 @@ hipError_t launch_factor(const Acc &acc, int ncols, int maxN, int ld, hipStream_
       hipLaunchKernelGGL((k_prologue<Acc, T>), dim3((ld + 7) / 8, ncols), dim3(256), 0, s, acc, k);
       if (prof) prof_end(kProfPrologue, s);
     }
-    for (int p = 0; p < npanel; ++p) {
-      if (prof) prof_begin(kProfPanel, s);
-      launch_panel<ThomasMats<Acc, T>, T>(ma, ncols, ld, k, p, s);
-      if (prof) prof_end(kProfPanel, s);
-      if (prof) prof_begin(kProfUpdate, s);
-      launch_update<ThomasMats<Acc, T>, T>(ma, ncols, ld, k, p, s);
-      if (prof) prof_end(kProfUpdate, s);
-    }
+    invert_blocks<ThomasMats<Acc, T>, T>(ma, ncols, ld, k, s, prof);
   }
   return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_invert_list(const MatRef<T> *dlist, int count, int ld, hipStream_t s,
-                              hipStream_t s2, hipEvent_t e1, hipEvent_t e2) {
+hipError_t launch_invert_list(const MatRef<T> *dlist, int count, int ld, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  const ListMats<T> ma{dlist};
-  const int npanel = ld / kNB;
-  const bool prof = options().profile != 0;
-  const bool overlap = s2 && !prof && (options().lookahead == 1 || count <= 8);
-  if (!overlap) {
-    for (int p = 0; p < npanel; ++p) {
-      if (prof) prof_begin(kProfPanel, s);
-      launch_panel<ListMats<T>, T>(ma, count, ld, 0, p, s);
-      if (prof) prof_end(kProfPanel, s);
-      if (prof) prof_begin(kProfUpdate, s);
-      launch_update<ListMats<T>, T>(ma, count, ld, 0, p, s);
-      if (prof) prof_end(kProfUpdate, s);
-    }
-    return hipGetLastError();
-  }
-  // Look-ahead: after panel p, first update the strips of panel p+1 (on s),
-  // then factor panel p+1 on s while the remaining strips of update p run on
-  // s2.  Update p+1 waits for both.  The two branches touch disjoint columns;
-  // the only shared state they read is the pivot bookkeeping of panel p,
-  // which neither changes.
-  const int spp = kNB / kStrip;   // strips per panel
-  for (int p = 0; p < npanel; ++p) {
-    if (p == 0) launch_panel<ListMats<T>, T>(ma, count, ld, 0, 0, s);
-    if (p + 1 < npanel) {
-      launch_update<ListMats<T>, T>(ma, count, ld, 0, p, s, (p + 1) * spp, spp);
-      hipError_t e = hipEventRecord(e1, s);
-      if (e != hipSuccess) return e;
-      e = hipStreamWaitEvent(s2, e1, 0);
-      if (e != hipSuccess) return e;
-      launch_update<ListMats<T>, T>(ma, count, ld, 0, p, s2, 0, -1, (p + 1) * spp,
-                                    (p + 2) * spp);
-      e = hipEventRecord(e2, s2);
-      if (e != hipSuccess) return e;
-      launch_panel<ListMats<T>, T>(ma, count, ld, 0, p + 1, s);
-      e = hipStreamWaitEvent(s, e2, 0);
-      if (e != hipSuccess) return e;
-    } else {
-      launch_update<ListMats<T>, T>(ma, count, ld, 0, p, s);
-    }
-  }
+  invert_blocks<ListMats<T>, T>(ListMats<T>{dlist}, count, ld, 0, s, options().profile != 0);
   return hipGetLastError();
 }
-template hipError_t launch_invert_list<double>(const MatRef<double> *, int, int, hipStream_t,
-                                               hipStream_t, hipEvent_t, hipEvent_t);
-template hipError_t launch_invert_list<float>(const MatRef<float> *, int, int, hipStream_t,
-                                              hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_invert_list<double>(const MatRef<double> *, int, int, hipStream_t);
+template hipError_t launch_invert_list<float>(const MatRef<float> *, int, int, hipStream_t);
 
 template <class Acc>
 hipError_t launch_factor_fp64(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s) {

@@ -81,7 +81,7 @@ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 struct Options {
   int gemm_mfma = 1;
   int update32 = 1;       // trailing update in panel-wide strips (0: 16-wide)
-  int lookahead = 0;      // captured inversions overlap panel p+1 with update p
+  int outer = 32;         // Gauss-Jordan outer panel width (32: unblocked)
   int gemm_large = 1;     // 128 x 128 product tiles for large batches
   int graph = 1;          // replay captured launch sequences (cyclic reduction)
   int profile = 0;        // record HIP events around profiled launches
@@ -136,14 +136,9 @@ struct MatRef {
 };
 
 // Invert `count` ld x ld blocks listed in dlist (device array).  rstep of
-// every listed block must hold INT_MAX on entry.  With a second stream s2
-// (and two events), the trailing update of each panel is split so that the
-// next panel's factorisation overlaps the rest of the update (s2 joins s
-// before the call returns its last launch).
+// every listed block must hold INT_MAX on entry.
 template <class T>
-hipError_t launch_invert_list(const MatRef<T> *dlist, int count, int ld, hipStream_t s,
-                              hipStream_t s2 = nullptr, hipEvent_t e1 = nullptr,
-                              hipEvent_t e2 = nullptr);
+hipError_t launch_invert_list(const MatRef<T> *dlist, int count, int ld, hipStream_t s);
 
 // Batched dense product on ld x ld row-major blocks:
 //   C = (beta ? C : 0) + alpha * (A * B[bg] + A2 * B2[bg2])

@@ -227,3 +227,28 @@ def test_block_product_tilings_agree():
     finally:
         xod.set_option("gemm_large", 1)
     np.testing.assert_array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("solver", [0, 1])
+def test_outer_panel_blocking_agrees(solver):
+    """Blocked Gauss-Jordan (128-column outer panels: panel updates confined
+    to the outer panel, then one rank-128 update) against updating the whole
+    block after every 32-column panel: the same elimination, summed in a
+    different order."""
+    import paper_2512_06729_amd as xod
+    net, col = synth.make_config(3)
+    stream = torch.cuda.current_stream().cuda_stream
+    gnet = xod.Network(net)
+    out = []
+    n0 = None
+    try:
+        for outer in (32, 128):
+            xod.set_option("outer", outer)
+            g = xod.Column(gnet, col, stream=stream, solver=solver)
+            n0 = g.state()
+            xod.xod_step(g, 1e-5)
+            out.append(g.state())
+            g.close()
+    finally:
+        xod.set_option("outer", 32)
+    G.assert_state_agrees(out[1], out[0], out[0] - n0, rel=1e-9)
