@@ -126,11 +126,12 @@ def bench_mixed(xod, torch, gnet, col, args, solver):
             "first_step_max_rel_err_vs_fp64": err, "first_step_refine_iters": st["refine_iters"]}
 
 
-def bench_batch(xod, torch, args):
+def bench_batch(xod, torch, args, precision):
     """Ragged batch of independent columns (60-200 layers; 90-, 250- and
     594-species networks, three of each; per-column T offset and Kzz scale),
     stepped together: columns with the same padded block size share every
-    launch (block Thomas across columns, FP64)."""
+    launch (block Thomas across columns), in FP64 or in mixed precision
+    (FP32 Schur complements, FP64 refinement of the group)."""
     import numpy as np
     import synth
     stream = torch.cuda.current_stream().cuda_stream
@@ -141,7 +142,7 @@ def bench_batch(xod, torch, args):
     for i, (net, col) in enumerate(cols):
         if id(net) not in gnets:
             gnets[id(net)] = xod.Network(net)
-        gcols.append(xod.Column(gnets[id(net)], col, stream=stream))
+        gcols.append(xod.Column(gnets[id(net)], col, precision=precision, stream=stream))
         if (i + 1) % 64 == 0:
             progress(f"batch: {i + 1} columns on the device")
     batch = xod.Batch(gcols)
@@ -152,8 +153,11 @@ def bench_batch(xod, torch, args):
     progress("batch: warm-up step done")
     k = args.batch_steps
     t0 = time.perf_counter()
+    refine = fallback = 0
     for _ in range(k):
-        batch.step(dts)
+        st = batch.step(dts)
+        refine = max(refine, max(x["refine_iters"] for x in st))
+        fallback += sum(x["fp64_fallback"] for x in st)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     layers = sum(c.N for c in gcols)
@@ -165,7 +169,11 @@ def bench_batch(xod, torch, args):
            "batched_steps_per_s": k / el, "ms_per_batched_step": 1e3 * el / k,
            "columns": len(gcols), "columns_per_species_count": sizes, "layers": layers,
            "gauss_jordan_tflops": flops * k / el / 1e12, "setup_s": setup, "steps": k,
-           "solver": "block Thomas across columns", "precision": "fp64"}
+           "solver": "block Thomas across columns",
+           "precision": "fp64" if precision == xod.XOD_FP64 else "mixed"}
+    if precision != xod.XOD_FP64:
+        out["max_group_refinements"] = refine
+        out["column_fp64_fallbacks"] = fallback
     batch.close()
     for c in gcols:
         c.close()
@@ -214,6 +222,14 @@ def bench_serve(xod, torch, args, precision, gnet, net):
         if time.perf_counter() - t0 > args.serve_timeout:
             break
     wall = time.perf_counter() - t0
+    incomplete = []
+    for j, rid in enumerate(ids):
+        if rid not in done:
+            o = srv.poll(rid)
+            incomplete.append({"request": j, "state": o["state"], "steps": o["steps"],
+                               "rejects": o["rejects"], "t": o["t"]})
+    for j in range(len(ids), n):
+        incomplete.append({"request": j, "state": "not submitted"})
     srv.close()
     lat = np.array(lat)
     ok = sum(1 for o in done.values() if o["state"] == xod.Server.DONE)
@@ -223,6 +239,7 @@ def bench_serve(xod, torch, args, precision, gnet, net):
             "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
             "solves_per_s": len(done) / wall, "wall_s": wall,
             "mean_steps_per_solve": float(np.mean(steps)) if steps else None,
+            "unfinished_at_timeout": incomplete,
             "precision": "fp64" if precision == xod.XOD_FP64 else "mixed"}, states
 
 
@@ -396,8 +413,11 @@ def main():
             smx["max_rel_diff_vs_fp64_steady_state"] = diffs
         line["serve"] = {"fp64": s64, "mixed": smx or None}
     if not args.skip_batch:
-        line["batch"] = bench_batch(xod, torch, args)
-        progress(f"batch: {line['batch']['value']:.1f} column-steps/s")
+        b64 = bench_batch(xod, torch, args, xod.XOD_FP64)
+        progress(f"batch fp64: {b64['value']:.1f} column-steps/s")
+        bmx = bench_batch(xod, torch, args, xod.XOD_MIXED)
+        progress(f"batch mixed: {bmx['value']:.1f} column-steps/s")
+        line["batch"] = {"fp64": b64, "mixed": bmx}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(net, col)
         progress("oracle timed")

@@ -216,13 +216,17 @@ xod_status xod_btd_solve(xod_column *col, const double *B, const double *a,
 
 /* One linearly implicit backward-Euler step of the column state:
  * solve (I/dt - J(n)) delta = F(n), n <- n + delta (no clipping).  In
- * XOD_MIXED the solve is refined in FP64 until the residual satisfies
- * |r|_inf <= 1e-14 (|M| |delta| + |F|)_inf or 10 refinements, after which an
- * FP64 refactorisation is used.  Synchronous (reads the statistics). */
+ * XOD_MIXED each refinement solves for the FP64 residual (computed from the
+ * reaction list and the transport coefficients) with the FP32 factors and
+ * adds the correction d; it stops once max over layers of
+ * max|d_k| / max|delta_k| <= 1e-10 (option "refine_tol_exp"), or when the
+ * ratio stops halving and is <= 1e-9; otherwise, and after 10 refinements,
+ * the step is refactored and solved in FP64.  Synchronous (reads the
+ * statistics). */
 typedef struct {
   double max_rel_change;   /* max |delta| / |n_new| over n_new/n_gas > 1e-30 */
   double min_ratio;        /* min n_new / n_gas                               */
-  double resid_inf;        /* final scaled residual (mixed) or 0              */
+  double resid_inf;        /* final correction ratio (mixed) or 0            */
   int32_t refine_iters;    /* refinement iterations used (mixed)              */
   int32_t fp64_fallback;   /* 1 if the mixed solve fell back to FP64          */
   int32_t nonfinite;       /* 1 if the new state holds NaN / Inf              */
@@ -269,6 +273,9 @@ xod_status xod_last_error(char *buf, size_t len);
  *            0 = always 16-column strips by 16-wave work-groups.
  *   "gemm_large": 1 = cyclic-reduction block products of large batches use
  *            128 x 128 output tiles (default); 0 = always 64 x 64.
+ *   "refine_tol_exp": e in 6..15: a mixed-precision solve has converged
+ *            once the largest layer-wise correction ratio max|d|/max|x| is
+ *            at most 10^-e (default 10).
  *   "outer": Gauss-Jordan outer panel width, 32 (default), 64, 96 or 128:
  *            with a width above 32 the 32-column panels of an outer panel
  *            update only its own columns, then one rank-width update covers
@@ -291,10 +298,14 @@ xod_status xod_profile_reset(void);
 
 /* ---- batches ---------------------------------------------------------- */
 
-/* A batch steps many columns together: columns with the same block size
- * share every launch (their layer chains advance in lock step; a column
- * with fewer layers idles once its chain ends).  Columns keep ownership of
- * their state; a column may belong to one batch at a time. */
+/* A batch steps many columns together with block Thomas: columns with the
+ * same block size share every launch (their layer chains advance in lock
+ * step; a column with fewer layers idles once its chain ends).  Columns keep
+ * ownership of their state; a column may belong to one batch at a time; all
+ * columns of a batch have one precision.  Mixed-precision columns of a block
+ * size are refined together until the group's largest correction ratio meets
+ * the single-column stopping rule (a group that stalls is refactored in
+ * FP64); stats report each column's group refinements and fallback. */
 xod_status xod_batch_create(xod_column *const *cols, int32_t ncols,
                             xod_batch **out);
 xod_status xod_batch_destroy(xod_batch *b);

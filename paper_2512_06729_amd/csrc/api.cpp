@@ -112,6 +112,11 @@ extern "C" xod_status xod_set_option(const char *name, int64_t value) {
     options().gemm_large = (int)value;
     return XOD_OK;
   }
+  if (std::strcmp(name, "refine_tol_exp") == 0) {
+    XOD_CHECK(value >= 6 && value <= 15, "xod_set_option: refine_tol_exp must be in 6..15");
+    options().refine_tol = std::pow(10.0, -(double)value);
+    return XOD_OK;
+  }
   if (std::strcmp(name, "outer") == 0) {
     XOD_CHECK(value == 32 || value == 64 || value == 96 || value == 128,
               "xod_set_option: outer must be 32, 64, 96 or 128");
@@ -648,18 +653,18 @@ xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, do
   bool ok = false;
   double prev = 1e300, ratio = 1e300;
   for (int it = 1; it <= c->max_refine; ++it) {
-    XOD_HIP(launch_residual(one, 1, c->N, c->S, c->R, c->dx, c->w, c->stream));
+    XOD_HIP(launch_residual(one, 1, c->N, c->S, c->R, c->stream));
     if (cr)
       XOD_TRY(c->cr32->solve(c));
     else
       XOD_HIP(launch_solve_mixed(one, 1, c->N, c->ld, c->stream));
-    XOD_HIP(launch_axpy_ratio(one, 1, c->N, c->dx, c->ratio, c->rmax, c->stream));
+    XOD_HIP(launch_axpy_ratio(one, 1, c->N, c->ratio, c->rmax, c->stream));
     XOD_HIP(hipMemcpyAsync(c->stats_host, c->rmax, sizeof(double), hipMemcpyDeviceToHost,
                            c->stream));
     XOD_HIP(hipStreamSynchronize(c->stream));
     ratio = c->stats_host[0];
     *iters = it;
-    if (ratio <= 1e-13) {
+    if (ratio <= options().refine_tol) {
       ok = true;
       break;
     }

@@ -1,8 +1,12 @@
 // Batched backward-Euler steps: columns with the same padded block size share
 // every launch (grid dimension over columns); their layer chains advance in
 // lock step and shorter columns idle once their chain ends.  Each column
-// keeps its own dt, state and statistics; the arithmetic of a column does not
-// depend on which other columns share the launch.
+// keeps its own dt, state and statistics.  In FP64 the arithmetic of a column
+// does not depend on which other columns share the launch.  Mixed-precision
+// columns are refined together: the group iterates until its largest
+// correction ratio meets the stopping rule of a single column, so a column
+// may receive more refinements than it would alone (each one only brings it
+// closer to the FP64 solution); a group that stalls is refactored in FP64.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,6 +29,9 @@ BatchRunner::~BatchRunner() {
   (void)hipFree(d_red);
   (void)hipFree(d_stats);
   (void)hipFree(d_partial);
+  (void)hipFree(d_ratio);
+  (void)hipFree(d_rmax);
+  (void)hipHostFree(h_rmax);
   (void)hipHostFree(h_args);
   (void)hipHostFree(h_upd);
   (void)hipHostFree(h_red);
@@ -43,6 +50,8 @@ xod_status BatchRunner::init(int capacity) {
   XOD_HIP(hipHostMalloc((void **)&h_upd, n * sizeof(UpdArgs), hipHostMallocDefault));
   XOD_HIP(hipHostMalloc((void **)&h_red, n * sizeof(RedArgs), hipHostMallocDefault));
   XOD_HIP(hipHostMalloc((void **)&h_stats, n * kStatLen * sizeof(double), hipHostMallocDefault));
+  XOD_HIP(hipMalloc((void **)&d_rmax, sizeof(double)));
+  XOD_HIP(hipHostMalloc((void **)&h_rmax, sizeof(double), hipHostMallocDefault));
   return XOD_OK;
 }
 
@@ -57,13 +66,17 @@ xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double
     return XOD_EINVAL;
   }
   stats.assign((size_t)n * kStatLen, 0.0);
-  // group by padded block size, keeping the caller's order inside a group
-  std::map<int, std::vector<int>> groups;
-  for (int i = 0; i < n; ++i) groups[cols[i]->ld].push_back(i);
+  last_iters.assign(n, 0);
+  last_fallback.assign(n, 0);
+  last_resid.assign(n, 0.0);
+  // group by padded block size and precision, keeping the caller's order
+  // inside a group
+  std::map<std::pair<int, int>, std::vector<int>> groups;
+  for (int i = 0; i < n; ++i) groups[{cols[i]->ld, (int)cols[i]->prec}].push_back(i);
   int base = 0;
   std::vector<std::pair<int, int>> slots;   // (caller index, staging slot)
   for (auto &kv : groups) {
-    const int ld = kv.first;
+    const int ld = kv.first.first;
     const std::vector<int> &idx = kv.second;
     int maxN = 0, maxR = 0, maxS = 0;
     for (size_t j = 0; j < idx.size(); ++j) {
@@ -99,14 +112,73 @@ xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double
     ManyCols acc{d_args + base};
     XOD_HIP(launch_rates(acc, nc, maxN, maxR, s));
     XOD_HIP(launch_rhs(acc, nc, maxN, maxR, maxS, s));
-    XOD_HIP(launch_jacobian(acc, nc, maxN, maxR, ld, false, s));
-    XOD_HIP(launch_factor_fp64(acc, nc, maxN, ld, s));
-    for (int j = 0; j < nc; ++j) {
-      xod_column *c = cols[idx[j]];
-      XOD_HIP(hipMemcpyAsync(c->x, c->f, (size_t)c->N * c->S * sizeof(double),
-                             hipMemcpyDeviceToDevice, s));
+    const bool mixed = cols[idx[0]]->prec == XOD_MIXED;
+    int iters = 0, fallback = 0;
+    double ratio = 0.0;
+    if (mixed) {
+      const size_t need = (size_t)nc * maxN;
+      if (need > ratio_cap) {
+        (void)hipFree(d_ratio);
+        d_ratio = nullptr;
+        XOD_HIP(hipMalloc((void **)&d_ratio, need * sizeof(double)));
+        ratio_cap = need;
+      }
+      XOD_HIP(launch_jacobian(acc, nc, maxN, maxR, ld, true, s));
+      XOD_HIP(launch_factor_mixed(acc, nc, maxN, ld, s));
+      XOD_HIP(launch_scale(acc, nc, maxN, maxS, s));
+      XOD_HIP(launch_solve_mixed(acc, nc, maxN, ld, s));
+      for (int j = 0; j < nc; ++j) {
+        xod_column *c = cols[idx[j]];
+        XOD_HIP(hipMemcpyAsync(c->dx, c->x, (size_t)c->N * c->S * sizeof(double),
+                               hipMemcpyDeviceToDevice, s));
+      }
+      bool ok = false;
+      double prev = 1e300;
+      ratio = 1e300;
+      for (int it = 1; it <= 10; ++it) {
+        XOD_HIP(launch_residual(acc, nc, maxN, maxS, maxR, s));
+        XOD_HIP(launch_solve_mixed(acc, nc, maxN, ld, s));
+        XOD_HIP(launch_axpy_ratio(acc, nc, maxN, d_ratio, d_rmax, s));
+        XOD_HIP(hipMemcpyAsync(h_rmax, d_rmax, sizeof(double), hipMemcpyDeviceToHost, s));
+        XOD_HIP(hipStreamSynchronize(s));
+        ratio = *h_rmax;
+        iters = it;
+        if (ratio <= options().refine_tol) {
+          ok = true;
+          break;
+        }
+        if (ratio > 0.5 * prev) {
+          ok = ratio <= 1e-9;
+          break;
+        }
+        prev = ratio;
+      }
+      if (!ok && ratio <= 1e-9) ok = true;
+      if (ok) {
+        for (int j = 0; j < nc; ++j) {
+          xod_column *c = cols[idx[j]];
+          XOD_HIP(hipMemcpyAsync(c->x, c->dx, (size_t)c->N * c->S * sizeof(double),
+                                 hipMemcpyDeviceToDevice, s));
+        }
+      } else {
+        fallback = 1;
+      }
     }
-    XOD_HIP(launch_solve_fp64(acc, nc, maxN, ld, s));
+    if (!mixed || fallback) {
+      XOD_HIP(launch_jacobian(acc, nc, maxN, maxR, ld, false, s));
+      XOD_HIP(launch_factor_fp64(acc, nc, maxN, ld, s));
+      for (int j = 0; j < nc; ++j) {
+        xod_column *c = cols[idx[j]];
+        XOD_HIP(hipMemcpyAsync(c->x, c->f, (size_t)c->N * c->S * sizeof(double),
+                               hipMemcpyDeviceToDevice, s));
+      }
+      XOD_HIP(launch_solve_fp64(acc, nc, maxN, ld, s));
+    }
+    for (int j = 0; j < nc; ++j) {
+      last_iters[idx[j]] = iters;
+      last_fallback[idx[j]] = fallback;
+      last_resid[idx[j]] = mixed ? ratio : 0.0;
+    }
     XOD_HIP(launch_update_state(d_upd + base, d_red + base, nc, s));
     base += nc;
   }
@@ -144,7 +216,7 @@ extern "C" xod_status xod_batch_create(xod_column *const *cols, int32_t ncols, x
   for (int i = 0; i < ncols; ++i) {
     BCHECK(cols[i] != nullptr, "xod_batch_create: null column");
     BCHECK(!cols[i]->in_batch, "xod_batch_create: column already in a batch");
-    BCHECK(cols[i]->prec == XOD_FP64, "xod_batch_create: batches step FP64 columns");
+    BCHECK(cols[i]->prec == cols[0]->prec, "xod_batch_create: columns of one precision");
     for (int j = 0; j < i; ++j) BCHECK(cols[j] != cols[i], "xod_batch_create: duplicate column");
   }
   std::unique_ptr<xod_batch> b(new xod_batch());
@@ -176,9 +248,9 @@ extern "C" xod_status xod_batch_step(xod_batch *b, const double *dts, xod_step_s
     if (st) {
       st[i].max_rel_change = sv[0];
       st[i].min_ratio = sv[1];
-      st[i].resid_inf = 0.0;
-      st[i].refine_iters = 0;
-      st[i].fp64_fallback = 0;
+      st[i].resid_inf = b->runner.last_resid[i];
+      st[i].refine_iters = b->runner.last_iters[i];
+      st[i].fp64_fallback = b->runner.last_fallback[i];
       st[i].nonfinite = sv[5] > 0 ? 1 : 0;
     }
     if (sv[kNStat] >= 0) {

@@ -20,6 +20,11 @@ struct BatchRunner {
   UpdArgs *d_upd = nullptr, *h_upd = nullptr;
   RedArgs *d_red = nullptr, *h_red = nullptr;
   double *d_stats = nullptr, *h_stats = nullptr, *d_partial = nullptr;
+  double *d_ratio = nullptr, *d_rmax = nullptr, *h_rmax = nullptr;   // mixed refinement
+  size_t ratio_cap = 0;
+  // per caller index, from the last step: refinements, FP64 fallback, final ratio
+  std::vector<int> last_iters, last_fallback;
+  std::vector<double> last_resid;
   ~BatchRunner();
   xod_status init(int capacity);
   xod_status step(const std::vector<xod_column *> &cols, const double *dts, bool clip,

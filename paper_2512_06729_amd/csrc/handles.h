@@ -114,6 +114,7 @@ struct xod_column {
     a_.piv = piv;
     a_.rstep = rstep;
     a_.x = x;
+    a_.dx = dx;
     a_.gs = gs;
     a_.flag = flag;
     return a_;

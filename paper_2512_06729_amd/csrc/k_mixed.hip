@@ -14,11 +14,13 @@
 namespace xod {
 
 template <class Acc>
-__global__ void __launch_bounds__(256) k_dwrate(Acc acc, const double *delta, double *dw) {
+__global__ void __launch_bounds__(256) k_dwrate(Acc acc) {
   const ColArgs &c = acc(blockIdx.z);
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = blockIdx.y;
   if (r >= c.R || k >= c.N) return;
+  const double *delta = c.dx;
+  double *dw = c.w;
   const double *n = c.n + (size_t)k * c.S;
   const double *d = delta + (size_t)k * c.S;
   const int *rc = c.reac + r * XOD_MAX_REAC;
@@ -43,11 +45,13 @@ __global__ void __launch_bounds__(256) k_dwrate(Acc acc, const double *delta, do
 }
 
 template <class Acc>
-__global__ void __launch_bounds__(256) k_resid(Acc acc, const double *delta, const double *dw) {
+__global__ void __launch_bounds__(256) k_resid(Acc acc) {
   const ColArgs &c = acc(blockIdx.z);
   const int y = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = blockIdx.y;
   if (y >= c.S || k >= c.N) return;
+  const double *delta = c.dx;
+  const double *dw = c.w;
   const double *w = dw + (size_t)k * c.R;
   double jd = 0.0;
   for (int e = c.inc_ptr[y]; e < c.inc_ptr[y + 1]; ++e) jd += c.inc_nu[e] * w[c.inc_r[e]];
@@ -71,9 +75,10 @@ __global__ void __launch_bounds__(256) k_scale(Acc acc) {
 
 // delta += x; ratio[k] = max|x_k| / max|delta_k| (0 if delta_k == 0).
 template <class Acc>
-__global__ void __launch_bounds__(256) k_axpy(Acc acc, double *delta, double *ratio) {
+__global__ void __launch_bounds__(256) k_axpy(Acc acc, double *ratio) {
   const ColArgs &c = acc(blockIdx.y);
   const int k = blockIdx.x;
+  double *delta = c.dx;
   double *rk = ratio + (size_t)blockIdx.y * gridDim.x + k;
   if (k >= c.N) {
     if (threadIdx.x == 0) *rk = 0.0;
@@ -119,12 +124,11 @@ __global__ void k_maxreduce(const double *v, int n, double *out) {
 
 template <class Acc>
 hipError_t launch_residual(const Acc &acc, int ncols, int maxN, int maxS, int maxR,
-                           const double *delta, double *dw, hipStream_t s) {
+                           hipStream_t s) {
   if (maxR > 0)
     hipLaunchKernelGGL(k_dwrate<Acc>, dim3((maxR + 255) / 256, maxN, ncols), dim3(256), 0, s,
-                       acc, delta, dw);
-  hipLaunchKernelGGL(k_resid<Acc>, dim3((maxS + 255) / 256, maxN, ncols), dim3(256), 0, s, acc,
-                     delta, dw);
+                       acc);
+  hipLaunchKernelGGL(k_resid<Acc>, dim3((maxS + 255) / 256, maxN, ncols), dim3(256), 0, s, acc);
   return hipGetLastError();
 }
 
@@ -135,17 +139,20 @@ hipError_t launch_scale(const Acc &acc, int ncols, int maxN, int maxS, hipStream
 }
 
 template <class Acc>
-hipError_t launch_axpy_ratio(const Acc &acc, int ncols, int maxN, double *delta, double *ratio,
-                             double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_axpy<Acc>, dim3(maxN, ncols), dim3(256), 0, s, acc, delta, ratio);
+hipError_t launch_axpy_ratio(const Acc &acc, int ncols, int maxN, double *ratio, double *out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy<Acc>, dim3(maxN, ncols), dim3(256), 0, s, acc, ratio);
   hipLaunchKernelGGL(k_maxreduce, dim3(1), dim3(256), 0, s, ratio, maxN * ncols, out);
   return hipGetLastError();
 }
 
-template hipError_t launch_residual<OneCol>(const OneCol &, int, int, int, int, const double *,
-                                            double *, hipStream_t);
+template hipError_t launch_residual<OneCol>(const OneCol &, int, int, int, int, hipStream_t);
+template hipError_t launch_residual<ManyCols>(const ManyCols &, int, int, int, int, hipStream_t);
 template hipError_t launch_scale<OneCol>(const OneCol &, int, int, int, hipStream_t);
+template hipError_t launch_scale<ManyCols>(const ManyCols &, int, int, int, hipStream_t);
 template hipError_t launch_axpy_ratio<OneCol>(const OneCol &, int, int, double *, double *,
-                                              double *, hipStream_t);
+                                              hipStream_t);
+template hipError_t launch_axpy_ratio<ManyCols>(const ManyCols &, int, int, double *, double *,
+                                                hipStream_t);
 
 }  // namespace xod

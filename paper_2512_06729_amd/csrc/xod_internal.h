@@ -46,6 +46,7 @@ struct ColArgs {
   int *piv;          // [N*ld] pivot row of each column
   int *rstep;        // [N*ld] pivot step of each row (inverse of piv)
   double *x;         // solve vector [N*S] (in/out)
+  double *dx;        // refined increment [N*S] (mixed precision)
   double *dwd;       // [N*R*6] dw_r/dn_x for the distinct species x = rsp[6r+u]
   double *gs;        // solve scratch [N*ld]
   int *flag;         // [4]: singular layer, singular column, nonfinite, spare
@@ -82,6 +83,7 @@ struct Options {
   int gemm_mfma = 1;
   int update32 = 1;       // trailing update in panel-wide strips (0: 16-wide)
   int outer = 32;         // Gauss-Jordan outer panel width (32: unblocked)
+  double refine_tol = 1e-10;   // mixed refinement: converged at this correction ratio
   int gemm_large = 1;     // 128 x 128 product tiles for large batches
   int graph = 1;          // replay captured launch sequences (cyclic reduction)
   int profile = 0;        // record HIP events around profiled launches
@@ -114,14 +116,19 @@ template <class Acc>
 hipError_t launch_solve_fp64(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s);
 template <class Acc>
 hipError_t launch_factor_mixed(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s);
+// Refinement (mixed precision), per column of the launch:
+//   residual  x = rs * (f - M dx)   (dw: the column's w buffer as scratch)
+//   scale     x = rs * f
+//   axpy      dx += x, ratio[col * maxN + k] = max|x_k| / max|dx_k|, and
+//             out[0] = the maximum over all columns and layers
 template <class Acc>
 hipError_t launch_residual(const Acc &acc, int ncols, int maxN, int maxS, int maxR,
-                           const double *delta, double *dw, hipStream_t s);
+                           hipStream_t s);
 template <class Acc>
 hipError_t launch_scale(const Acc &acc, int ncols, int maxN, int maxS, hipStream_t s);
 template <class Acc>
-hipError_t launch_axpy_ratio(const Acc &acc, int ncols, int maxN, double *delta, double *ratio,
-                             double *out, hipStream_t s);
+hipError_t launch_axpy_ratio(const Acc &acc, int ncols, int maxN, double *ratio, double *out,
+                             hipStream_t s);
 template <class Acc>
 hipError_t launch_solve_mixed(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s);
 
