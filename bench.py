@@ -243,6 +243,27 @@ def bench_serve(xod, torch, args, precision, gnet, net):
             "precision": "fp64" if precision == xod.XOD_FP64 else "mixed"}, states
 
 
+def panel_traffic():
+    """HBM bytes per k_panel launch from the committed rocprofv3 counter runs
+    (calibrated FETCH_SIZE + WRITE_SIZE), or None if the kernel source has
+    changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_panel_594x150_traffic.md")
+    src = os.path.join(ROOT, "paper_2512_06729_amd", "csrc", "k_btd.hip")
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = {}
+    for ln in text.splitlines():
+        if ln.startswith("traffic_bytes_per_launch:"):
+            vals["bytes"] = float(ln.split(":")[1])
+        if ln.startswith("source_sha256"):
+            vals["sha"] = ln.split(":")[-1].strip()
+    return vals.get("bytes") if vals.get("sha") == sha else None
+
+
 def timed_steps(xod, torch, gcol, dt, steps):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -281,6 +302,9 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-timeout", type=float, default=70.0)
     ap.add_argument("--serve-fp64-only", action="store_true")
+    ap.add_argument("--pmc-calibrate", action="store_true",
+                    help="copy 256 MiB device to device three times first (the plain copy "
+                         "that scales FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): columns are "
@@ -294,6 +318,14 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.pmc_calibrate:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        progress("calibration copies done (3 x 256 MiB)")
     net, col = synth.make_config(3)
     stream = torch.cuda.current_stream().cuda_stream
     gnet = xod.Network(net)
@@ -346,8 +378,9 @@ def main():
                                           if dominant == "gemm" else
                                           "k_update (Gauss-Jordan trailing update, FP64 MFMA)"),
               "peak": PEAK_FP64_MFMA_TFLOPS}
+    traffic = panel_traffic() if (dominant == "panel" and args.solver == "cr") else None
     rl.update({"achieved": achieved, "unit": "TFLOP/s",
-               "frac": achieved / rl["peak"] if achieved else None, "traffic": None,
+               "frac": achieved / rl["peak"] if achieved else None, "traffic": traffic,
                "flops_per_launch": per_launch_flops, "avg_launch_us": dk["avg_us"]})
     gemm = kern["gemm"]
     gemm_rl = None
