@@ -29,6 +29,9 @@ BatchRunner::~BatchRunner() {
   (void)hipFree(d_red);
   (void)hipFree(d_stats);
   (void)hipFree(d_partial);
+  for (hipEvent_t e : gevent) (void)hipEventDestroy(e);
+  for (hipStream_t st : gstream) (void)hipStreamDestroy(st);
+  if (fork_ev) (void)hipEventDestroy(fork_ev);
   (void)hipFree(d_ratio);
   (void)hipFree(d_rmax);
   (void)hipHostFree(h_rmax);
@@ -50,8 +53,9 @@ xod_status BatchRunner::init(int capacity) {
   XOD_HIP(hipHostMalloc((void **)&h_upd, n * sizeof(UpdArgs), hipHostMallocDefault));
   XOD_HIP(hipHostMalloc((void **)&h_red, n * sizeof(RedArgs), hipHostMallocDefault));
   XOD_HIP(hipHostMalloc((void **)&h_stats, n * kStatLen * sizeof(double), hipHostMallocDefault));
-  XOD_HIP(hipMalloc((void **)&d_rmax, sizeof(double)));
-  XOD_HIP(hipHostMalloc((void **)&h_rmax, sizeof(double), hipHostMallocDefault));
+  XOD_HIP(hipMalloc((void **)&d_rmax, kMaxGroups * sizeof(double)));
+  XOD_HIP(hipHostMalloc((void **)&h_rmax, kMaxGroups * sizeof(double), hipHostMallocDefault));
+  XOD_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
   return XOD_OK;
 }
 
@@ -69,20 +73,35 @@ xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double
   last_iters.assign(n, 0);
   last_fallback.assign(n, 0);
   last_resid.assign(n, 0.0);
-  // group by padded block size and precision, keeping the caller's order
-  // inside a group
+  // Group by padded block size and precision (caller's order inside a
+  // group).  Groups are independent: each runs on its own stream, forked
+  // from s and joined back before the statistics are read.
   std::map<std::pair<int, int>, std::vector<int>> groups;
   for (int i = 0; i < n; ++i) groups[{cols[i]->ld, (int)cols[i]->prec}].push_back(i);
+  struct Group {
+    int ld, base, nc, maxN = 0, maxR = 0, maxS = 0;
+    bool mixed;
+    const std::vector<int> *idx;
+    hipStream_t st;
+    size_t roff;
+    int iters = 0, fallback = 0;
+    double ratio = 0.0;
+  };
+  std::vector<Group> gs;
   int base = 0;
+  size_t rneed = 0;
   std::vector<std::pair<int, int>> slots;   // (caller index, staging slot)
   for (auto &kv : groups) {
-    const int ld = kv.first.first;
-    const std::vector<int> &idx = kv.second;
-    int maxN = 0, maxR = 0, maxS = 0;
-    for (size_t j = 0; j < idx.size(); ++j) {
-      xod_column *c = cols[idx[j]];
-      const int sl = base + (int)j;
-      c->dt = dts[idx[j]];
+    Group g{};
+    g.ld = kv.first.first;
+    g.idx = &kv.second;
+    g.base = base;
+    g.nc = (int)kv.second.size();
+    g.mixed = kv.first.second == (int)XOD_MIXED;
+    for (int j = 0; j < g.nc; ++j) {
+      xod_column *c = cols[kv.second[j]];
+      const int sl = base + j;
+      c->dt = dts[kv.second[j]];
       h_args[sl] = c->args();
       UpdArgs u{};
       u.n = c->n;
@@ -97,90 +116,131 @@ xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double
       u.y_sig = y_sig;
       h_upd[sl] = u;
       h_red[sl] = RedArgs{u.partial, c->flag, d_stats + (size_t)sl * kStatLen};
-      maxN = std::max(maxN, c->N);
-      maxR = std::max(maxR, c->R);
-      maxS = std::max(maxS, c->S);
-      slots.push_back({idx[j], sl});
+      g.maxN = std::max(g.maxN, c->N);
+      g.maxR = std::max(g.maxR, c->R);
+      g.maxS = std::max(g.maxS, c->S);
+      slots.push_back({kv.second[j], sl});
     }
-    const int nc = (int)idx.size();
-    XOD_HIP(hipMemcpyAsync(d_args + base, h_args + base, nc * sizeof(ColArgs),
-                           hipMemcpyHostToDevice, s));
-    XOD_HIP(hipMemcpyAsync(d_upd + base, h_upd + base, nc * sizeof(UpdArgs),
-                           hipMemcpyHostToDevice, s));
-    XOD_HIP(hipMemcpyAsync(d_red + base, h_red + base, nc * sizeof(RedArgs),
-                           hipMemcpyHostToDevice, s));
-    ManyCols acc{d_args + base};
-    XOD_HIP(launch_rates(acc, nc, maxN, maxR, s));
-    XOD_HIP(launch_rhs(acc, nc, maxN, maxR, maxS, s));
-    const bool mixed = cols[idx[0]]->prec == XOD_MIXED;
-    int iters = 0, fallback = 0;
-    double ratio = 0.0;
-    if (mixed) {
-      const size_t need = (size_t)nc * maxN;
-      if (need > ratio_cap) {
-        (void)hipFree(d_ratio);
-        d_ratio = nullptr;
-        XOD_HIP(hipMalloc((void **)&d_ratio, need * sizeof(double)));
-        ratio_cap = need;
-      }
-      XOD_HIP(launch_jacobian(acc, nc, maxN, maxR, ld, true, s));
-      XOD_HIP(launch_factor_mixed(acc, nc, maxN, ld, s));
-      XOD_HIP(launch_scale(acc, nc, maxN, maxS, s));
-      XOD_HIP(launch_solve_mixed(acc, nc, maxN, ld, s));
-      for (int j = 0; j < nc; ++j) {
-        xod_column *c = cols[idx[j]];
+    g.roff = rneed;
+    if (g.mixed) rneed += (size_t)g.nc * g.maxN;
+    base += g.nc;
+    gs.push_back(g);
+  }
+  if ((int)gs.size() > kMaxGroups) {
+    set_error("batch step: too many distinct block sizes");
+    return XOD_EINVAL;
+  }
+  if (rneed > ratio_cap) {
+    (void)hipFree(d_ratio);
+    d_ratio = nullptr;
+    XOD_HIP(hipMalloc((void **)&d_ratio, rneed * sizeof(double)));
+    ratio_cap = rneed;
+  }
+  while (gstream.size() < gs.size()) {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    XOD_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    XOD_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    gstream.push_back(st);
+    gevent.push_back(ev);
+  }
+  XOD_HIP(hipEventRecord(fork_ev, s));
+  // phase 1: factor and first solve of every group
+  for (size_t gi = 0; gi < gs.size(); ++gi) {
+    Group &g = gs[gi];
+    g.st = gstream[gi];
+    const hipStream_t st = g.st;
+    XOD_HIP(hipStreamWaitEvent(st, fork_ev, 0));
+    XOD_HIP(hipMemcpyAsync(d_args + g.base, h_args + g.base, g.nc * sizeof(ColArgs),
+                           hipMemcpyHostToDevice, st));
+    XOD_HIP(hipMemcpyAsync(d_upd + g.base, h_upd + g.base, g.nc * sizeof(UpdArgs),
+                           hipMemcpyHostToDevice, st));
+    XOD_HIP(hipMemcpyAsync(d_red + g.base, h_red + g.base, g.nc * sizeof(RedArgs),
+                           hipMemcpyHostToDevice, st));
+    const ManyCols acc{d_args + g.base};
+    XOD_HIP(launch_rates(acc, g.nc, g.maxN, g.maxR, st));
+    XOD_HIP(launch_rhs(acc, g.nc, g.maxN, g.maxR, g.maxS, st));
+    if (g.mixed) {
+      XOD_HIP(launch_jacobian(acc, g.nc, g.maxN, g.maxR, g.ld, true, st));
+      XOD_HIP(launch_factor_mixed(acc, g.nc, g.maxN, g.ld, st));
+      XOD_HIP(launch_scale(acc, g.nc, g.maxN, g.maxS, st));
+      XOD_HIP(launch_solve_mixed(acc, g.nc, g.maxN, g.ld, st));
+      for (int j = 0; j < g.nc; ++j) {
+        xod_column *c = cols[(*g.idx)[j]];
         XOD_HIP(hipMemcpyAsync(c->dx, c->x, (size_t)c->N * c->S * sizeof(double),
-                               hipMemcpyDeviceToDevice, s));
+                               hipMemcpyDeviceToDevice, st));
       }
-      bool ok = false;
-      double prev = 1e300;
-      ratio = 1e300;
-      for (int it = 1; it <= 10; ++it) {
-        XOD_HIP(launch_residual(acc, nc, maxN, maxS, maxR, s));
-        XOD_HIP(launch_solve_mixed(acc, nc, maxN, ld, s));
-        XOD_HIP(launch_axpy_ratio(acc, nc, maxN, d_ratio, d_rmax, s));
-        XOD_HIP(hipMemcpyAsync(h_rmax, d_rmax, sizeof(double), hipMemcpyDeviceToHost, s));
-        XOD_HIP(hipStreamSynchronize(s));
-        ratio = *h_rmax;
-        iters = it;
-        if (ratio <= options().refine_tol) {
-          ok = true;
-          break;
-        }
-        if (ratio > 0.5 * prev) {
-          ok = ratio <= 1e-9;
-          break;
-        }
-        prev = ratio;
-      }
-      if (!ok && ratio <= 1e-9) ok = true;
-      if (ok) {
-        for (int j = 0; j < nc; ++j) {
-          xod_column *c = cols[idx[j]];
-          XOD_HIP(hipMemcpyAsync(c->x, c->dx, (size_t)c->N * c->S * sizeof(double),
-                                 hipMemcpyDeviceToDevice, s));
-        }
-      } else {
-        fallback = 1;
-      }
-    }
-    if (!mixed || fallback) {
-      XOD_HIP(launch_jacobian(acc, nc, maxN, maxR, ld, false, s));
-      XOD_HIP(launch_factor_fp64(acc, nc, maxN, ld, s));
-      for (int j = 0; j < nc; ++j) {
-        xod_column *c = cols[idx[j]];
+    } else {
+      XOD_HIP(launch_jacobian(acc, g.nc, g.maxN, g.maxR, g.ld, false, st));
+      XOD_HIP(launch_factor_fp64(acc, g.nc, g.maxN, g.ld, st));
+      for (int j = 0; j < g.nc; ++j) {
+        xod_column *c = cols[(*g.idx)[j]];
         XOD_HIP(hipMemcpyAsync(c->x, c->f, (size_t)c->N * c->S * sizeof(double),
-                               hipMemcpyDeviceToDevice, s));
+                               hipMemcpyDeviceToDevice, st));
       }
-      XOD_HIP(launch_solve_fp64(acc, nc, maxN, ld, s));
+      XOD_HIP(launch_solve_fp64(acc, g.nc, g.maxN, g.ld, st));
     }
-    for (int j = 0; j < nc; ++j) {
-      last_iters[idx[j]] = iters;
-      last_fallback[idx[j]] = fallback;
-      last_resid[idx[j]] = mixed ? ratio : 0.0;
+  }
+  // phase 2: refinement of mixed groups (each waits on its own stream only)
+  for (size_t gi = 0; gi < gs.size(); ++gi) {
+    Group &g = gs[gi];
+    if (!g.mixed) continue;
+    const hipStream_t st = g.st;
+    const ManyCols acc{d_args + g.base};
+    double *ratio = d_ratio + g.roff;
+    bool ok = false;
+    double prev = 1e300;
+    g.ratio = 1e300;
+    for (int it = 1; it <= 10; ++it) {
+      XOD_HIP(launch_residual(acc, g.nc, g.maxN, g.maxS, g.maxR, st));
+      XOD_HIP(launch_solve_mixed(acc, g.nc, g.maxN, g.ld, st));
+      XOD_HIP(launch_axpy_ratio(acc, g.nc, g.maxN, ratio, d_rmax + gi, st));
+      XOD_HIP(hipMemcpyAsync(h_rmax + gi, d_rmax + gi, sizeof(double), hipMemcpyDeviceToHost,
+                             st));
+      XOD_HIP(hipStreamSynchronize(st));
+      g.ratio = h_rmax[gi];
+      g.iters = it;
+      if (g.ratio <= options().refine_tol) {
+        ok = true;
+        break;
+      }
+      if (g.ratio > 0.5 * prev) {
+        ok = g.ratio <= 1e-9;
+        break;
+      }
+      prev = g.ratio;
     }
-    XOD_HIP(launch_update_state(d_upd + base, d_red + base, nc, s));
-    base += nc;
+    if (!ok && g.ratio <= 1e-9) ok = true;
+    if (ok) {
+      for (int j = 0; j < g.nc; ++j) {
+        xod_column *c = cols[(*g.idx)[j]];
+        XOD_HIP(hipMemcpyAsync(c->x, c->dx, (size_t)c->N * c->S * sizeof(double),
+                               hipMemcpyDeviceToDevice, st));
+      }
+    } else {
+      g.fallback = 1;
+      XOD_HIP(launch_jacobian(acc, g.nc, g.maxN, g.maxR, g.ld, false, st));
+      XOD_HIP(launch_factor_fp64(acc, g.nc, g.maxN, g.ld, st));
+      for (int j = 0; j < g.nc; ++j) {
+        xod_column *c = cols[(*g.idx)[j]];
+        XOD_HIP(hipMemcpyAsync(c->x, c->f, (size_t)c->N * c->S * sizeof(double),
+                               hipMemcpyDeviceToDevice, st));
+      }
+      XOD_HIP(launch_solve_fp64(acc, g.nc, g.maxN, g.ld, st));
+    }
+  }
+  // phase 3: state update and statistics, then join
+  for (size_t gi = 0; gi < gs.size(); ++gi) {
+    Group &g = gs[gi];
+    XOD_HIP(launch_update_state(d_upd + g.base, d_red + g.base, g.nc, g.st));
+    XOD_HIP(hipEventRecord(gevent[gi], g.st));
+    XOD_HIP(hipStreamWaitEvent(s, gevent[gi], 0));
+    for (int j = 0; j < g.nc; ++j) {
+      const int ci = (*g.idx)[j];
+      last_iters[ci] = g.iters;
+      last_fallback[ci] = g.fallback;
+      last_resid[ci] = g.mixed ? g.ratio : 0.0;
+    }
   }
   XOD_HIP(hipMemcpyAsync(h_stats, d_stats, (size_t)n * kStatLen * sizeof(double),
                          hipMemcpyDeviceToHost, s));

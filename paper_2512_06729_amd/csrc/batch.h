@@ -22,6 +22,12 @@ struct BatchRunner {
   double *d_stats = nullptr, *h_stats = nullptr, *d_partial = nullptr;
   double *d_ratio = nullptr, *d_rmax = nullptr, *h_rmax = nullptr;   // mixed refinement
   size_t ratio_cap = 0;
+  // one stream per group of equal block size and precision (created on first
+  // use, default priority), forked from and joined back to the caller's stream
+  static constexpr int kMaxGroups = 16;
+  std::vector<hipStream_t> gstream;
+  std::vector<hipEvent_t> gevent;
+  hipEvent_t fork_ev = nullptr;
   // per caller index, from the last step: refinements, FP64 fallback, final ratio
   std::vector<int> last_iters, last_fallback;
   std::vector<double> last_resid;
