@@ -123,6 +123,11 @@ extern "C" xod_status xod_set_option(const char *name, int64_t value) {
     options().outer = (int)value;
     return XOD_OK;
   }
+  if (std::strcmp(name, "outer_nmat") == 0) {
+    XOD_CHECK(value >= 1 && value <= 1000000, "xod_set_option: outer_nmat must be >= 1");
+    options().outer_nmat = (int)value;
+    return XOD_OK;
+  }
   if (std::strcmp(name, "update32") == 0) {
     XOD_CHECK(value == 0 || value == 1, "xod_set_option: update32 must be 0 or 1");
     options().update32 = (int)value;

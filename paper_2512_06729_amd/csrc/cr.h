@@ -45,7 +45,7 @@ struct CrPlan {
   // column's stream; built on first use with the options then in force
   hipStream_t cap = nullptr;   // capture stream
   hipGraphExec_t gfactor = nullptr, gsolve = nullptr;
-  int graph_gemm = -1;   // the kernel options the graphs were captured with
+  long long graph_gemm = -1;   // the kernel options the graphs were captured with
 
   ~CrPlan();
   // Device descriptors for the column's buffers (blocks, couplings, pivots).

@@ -106,11 +106,17 @@ struct ListMats {
 // threads).  Per column, one barrier:
 //   - every unused row forms a key: |x| with its 10 lowest mantissa bits
 //     replaced by (1023 - row), so the largest key is the largest magnitude
-//     (to 42 mantissa bits) and, among equals, the lowest row;
-//   - a DPP max gives each wave's best key; the owning lane publishes its
-//     row in LDS (double-buffered by column parity), lane 0 the key;
-//   - after the barrier, 16 lanes read the wave keys and a second DPP max
-//     gives the pivot row, whose values every thread reads from LDS.
+//     (to 42 mantissa bits) and, among equals, the lowest row; used rows
+//     give 0;
+//   - a DPP max gives each wave's best key, which names the wave's
+//     candidate row: its owning lane publishes the row in LDS
+//     (double-buffered by column parity) with the reciprocal of its pivot
+//     entry in the pivot column's slot, lane 0 the key;
+//   - after the barrier every lane reads the wave keys; their maximum names
+//     the pivot row, whose values (and reciprocal pivot) every thread reads.
+// The code from the elimination update of one column to the wave maximum of
+// the next has no branches, so the compiler can overlap the next column's
+// key reduction with the update (the next column is updated first).
 // Pivot rows are kept unscaled while the panel runs (the elimination update
 // is linear in each row, so scaling commutes with it): the pivot row's own
 // column is set to 1 and the row is multiplied by its reciprocal pivot when
@@ -121,7 +127,7 @@ constexpr int kGroup = 8;                                   // columns per unrol
 
 struct PanelShared {
   double cand[2][kPanelWaves][kNB];
-  double key[2][16];
+  double key[2][kPanelWaves];
   int piv[kNB];
   int bad;
 };
@@ -139,103 +145,104 @@ __device__ __forceinline__ double read_lane(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
-// Maximum over each row of 16 lanes (quad_perm [1,0,3,2], [2,3,0,1],
-// row_ror:4, row_ror:8): every lane of the row holds it afterwards.
-__device__ __forceinline__ double row16_max(double v) {
+// Maximum over the 64 lanes (quad_perm [1,0,3,2], [2,3,0,1], row_ror:4,
+// row_ror:8, then row_bcast:15 / row_bcast:31), read from the last lane.
+__device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_move<0xb1>(v));
   v = fmax(v, dpp_move<0x4e>(v));
   v = fmax(v, dpp_move<0x124>(v));
   v = fmax(v, dpp_move<0x128>(v));
-  return v;
-}
-
-// Maximum over the 64 lanes (row maxima, then row_bcast:15 / row_bcast:31),
-// read from the last lane.
-__device__ __forceinline__ double wave_max(double v) {
-  v = row16_max(v);
   v = fmax(v, dpp_move<0x142>(v));
   v = fmax(v, dpp_move<0x143>(v));
   return read_lane(v, 63);
 }
 
-__device__ __forceinline__ double pivot_key(double x, int row) {
-  const double a = fmin(fabs(x), 1e300);   // NaN / Inf -> 1e300: chosen, then reported
-  unsigned long long b = (unsigned long long)__double_as_longlong(a);
-  b = (b & ~1023ull) | (unsigned long long)(1023 - row);
-  return __longlong_as_double((long long)b);
+// Key of a row (see above); mask is all ones for an unused row, 0 for a used
+// one.  NaN and Inf map to 1e300: such a pivot is taken, then reported.
+__device__ __forceinline__ double pivot_key(double x, int row, unsigned mask) {
+  const double a = fmin(fabs(x), 1e300);
+  const unsigned lo = ((unsigned)__double2loint(a) & ~1023u) | (unsigned)(1023 - row);
+  const unsigned hi = (unsigned)__double2hiint(a);
+  return __hiloint2double((int)(hi & mask), (int)(lo & mask));
 }
 __device__ __forceinline__ int key_row(double k) {
-  return 1023 - (int)((unsigned long long)__double_as_longlong(k) & 1023ull);
+  return 1023 - (__double2loint(k) & 1023);
 }
 
 // One Gauss-Jordan column at static position U of the (rotated) rows.
+// umask[i]: all ones while row R*t+i is unused.
 template <int R, int U>
-__device__ __forceinline__ void gj_col(double (&row)[R][kNB], double (&sig)[R], bool (&used)[R],
-                                       int (&mystep)[R], PanelShared &sh, int t, int jcol,
-                                       int j0) {
+__device__ __forceinline__ void gj_col(double (&row)[R][kNB], double (&sig)[R],
+                                       unsigned (&umask)[R], int (&mystep)[R], PanelShared &sh,
+                                       int t, int jcol, int j0) {
   const int lane = t & 63, wid = t >> 6;
   const int buf = jcol & 1;
   double key = 0.0;
-  int ib = 0;
 #pragma unroll
-  for (int i = 0; i < R; ++i) {
-    const double k = used[i] ? 0.0 : pivot_key(row[i][U], R * t + i);
-    if (k > key) { key = k; ib = i; }
-  }
+  for (int i = 0; i < R; ++i) key = fmax(key, pivot_key(row[i][U], R * t + i, umask[i]));
   const double m = wave_max(key);
-  if (m > 0.0 && key == m) {
+  if (m > 0.0) {                       // this wave has an unused row: publish its best
+    const int rw = key_row(m);
+    const int iw = rw % R;             // wave-uniform register index, owner lane below
 #pragma unroll
     for (int i = 0; i < R; ++i)
-      if (i == ib) {
+      if (i == iw) {
+        if (R * t + i == rw) {
+          double *dst = sh.cand[buf][wid];
 #pragma unroll
-        for (int q = 0; q < kNB; ++q) sh.cand[buf][wid][q] = row[i][q];
+          for (int q = 0; q < kNB; ++q)
+            if (q != U) dst[q] = row[i][q];
+          const double pv = row[i][U];
+          dst[U] = (fabs(pv) > 0.0 && isfinite(pv)) ? 1.0 / pv : __builtin_nan("");
+        }
       }
   }
   if (lane == 0) sh.key[buf][wid] = m;
   __syncthreads();
-  const int nw = blockDim.x >> 6;
-  const double M = read_lane(row16_max(lane < nw ? sh.key[buf][lane & 15] : 0.0), 0);
-  if (!(M > 0.0)) {                                   // no unused row left
+  double K = sh.key[buf][0];
+#pragma unroll
+  for (int w = 1; w < kPanelWaves; ++w) K = fmax(K, sh.key[buf][w]);
+  if (!(K > 0.0)) {                    // no unused row left
     if (t == 0) { sh.piv[jcol] = 0; if (sh.bad < 0) sh.bad = jcol; }
     return;
   }
-  const int r = key_row(M);
+  const int r = key_row(K);
   const double *prow = sh.cand[buf][r / (64 * R)];
-  double pv = prow[U];
-  if (!(fabs(pv) > 0.0) || !isfinite(pv)) {
+  double npiv = prow[U];
+  if (npiv != npiv) {                  // zero or non-finite pivot
     if (t == 0 && sh.bad < 0) sh.bad = jcol;
-    pv = 1.0;
+    npiv = 1.0;
   }
-  const double npiv = 1.0 / pv;
+  sh.piv[jcol] = r;                    // every thread stores the same value
+  bool me[R];
   double fm[R];
 #pragma unroll
-  for (int i = 0; i < R; ++i) fm[i] = (R * t + i == r) ? 0.0 : row[i][U] * npiv;
+  for (int i = 0; i < R; ++i) {
+    me[i] = R * t + i == r;
+    fm[i] = me[i] ? 0.0 : row[i][U] * npiv;
+  }
 #pragma unroll
-  for (int q = 0; q < kNB; ++q) {
-    if (q == U) continue;
+  for (int qq = 1; qq < kNB; ++qq) {   // the next column first
+    const int q = (U + qq) % kNB;
     const double pq = prow[q];
 #pragma unroll
     for (int i = 0; i < R; ++i) row[i][q] = fma(-fm[i], pq, row[i][q]);
   }
 #pragma unroll
   for (int i = 0; i < R; ++i) {
-    const bool me = (R * t + i == r);
-    row[i][U] = me ? 1.0 : -fm[i];
-    if (me) {
-      used[i] = true;
-      sig[i] = npiv;
-      mystep[i] = j0 + jcol;
-    }
+    row[i][U] = me[i] ? 1.0 : -fm[i];
+    umask[i] = me[i] ? 0u : umask[i];
+    sig[i] = me[i] ? npiv : sig[i];
+    mystep[i] = me[i] ? j0 + jcol : mystep[i];
   }
-  if (t == 0) sh.piv[jcol] = r;
 }
 
 template <int R, int U>
 __device__ __forceinline__ void gj_group(double (&row)[R][kNB], double (&sig)[R],
-                                         bool (&used)[R], int (&mystep)[R], PanelShared &sh,
-                                         int t, int jbase, int j0) {
-  gj_col<R, U>(row, sig, used, mystep, sh, t, jbase + U, j0);
-  if constexpr (U + 1 < kGroup) gj_group<R, U + 1>(row, sig, used, mystep, sh, t, jbase, j0);
+                                         unsigned (&umask)[R], int (&mystep)[R],
+                                         PanelShared &sh, int t, int jbase, int j0) {
+  gj_col<R, U>(row, sig, umask, mystep, sh, t, jbase + U, j0);
+  if constexpr (U + 1 < kGroup) gj_group<R, U + 1>(row, sig, umask, mystep, sh, t, jbase, j0);
 }
 
 template <class MA, class T, int R>
@@ -248,12 +255,12 @@ __global__ void __launch_bounds__(64 * kPanelWaves) k_panel(MA ma, int k, int p,
   __shared__ PanelShared sh;
 
   double row[R][kNB], sig[R];
-  bool used[R];
+  unsigned umask[R];
   int mystep[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     const int g = R * t + i;
-    used[i] = true;
+    umask[i] = 0u;
     mystep[i] = INT_MAX;
     sig[i] = 1.0;
     if (g < ld) {
@@ -261,20 +268,22 @@ __global__ void __launch_bounds__(64 * kPanelWaves) k_panel(MA ma, int k, int p,
 #pragma unroll
       for (int q = 0; q < kNB; ++q) row[i][q] = (double)src[q];
       mystep[i] = mat.rstep[g];
-      used[i] = mystep[i] < j0;
+      umask[i] = mystep[i] < j0 ? 0u : ~0u;
     } else {
 #pragma unroll
       for (int q = 0; q < kNB; ++q) row[i][q] = 0.0;
     }
   }
+  if (t < 2 * kPanelWaves) sh.key[t / kPanelWaves][t % kPanelWaves] = 0.0;   // absent waves
   if (t == 0) sh.bad = -1;
+  __syncthreads();
 
   // Columns in groups of kGroup at static positions 0..kGroup-1; afterwards
   // every row rotates left by kGroup, so after the last group the rows are
   // back in panel order.
 #pragma unroll 1
   for (int jb = 0; jb < kNB; jb += kGroup) {
-    gj_group<R, 0>(row, sig, used, mystep, sh, t, jb, j0);
+    gj_group<R, 0>(row, sig, umask, mystep, sh, t, jb, j0);
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       double tmp[kGroup];
@@ -563,7 +572,7 @@ __global__ void __launch_bounds__(kUpd32Threads) k_update_outer(MA ma, int k, in
 // column.  With outer = 32 every panel updates the whole block.
 template <class MA, class T>
 void invert_blocks(const MA &ma, int nmat, int ld, int k, hipStream_t s, bool prof) {
-  const int wmax = options().outer;
+  const int wmax = nmat >= options().outer_nmat ? options().outer : kNB;
   for (int jo = 0; jo < ld; jo += wmax) {
     const int wo = std::min(wmax, ld - jo);
     for (int p = jo / kNB; p < (jo + wo) / kNB; ++p) {

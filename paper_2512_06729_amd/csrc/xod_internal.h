@@ -83,6 +83,7 @@ struct Options {
   int gemm_mfma = 1;
   int update32 = 1;       // trailing update in panel-wide strips (0: 16-wide)
   int outer = 32;         // Gauss-Jordan outer panel width (32: unblocked)
+  int outer_nmat = 1;     // ... for launches of at least this many blocks
   double refine_tol = 1e-10;   // mixed refinement: converged at this correction ratio
   int gemm_large = 1;     // 128 x 128 product tiles for large batches
   int graph = 1;          // replay captured launch sequences (cyclic reduction)
