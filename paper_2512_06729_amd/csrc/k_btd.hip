@@ -125,8 +125,10 @@ constexpr int kPanelRows = 2;                               // rows per thread
 constexpr int kPanelWaves = kMaxLd / (64 * kPanelRows);     // up to 8 waves
 constexpr int kGroup = 8;                                   // columns per unrolled group
 
+// cand[w][b]: wave w's candidate row for columns of parity b (one base
+// address per wave, so every write of a row folds into the LDS offset field).
 struct PanelShared {
-  double cand[2][kPanelWaves][kNB];
+  double cand[kPanelWaves][2][kNB];
   double key[2][kPanelWaves];
   int piv[kNB];
   int bad;
@@ -188,7 +190,7 @@ __device__ __forceinline__ void gj_col(double (&row)[R][kNB], double (&sig)[R],
     for (int i = 0; i < R; ++i)
       if (i == iw) {
         if (R * t + i == rw) {
-          double *dst = sh.cand[buf][wid];
+          double *dst = sh.cand[wid][buf];
 #pragma unroll
           for (int q = 0; q < kNB; ++q)
             if (q != U) dst[q] = row[i][q];
@@ -207,7 +209,7 @@ __device__ __forceinline__ void gj_col(double (&row)[R][kNB], double (&sig)[R],
     return;
   }
   const int r = key_row(K);
-  const double *prow = sh.cand[buf][r / (64 * R)];
+  const double *prow = sh.cand[r / (64 * R)][buf];
   double npiv = prow[U];
   if (npiv != npiv) {                  // zero or non-finite pivot
     if (t == 0 && sh.bad < 0) sh.bad = jcol;
@@ -250,7 +252,7 @@ __global__ void __launch_bounds__(64 * kPanelWaves) k_panel(MA ma, int k, int p,
   MatRef<T> mat;
   if (!ma(blockIdx.x, k, mat)) return;
   const int t = threadIdx.x;
-  T *W = mat.W;
+  const auto W = gmem(mat.W);
   const int j0 = p * kNB;
   __shared__ PanelShared sh;
 
@@ -264,7 +266,7 @@ __global__ void __launch_bounds__(64 * kPanelWaves) k_panel(MA ma, int k, int p,
     mystep[i] = INT_MAX;
     sig[i] = 1.0;
     if (g < ld) {
-      const T *src = W + (size_t)g * ld + j0;
+      const auto src = W + (size_t)g * ld + j0;
 #pragma unroll
       for (int q = 0; q < kNB; ++q) row[i][q] = (double)src[q];
       mystep[i] = mat.rstep[g];
@@ -302,7 +304,7 @@ __global__ void __launch_bounds__(64 * kPanelWaves) k_panel(MA ma, int k, int p,
   for (int i = 0; i < R; ++i) {
     const int g = R * t + i;
     if (g < ld) {
-      T *dst = W + (size_t)g * ld + j0;
+      const auto dst = W + (size_t)g * ld + j0;
 #pragma unroll
       for (int q = 0; q < kNB; ++q) dst[q] = (T)(row[i][q] * sig[i]);
       mat.rstep[g] = mystep[i];
@@ -335,9 +337,9 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(MA ma, int k, int p, int
   const int s = s0 + blockIdx.x;
   const int c0 = s * kStrip;
   if (c0 >= ld || (c0 >= j0 && c0 < j0 + kNB) || (s >= skip0 && s < skip1)) return;
-  T *W = mat.W;
-  const int *piv = mat.piv + j0;
-  const int *rstep = mat.rstep;
+  const auto W = gmem(mat.W);
+  const auto piv = gmem((const int *)mat.piv) + j0;
+  const auto rstep = gmem((const int *)mat.rstep);
 
   __shared__ T sU[kNB][kStrip];               // U = W[piv[J], strip]
   const int t = threadIdx.x;
@@ -347,23 +349,25 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(MA ma, int k, int p, int
   if (kMfma) {
     // Prefetch this wave's tiles (A operand, C tile, pivot mask) before U is
     // published, so their latency overlaps the U gather.
+    // The pivot mask is applied when the tile is used, so that no load waits
+    // for another.
     constexpr int kMaxTiles = kMaxLd / 16 / (kUpdThreads / 64);
     T av[kMaxTiles][kNB / 4];
     T cv[kMaxTiles][4];
+    int sv[kMaxTiles][4];
 #pragma unroll
     for (int u = 0; u < kMaxTiles; ++u) {
       const int tile = wid + nwave * u;
       if (tile < ntile) {
         const int rbase = tile * 16;
-        const T *Arow = W + (size_t)(rbase + (lane & 15)) * ld + j0;
+        const auto Arow = W + (size_t)(rbase + (lane & 15)) * ld + j0;
 #pragma unroll
         for (int kk = 0; kk < kNB / 4; ++kk) av[u][kk] = Arow[4 * kk + (lane >> 4)];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int row = rbase + mfma_row(T(0), lane, i);
-          const int st = rstep[row];
-          const bool piv_here = st >= j0 && st < j0 + kNB;
-          cv[u][i] = piv_here ? T(0) : W[(size_t)row * ld + c0 + (lane & 15)];
+          sv[u][i] = rstep[row];
+          cv[u][i] = W[(size_t)row * ld + c0 + (lane & 15)];
         }
       }
     }
@@ -381,7 +385,7 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(MA ma, int k, int p, int
         const int rbase = tile * 16;
         typename Vec4<T>::type accv;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) accv[i] = cv[u][i];
+        for (int i = 0; i < 4; ++i) accv[i] = (sv[u][i] >= j0 && sv[u][i] < j0 + kNB) ? T(0) : cv[u][i];
 #pragma unroll
         for (int kk = 0; kk < kNB / 4; ++kk)
           accv = mfma16(av[u][kk], sU[4 * kk + (lane >> 4)][lane & 15], accv);
@@ -402,9 +406,9 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(MA ma, int k, int p, int
     const int col = t & 15;
     for (int row = t >> 4; row < ld; row += blockDim.x >> 4) {
       const int st = rstep[row];
-      const bool piv_here = st >= j0 && st < j0 + kNB;
-      T acc = piv_here ? T(0) : W[(size_t)row * ld + c0 + col];
-      const T *Arow = W + (size_t)row * ld + j0;
+      const T cw = W[(size_t)row * ld + c0 + col];
+      T acc = (st >= j0 && st < j0 + kNB) ? T(0) : cw;
+      const auto Arow = W + (size_t)row * ld + j0;
 #pragma unroll 8
       for (int q = 0; q < kNB; ++q) acc = fma(Arow[q], sU[q][col], acc);
       W[(size_t)row * ld + c0 + col] = acc;
@@ -428,9 +432,9 @@ __global__ void __launch_bounds__(kUpd32Threads) k_update32(MA ma, int k, int p,
   const int c0 = q * kNB;
   if (q == p || q == skip || c0 >= ld) return;
   const int j0 = p * kNB;
-  T *W = mat.W;
-  const int *piv = mat.piv + j0;
-  const int *rstep = mat.rstep;
+  const auto W = gmem(mat.W);
+  const auto piv = gmem((const int *)mat.piv) + j0;
+  const auto rstep = gmem((const int *)mat.rstep);
   __shared__ T sU[kNB][kNB + 1];
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   for (int e = t; e < kNB * kNB; e += blockDim.x) {
@@ -447,20 +451,21 @@ __global__ void __launch_bounds__(kUpd32Threads) k_update32(MA ma, int k, int p,
   __syncthreads();   // every wave holds U before any pivot row of the strip is rewritten
 
   const int ntile = ld / 16;
+  // Loads only: the pivot mask is applied when the tile is used, so the
+  // next tile's loads stay in flight during the current tile's MFMAs.
   T av[kNB / 4], cv[2][4];
+  int sv[4];
   auto load = [&](int tile) {
     const int rbase = tile * 16;
-    const T *Arow = W + (size_t)(rbase + (lane & 15)) * ld + j0;
+    const auto Arow = W + (size_t)(rbase + (lane & 15)) * ld + j0;
 #pragma unroll
     for (int kk = 0; kk < kNB / 4; ++kk) av[kk] = Arow[4 * kk + (lane >> 4)];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = rbase + mfma_row(T(0), lane, i);
-      const int st = rstep[row];
-      const bool piv_here = st >= j0 && st < j0 + kNB;
+      sv[i] = rstep[row];
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
-        cv[h][i] = piv_here ? T(0) : W[(size_t)row * ld + c0 + 16 * h + (lane & 15)];
+      for (int h = 0; h < 2; ++h) cv[h][i] = W[(size_t)row * ld + c0 + 16 * h + (lane & 15)];
     }
   };
   int tile = wid;
@@ -471,9 +476,11 @@ __global__ void __launch_bounds__(kUpd32Threads) k_update32(MA ma, int k, int p,
 #pragma unroll
     for (int kk = 0; kk < kNB / 4; ++kk) a_now[kk] = av[kk];
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int i = 0; i < 4; ++i) {
+      const bool piv_here = sv[i] >= j0 && sv[i] < j0 + kNB;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc[h][i] = cv[h][i];
+      for (int h = 0; h < 2; ++h) acc[h][i] = piv_here ? T(0) : cv[h][i];
+    }
     const int cur = tile;
     tile += 4;
     if (tile < ntile) load(tile);   // next tile's operands in flight during the MFMAs
@@ -524,9 +531,9 @@ __global__ void __launch_bounds__(kUpd32Threads) k_update_outer(MA ma, int k, in
   if (!ma(blockIdx.y, k, mat)) return;
   const int c0 = blockIdx.x * kNB;
   if (c0 >= ld || (c0 >= jo && c0 < jo + WO)) return;
-  T *W = mat.W;
-  const int *piv = mat.piv + jo;
-  const int *rstep = mat.rstep;
+  const auto W = gmem(mat.W);
+  const auto piv = gmem((const int *)mat.piv) + jo;
+  const auto rstep = gmem((const int *)mat.rstep);
   __shared__ T sU[WO][kNB + 1];
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   for (int e = t; e < WO * kNB; e += blockDim.x) {
@@ -538,7 +545,7 @@ __global__ void __launch_bounds__(kUpd32Threads) k_update_outer(MA ma, int k, in
   for (int tile = wid; tile < ntile; tile += 4) {
     const int rbase = tile * 16;
     T av[WO / 4];
-    const T *Arow = W + (size_t)(rbase + (lane & 15)) * ld + jo;
+    const auto Arow = W + (size_t)(rbase + (lane & 15)) * ld + jo;
 #pragma unroll
     for (int kk = 0; kk < WO / 4; ++kk) av[kk] = Arow[4 * kk + (lane >> 4)];
     typename Vec4<T>::type acc[2];
@@ -548,8 +555,10 @@ __global__ void __launch_bounds__(kUpd32Threads) k_update_outer(MA ma, int k, in
       const int st = rstep[row];
       const bool piv_here = st >= jo && st < jo + WO;
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
-        acc[h][i] = piv_here ? T(0) : W[(size_t)row * ld + c0 + 16 * h + (lane & 15)];
+      for (int h = 0; h < 2; ++h) {
+        const T cw = W[(size_t)row * ld + c0 + 16 * h + (lane & 15)];
+        acc[h][i] = piv_here ? T(0) : cw;
+      }
     }
 #pragma unroll
     for (int kk = 0; kk < WO / 4; ++kk)

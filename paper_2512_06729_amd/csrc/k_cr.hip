@@ -50,8 +50,8 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmOp<T> *ops, int
   const int nk1 = ld / kGemmK;
   const int nk = g.A2 ? 2 * nk1 : nk1;
   for (int m = threadIdx.x; m < ld; m += blockDim.x) {
-    sbg[0][m] = g.bg ? in_block(g.bg[m], ld) : m;
-    sbg[1][m] = g.bg2 ? in_block(g.bg2[m], ld) : m;
+    sbg[0][m] = g.bg ? in_block(gmem(g.bg)[m], ld) : m;
+    sbg[1][m] = g.bg2 ? in_block(gmem(g.bg2)[m], ld) : m;
   }
   __syncthreads();
   // this thread's staging element: A (row t/16, k t%16), B (k t/64, col t%64)
@@ -61,8 +61,8 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmOp<T> *ops, int
   T ra, rb;
   auto gload = [&](int kt) {
     const bool second = kt >= nk1;
-    const T *A = second ? g.A2 : g.A;
-    const T *B = second ? g.B2 : g.B;
+    const auto A = gmem(second ? g.A2 : g.A);
+    const auto B = gmem(second ? g.B2 : g.B);
     const int k0 = (second ? kt - nk1 : kt) * kGemmK;
     ra = arow_ok ? A[(size_t)(tm0 + ar) * ld + k0 + ak] : T(0);
     const int brow = sbg[second ? 1 : 0][k0 + bk];
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmOp<T> *ops, int
   for (int i = 0; i < 4; ++i) {
     const int r = tm0 + wr * 16 + mfma_row(T(0), lane, i);
     if (r < ld && c < ld) {
-      T *p = g.C + (size_t)r * ld + c;
+      const auto p = gmem(g.C) + (size_t)r * ld + c;
       const double v = g.alpha * (double)acc[i];
       *p = (T)(g.beta ? (double)*p + v : v);
     }
@@ -121,8 +121,8 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_l(const GemmOp<T> *ops, i
   const int nk1 = ld / kGemmK;
   const int nk = g.A2 ? 2 * nk1 : nk1;
   for (int m = threadIdx.x; m < ld; m += blockDim.x) {
-    sbg[0][m] = g.bg ? in_block(g.bg[m], ld) : m;
-    sbg[1][m] = g.bg2 ? in_block(g.bg2[m], ld) : m;
+    sbg[0][m] = g.bg ? in_block(gmem(g.bg)[m], ld) : m;
+    sbg[1][m] = g.bg2 ? in_block(gmem(g.bg2)[m], ld) : m;
   }
   __syncthreads();
   // staging: two A elements (rows t/16 and t/16 + 64, k t%16) and two B
@@ -133,8 +133,8 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_l(const GemmOp<T> *ops, i
   T ra[2], rb[2];
   auto gload = [&](int kt) {
     const bool second = kt >= nk1;
-    const T *A = second ? g.A2 : g.A;
-    const T *B = second ? g.B2 : g.B;
+    const auto A = gmem(second ? g.A2 : g.A);
+    const auto B = gmem(second ? g.B2 : g.B);
     const int k0 = (second ? kt - nk1 : kt) * kGemmK;
     ra[0] = a0 ? A[(size_t)(tm0 + ar) * ld + k0 + ak] : T(0);
     ra[1] = a1 ? A[(size_t)(tm0 + ar + 64) * ld + k0 + ak] : T(0);
@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_l(const GemmOp<T> *ops, i
       for (int q = 0; q < 4; ++q) {
         const int r = tm0 + wr * 32 + i * 16 + mfma_row(T(0), lane, q);
         if (r < ld && c < ld) {
-          T *p = g.C + (size_t)r * ld + c;
+          const auto p = gmem(g.C) + (size_t)r * ld + c;
           const double v = g.alpha * (double)acc[i][j][q];
           *p = (T)(g.beta ? (double)*p + v : v);
         }
@@ -236,29 +236,59 @@ hipError_t launch_cr_level0(const CrLevel0Op<T> *dops, int count, int ld, hipStr
 }
 
 // ---------------------------------------------------------------------------
-// Matrix-vector terms.  One work-group per 16 output rows of one op; the
-// (gathered) input vectors are staged in LDS, each wave reduces 4 rows.
+// Matrix-vector terms.  One work-group of four waves per 8 output rows of
+// one op; the (gathered) input vectors are staged in LDS.  Each wave reduces
+// two rows, with every matrix element it needs loaded before the first is
+// used (ld <= kMaxLd: at most 16 per lane, row and term).
+constexpr int kMvRows = 2;                 // rows per wave
+constexpr int kMvChunks = kMaxLd / 64;     // row elements per lane
+
 template <class T>
 __global__ void __launch_bounds__(256) k_mv(const MvOp<T> *ops, int ld) {
   const MvOp<T> &o = ops[blockIdx.y];
   __shared__ double xs[2][kMaxLd];
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-  for (int q = 0; q < o.nterm; ++q) {
+  const int nterm = o.nterm;
+  for (int q = 0; q < nterm; ++q) {
     const MvTerm<T> &tm = o.t[q];
-    for (int m = t; m < ld; m += blockDim.x) xs[q][m] = tm.x[tm.xm ? in_block(tm.xm[m], ld) : m];
+    const auto x = gmem(tm.x);
+    for (int m = t; m < ld; m += blockDim.x)
+      xs[q][m] = x[tm.xm ? in_block(gmem(tm.xm)[m], ld) : m];
   }
+  const int j0 = (blockIdx.x * 4 + wid) * kMvRows;
+  T mv[kMvRows][2][kMvChunks];
+#pragma unroll
+  for (int rr = 0; rr < kMvRows; ++rr)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int j = j0 + rr;
+      const MvTerm<T> &tm = o.t[q];
+      const bool on = q < nterm && tm.M && j < ld;
+      const auto row = gmem(tm.M) + (size_t)(on && tm.rm ? in_block(gmem(tm.rm)[j], ld) : j) * ld;
+#pragma unroll
+      for (int c = 0; c < kMvChunks; ++c) {
+        const int m = lane + 64 * c;
+        mv[rr][q][c] = (on && m < ld) ? row[m] : T(0);
+      }
+    }
   __syncthreads();
-  for (int rr = 0; rr < 4; ++rr) {
-    const int j = blockIdx.x * 16 + wid * 4 + rr;
+#pragma unroll
+  for (int rr = 0; rr < kMvRows; ++rr) {
+    const int j = j0 + rr;
     if (j >= ld) break;
     double y = o.b ? o.b[j] : 0.0;
-    for (int q = 0; q < o.nterm; ++q) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (q >= nterm) break;
       const MvTerm<T> &tm = o.t[q];
       double v;
       if (tm.M) {
-        const T *row = tm.M + (size_t)(tm.rm ? in_block(tm.rm[j], ld) : j) * ld;
         double z = 0.0;
-        for (int m = lane; m < ld; m += 64) z = fma((double)row[m], xs[q][m], z);
+#pragma unroll
+        for (int c = 0; c < kMvChunks; ++c) {
+          const int m = lane + 64 * c;
+          if (m < ld) z = fma((double)mv[rr][q][c], xs[q][m], z);
+        }
         for (int off = 32; off > 0; off >>= 1) z += __shfl_xor(z, off, 64);
         v = z;
       } else {
@@ -275,7 +305,8 @@ hipError_t launch_mv(const MvOp<T> *dops, int count, int ld, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   const bool prof = options().profile != 0;
   if (prof) prof_begin(kProfSolve, s);
-  hipLaunchKernelGGL((k_mv<T>), dim3((ld + 15) / 16, count), dim3(256), 0, s, dops, ld);
+  const int rows = 4 * kMvRows;
+  hipLaunchKernelGGL((k_mv<T>), dim3((ld + rows - 1) / rows, count), dim3(256), 0, s, dops, ld);
   if (prof) prof_end(kProfSolve, s);
   return hipGetLastError();
 }
