@@ -128,7 +128,7 @@ constexpr int kGroup = 8;                                   // columns per unrol
 // cand[w][b]: wave w's candidate row for columns of parity b (one base
 // address per wave, so every write of a row folds into the LDS offset field).
 struct PanelShared {
-  double cand[kPanelWaves][2][kNB];
+  alignas(16) double cand[kPanelWaves][2][kNB];
   double key[2][kPanelWaves];
   int piv[kNB];
   int bad;
@@ -190,12 +190,12 @@ __device__ __forceinline__ void gj_col(double (&row)[R][kNB], double (&sig)[R],
     for (int i = 0; i < R; ++i)
       if (i == iw) {
         if (R * t + i == rw) {
-          double *dst = sh.cand[wid][buf];
-#pragma unroll
-          for (int q = 0; q < kNB; ++q)
-            if (q != U) dst[q] = row[i][q];
           const double pv = row[i][U];
-          dst[U] = (fabs(pv) > 0.0 && isfinite(pv)) ? 1.0 / pv : __builtin_nan("");
+          const double rp = (fabs(pv) > 0.0 && isfinite(pv)) ? 1.0 / pv : __builtin_nan("");
+          double2 *dst = reinterpret_cast<double2 *>(sh.cand[wid][buf]);
+#pragma unroll
+          for (int q = 0; q < kNB; q += 2)   // 16-byte stores
+            dst[q / 2] = make_double2(q == U ? rp : row[i][q], q + 1 == U ? rp : row[i][q + 1]);
         }
       }
   }
@@ -209,8 +209,15 @@ __device__ __forceinline__ void gj_col(double (&row)[R][kNB], double (&sig)[R],
     return;
   }
   const int r = key_row(K);
-  const double *prow = sh.cand[r / (64 * R)][buf];
-  double npiv = prow[U];
+  const double2 *prow = reinterpret_cast<const double2 *>(sh.cand[r / (64 * R)][buf]);
+  double pr[kNB];
+#pragma unroll
+  for (int q = 0; q < kNB; q += 2) {     // 16-byte loads
+    const double2 v = prow[q / 2];
+    pr[q] = v.x;
+    pr[q + 1] = v.y;
+  }
+  double npiv = pr[U];
   if (npiv != npiv) {                  // zero or non-finite pivot
     if (t == 0 && sh.bad < 0) sh.bad = jcol;
     npiv = 1.0;
@@ -226,7 +233,7 @@ __device__ __forceinline__ void gj_col(double (&row)[R][kNB], double (&sig)[R],
 #pragma unroll
   for (int qq = 1; qq < kNB; ++qq) {   // the next column first
     const int q = (U + qq) % kNB;
-    const double pq = prow[q];
+    const double pq = pr[q];
 #pragma unroll
     for (int i = 0; i < R; ++i) row[i][q] = fma(-fm[i], pq, row[i][q]);
   }
