@@ -273,6 +273,9 @@ xod_status xod_last_error(char *buf, size_t len);
  *            0 = always 16-column strips by 16-wave work-groups.
  *   "gemm_large": 1 = cyclic-reduction block products of large batches use
  *            128 x 128 output tiles (default); 0 = always 64 x 64.
+ *   "gemm_k": K step of the block products staged through LDS, 16 or 32
+ *            (default 32); every element sums its K terms in the same order
+ *            with either.
  *   "refine_tol_exp": e in 6..15: a mixed-precision solve has converged
  *            once the largest layer-wise correction ratio max|d|/max|x| is
  *            at most 10^-e (default 10).
@@ -281,6 +284,8 @@ xod_status xod_last_error(char *buf, size_t len);
  *            update only its own columns, then one rank-width update covers
  *            the rest of the block (fewer passes over the block, more
  *            launches); 32 = every panel updates the whole block.
+ *   "outer_nmat": the outer panel width applies to launches of at least
+ *            this many blocks (default 1); smaller launches use 32.
  *   "graph": 1 = the cyclic-reduction factor and solve launch sequences of a
  *            column are captured once into HIP graphs (kernel nodes only)
  *            and replayed (default); 0 = launched one by one.  Graphs are
@@ -289,6 +294,11 @@ xod_status xod_last_error(char *buf, size_t len);
  *              profiled kernel launch (default 0).
  *   "profile_every": profile layer k only when k % value == 0 (default 1). */
 xod_status xod_set_option(const char *name, int64_t value);
+
+/* Current value of a kernel option above (refine_tol_exp: the exponent e of
+ * the current tolerance 10^-e, rounded).  XOD_EINVAL for an unknown name or a
+ * null pointer. */
+xod_status xod_get_option(const char *name, int64_t *value);
 
 /* Sum of the recorded launch durations (ms) and the launch count of one
  * kernel kind: "panel", "update", "prologue", "solve", "jacobian", "rates",

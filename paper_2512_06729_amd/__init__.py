@@ -120,6 +120,7 @@ _f = {
                                           ctypes.POINTER(SSOpts), ctypes.POINTER(SSResult)),
     "xod_last_error": _sig("xod_last_error", ctypes.c_char_p, ctypes.c_size_t),
     "xod_set_option": _sig("xod_set_option", ctypes.c_char_p, ctypes.c_int64),
+    "xod_get_option": _sig("xod_get_option", ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)),
     "xod_batch_create": _sig("xod_batch_create", ctypes.POINTER(c_void_p), c_int32,
                              ctypes.POINTER(c_void_p)),
     "xod_batch_destroy": _sig("xod_batch_destroy", c_void_p),
@@ -174,6 +175,12 @@ def _check(status):
 
 def set_option(name, value):
     _check(_f["xod_set_option"](name.encode(), int(value)))
+
+
+def get_option(name):
+    v = ctypes.c_int64()
+    _check(_f["xod_get_option"](name.encode(), ctypes.byref(v)))
+    return v.value
 
 
 def _ptr(arr, ctype):

@@ -112,6 +112,11 @@ extern "C" xod_status xod_set_option(const char *name, int64_t value) {
     options().gemm_large = (int)value;
     return XOD_OK;
   }
+  if (std::strcmp(name, "gemm_k") == 0) {
+    XOD_CHECK(value == 16 || value == 32, "xod_set_option: gemm_k must be 16 or 32");
+    options().gemm_k = (int)value;
+    return XOD_OK;
+  }
   if (std::strcmp(name, "refine_tol_exp") == 0) {
     XOD_CHECK(value >= 6 && value <= 15, "xod_set_option: refine_tol_exp must be in 6..15");
     options().refine_tol = std::pow(10.0, -(double)value);
@@ -149,6 +154,27 @@ extern "C" xod_status xod_set_option(const char *name, int64_t value) {
     return XOD_OK;
   }
   set_error(std::string("xod_set_option: unknown option ") + name);
+  return XOD_EINVAL;
+}
+
+extern "C" xod_status xod_get_option(const char *name, int64_t *value) {
+  XOD_CHECK(name != nullptr && value != nullptr, "xod_get_option: null argument");
+  const Options &o = options();
+  struct Entry { const char *name; int64_t v; };
+  const Entry entries[] = {
+      {"gemm", o.gemm_mfma},           {"gemm_large", o.gemm_large},
+      {"gemm_k", o.gemm_k},            {"outer", o.outer},
+      {"outer_nmat", o.outer_nmat},    {"update32", o.update32},
+      {"graph", o.graph},              {"profile", o.profile},
+      {"profile_every", o.profile_every},
+      {"refine_tol_exp", (int64_t)std::lround(-std::log10(o.refine_tol))},
+  };
+  for (const Entry &e : entries)
+    if (std::strcmp(name, e.name) == 0) {
+      *value = e.v;
+      return XOD_OK;
+    }
+  set_error(std::string("xod_get_option: unknown option ") + name);
   return XOD_EINVAL;
 }
 

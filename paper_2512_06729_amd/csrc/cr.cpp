@@ -307,7 +307,8 @@ xod_status CrPlan<T>::enqueue_solve(hipStream_t s, xod_column *c) {
 // stream.  The graphs hold kernel nodes only.
 template <class T>
 xod_status CrPlan<T>::replay(hipGraphExec_t *g, bool factor, xod_column *c) {
-  const long long key = ((long long)options().outer_nmat * 256 + options().outer) * 8 +
+  const long long key = (((long long)options().outer_nmat * 256 + options().outer) * 64 +
+                         options().gemm_k) * 8 +
                         options().gemm_large * 4 + options().gemm_mfma * 2 + options().update32;
   if (graph_gemm != key) {
     if (gfactor) XOD_HIP(hipGraphExecDestroy(gfactor));

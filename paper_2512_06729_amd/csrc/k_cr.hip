@@ -28,125 +28,71 @@ __device__ __forceinline__ int in_block(int i, int ld) {
 }
 
 // ---------------------------------------------------------------------------
-// Block products.  One work-group of 16 waves per 64 x 64 output tile; wave w
-// owns the 16 x 16 tile (w/4, w%4).  K is staged through LDS in steps of 16
-// (double-buffered: the next step's global loads are issued before the MFMAs
-// of the current one).  Rows / columns beyond ld are never touched: ld is a
-// multiple of 32, so a tile is either full or its second half is outside.
-constexpr int kGemmTile = 64;
-constexpr int kGemmK = 16;
+// Block products.  One work-group of 16 waves per BM x BM output tile (BM =
+// 64 or 128); the waves form a 4 x 4 grid, each owning a (BM/4)^2 sub-tile
+// of (BM/64)^2 16 x 16 MFMA accumulators, so each LDS fragment feeds BM/64
+// MFMAs.  K is staged through LDS in steps of KB (double-buffered: the next
+// step's global loads are issued before the MFMAs of the current one).  Every
+// output element accumulates its K terms in increasing order whatever BM and
+// KB are.  Rows / columns beyond ld are never touched (ld is a multiple of
+// 32).
 constexpr int kGemmThreads = 1024;
 
-template <class T>
+template <class T, int BM, int KB>
 __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmOp<T> *ops, int ld) {
+  constexpr int TM = BM / 64;                       // MFMA tiles per wave and dimension
+  constexpr int AL = BM * KB / kGemmThreads;        // A elements staged per thread
+  constexpr int BL = KB * BM / kGemmThreads;        // B elements staged per thread
   const GemmOp<T> g = ops[blockIdx.z];
-  const int tm0 = blockIdx.y * kGemmTile, tn0 = blockIdx.x * kGemmTile;
+  const int tm0 = blockIdx.y * BM, tn0 = blockIdx.x * BM;
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   const int wr = wid >> 2, wc = wid & 3;
-  __shared__ T As[2][kGemmTile][kGemmK + 1];
-  __shared__ T Bs[2][kGemmK][kGemmTile + 2];
+  __shared__ T As[2][BM][KB + 1];
+  __shared__ T Bs[2][KB][BM + 2];
   __shared__ int sbg[2][kMaxLd];   // the row gathers of B and B2
-  typename Vec4<T>::type acc = {0, 0, 0, 0};
-  const int nk1 = ld / kGemmK;
+  typename Vec4<T>::type acc[TM][TM];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TM; ++j) acc[i][j] = {0, 0, 0, 0};
+  const int nk1 = ld / KB;
   const int nk = g.A2 ? 2 * nk1 : nk1;
   for (int m = threadIdx.x; m < ld; m += blockDim.x) {
     sbg[0][m] = g.bg ? in_block(gmem(g.bg)[m], ld) : m;
     sbg[1][m] = g.bg2 ? in_block(gmem(g.bg2)[m], ld) : m;
   }
   __syncthreads();
-  // this thread's staging element: A (row t/16, k t%16), B (k t/64, col t%64)
-  const int ar = t / kGemmK, ak = t % kGemmK;
-  const int bk = t / kGemmTile, bc = t % kGemmTile;
-  const bool arow_ok = tm0 + ar < ld, bcol_ok = tn0 + bc < ld;
-  T ra, rb;
+  // staging element e of this thread: A (row (t + e*1024) / KB, k % KB),
+  // B (k (t + e*1024) / BM, column % BM)
+  T ra[AL], rb[BL];
   auto gload = [&](int kt) {
     const bool second = kt >= nk1;
     const auto A = gmem(second ? g.A2 : g.A);
     const auto B = gmem(second ? g.B2 : g.B);
-    const int k0 = (second ? kt - nk1 : kt) * kGemmK;
-    ra = arow_ok ? A[(size_t)(tm0 + ar) * ld + k0 + ak] : T(0);
-    const int brow = sbg[second ? 1 : 0][k0 + bk];
-    rb = bcol_ok ? B[(size_t)brow * ld + tn0 + bc] : T(0);
-  };
-  gload(0);
-  As[0][ar][ak] = ra;
-  Bs[0][bk][bc] = rb;
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) gload(kt + 1);
-#pragma unroll
-    for (int kk = 0; kk < kGemmK / 4; ++kk) {
-      const T av = As[buf][wr * 16 + (lane & 15)][kk * 4 + (lane >> 4)];
-      const T bv = Bs[buf][kk * 4 + (lane >> 4)][wc * 16 + (lane & 15)];
-      acc = mfma16(av, bv, acc);
-    }
-    if (kt + 1 < nk) {
-      As[buf ^ 1][ar][ak] = ra;
-      Bs[buf ^ 1][bk][bc] = rb;
-    }
-    __syncthreads();
-  }
-  const int c = tn0 + wc * 16 + (lane & 15);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = tm0 + wr * 16 + mfma_row(T(0), lane, i);
-    if (r < ld && c < ld) {
-      const auto p = gmem(g.C) + (size_t)r * ld + c;
-      const double v = g.alpha * (double)acc[i];
-      *p = (T)(g.beta ? (double)*p + v : v);
-    }
-  }
-}
-
-// The same product with 128 x 128 output tiles for large batches: 16 waves
-// in a 4 x 4 grid, each owning a 32 x 32 sub-tile (2 x 2 MFMA accumulators),
-// so each LDS fragment feeds two MFMAs and a K step holds 16 MFMAs per wave.
-constexpr int kGemmTileL = 128;
-
-template <class T>
-__global__ void __launch_bounds__(kGemmThreads) k_gemm_l(const GemmOp<T> *ops, int ld) {
-  const GemmOp<T> g = ops[blockIdx.z];
-  const int tm0 = blockIdx.y * kGemmTileL, tn0 = blockIdx.x * kGemmTileL;
-  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-  const int wr = wid >> 2, wc = wid & 3;
-  __shared__ T As[2][kGemmTileL][kGemmK + 1];
-  __shared__ T Bs[2][kGemmK][kGemmTileL + 2];
-  __shared__ int sbg[2][kMaxLd];
-  typename Vec4<T>::type acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = {0, 0, 0, 0};
-  const int nk1 = ld / kGemmK;
-  const int nk = g.A2 ? 2 * nk1 : nk1;
-  for (int m = threadIdx.x; m < ld; m += blockDim.x) {
-    sbg[0][m] = g.bg ? in_block(gmem(g.bg)[m], ld) : m;
-    sbg[1][m] = g.bg2 ? in_block(gmem(g.bg2)[m], ld) : m;
-  }
-  __syncthreads();
-  // staging: two A elements (rows t/16 and t/16 + 64, k t%16) and two B
-  // elements (k t/128 and t/128 + 8, column t%128) per thread
-  const int ar = t / kGemmK, ak = t % kGemmK;
-  const int bk = t / kGemmTileL, bc = t % kGemmTileL;
-  const bool a0 = tm0 + ar < ld, a1 = tm0 + ar + 64 < ld, bok = tn0 + bc < ld;
-  T ra[2], rb[2];
-  auto gload = [&](int kt) {
-    const bool second = kt >= nk1;
-    const auto A = gmem(second ? g.A2 : g.A);
-    const auto B = gmem(second ? g.B2 : g.B);
-    const int k0 = (second ? kt - nk1 : kt) * kGemmK;
-    ra[0] = a0 ? A[(size_t)(tm0 + ar) * ld + k0 + ak] : T(0);
-    ra[1] = a1 ? A[(size_t)(tm0 + ar + 64) * ld + k0 + ak] : T(0);
+    const int k0 = (second ? kt - nk1 : kt) * KB;
     const int *gb = sbg[second ? 1 : 0];
-    rb[0] = bok ? B[(size_t)gb[k0 + bk] * ld + tn0 + bc] : T(0);
-    rb[1] = bok ? B[(size_t)gb[k0 + bk + 8] * ld + tn0 + bc] : T(0);
+#pragma unroll
+    for (int e = 0; e < AL; ++e) {
+      const int idx = t + e * kGemmThreads, r = tm0 + idx / KB;
+      ra[e] = r < ld ? A[(size_t)r * ld + k0 + idx % KB] : T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < BL; ++e) {
+      const int idx = t + e * kGemmThreads, c = tn0 + idx % BM;
+      rb[e] = c < ld ? B[(size_t)gb[k0 + idx / BM] * ld + c] : T(0);
+    }
   };
   auto sstore = [&](int buf) {
-    As[buf][ar][ak] = ra[0];
-    As[buf][ar + 64][ak] = ra[1];
-    Bs[buf][bk][bc] = rb[0];
-    Bs[buf][bk + 8][bc] = rb[1];
+#pragma unroll
+    for (int e = 0; e < AL; ++e) {
+      const int idx = t + e * kGemmThreads;
+      As[buf][idx / KB][idx % KB] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < BL; ++e) {
+      const int idx = t + e * kGemmThreads;
+      Bs[buf][idx / BM][idx % BM] = rb[e];
+    }
   };
   gload(0);
   sstore(0);
@@ -155,28 +101,30 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_l(const GemmOp<T> *ops, i
     const int buf = kt & 1;
     if (kt + 1 < nk) gload(kt + 1);
 #pragma unroll
-    for (int kk = 0; kk < kGemmK / 4; ++kk) {
-      T av[2], bv[2];
+    for (int kk = 0; kk < KB / 4; ++kk) {
+      T av[TM], bv[TM];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) av[i] = As[buf][wr * 32 + i * 16 + (lane & 15)][kk * 4 + (lane >> 4)];
+      for (int i = 0; i < TM; ++i)
+        av[i] = As[buf][(wr * TM + i) * 16 + (lane & 15)][kk * 4 + (lane >> 4)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) bv[j] = Bs[buf][kk * 4 + (lane >> 4)][wc * 32 + j * 16 + (lane & 15)];
+      for (int j = 0; j < TM; ++j)
+        bv[j] = Bs[buf][kk * 4 + (lane >> 4)][(wc * TM + j) * 16 + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = mfma16(av[i], bv[j], acc[i][j]);
+        for (int j = 0; j < TM; ++j) acc[i][j] = mfma16(av[i], bv[j], acc[i][j]);
     }
     if (kt + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int c = tn0 + wc * 32 + j * 16 + (lane & 15);
+    for (int j = 0; j < TM; ++j) {
+      const int c = tn0 + (wc * TM + j) * 16 + (lane & 15);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int r = tm0 + wr * 32 + i * 16 + mfma_row(T(0), lane, q);
+        const int r = tm0 + (wr * TM + i) * 16 + mfma_row(T(0), lane, q);
         if (r < ld && c < ld) {
           const auto p = gmem(g.C) + (size_t)r * ld + c;
           const double v = g.alpha * (double)acc[i][j][q];
@@ -189,15 +137,27 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_l(const GemmOp<T> *ops, i
 template <class T>
 hipError_t launch_gemm(const GemmOp<T> *dops, int count, int ld, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  const int ntl = (ld + kGemmTileL - 1) / kGemmTileL;
-  const int nt = (ld + kGemmTile - 1) / kGemmTile;
+  const int ntl = (ld + 127) / 128;
+  const int nt = (ld + 63) / 64;
   const bool prof = options().profile != 0;
+  const bool k32 = options().gemm_k == 32;
   if (prof) prof_begin(kProfGemm, s);
   // large tiles when the batch alone gives every CU two work-groups
-  if (options().gemm_large && (size_t)count * ntl * ntl >= 512)
-    hipLaunchKernelGGL((k_gemm_l<T>), dim3(ntl, ntl, count), dim3(kGemmThreads), 0, s, dops, ld);
-  else
-    hipLaunchKernelGGL((k_gemm<T>), dim3(nt, nt, count), dim3(kGemmThreads), 0, s, dops, ld);
+  if (options().gemm_large && (size_t)count * ntl * ntl >= 512) {
+    if (k32)
+      hipLaunchKernelGGL((k_gemm<T, 128, 32>), dim3(ntl, ntl, count), dim3(kGemmThreads), 0, s,
+                         dops, ld);
+    else
+      hipLaunchKernelGGL((k_gemm<T, 128, 16>), dim3(ntl, ntl, count), dim3(kGemmThreads), 0, s,
+                         dops, ld);
+  } else {
+    if (k32)
+      hipLaunchKernelGGL((k_gemm<T, 64, 32>), dim3(nt, nt, count), dim3(kGemmThreads), 0, s, dops,
+                         ld);
+    else
+      hipLaunchKernelGGL((k_gemm<T, 64, 16>), dim3(nt, nt, count), dim3(kGemmThreads), 0, s, dops,
+                         ld);
+  }
   if (prof) prof_end(kProfGemm, s);
   return hipGetLastError();
 }

@@ -210,23 +210,27 @@ def test_update_kernels_agree():
 
 
 def test_block_product_tilings_agree():
-    """128 x 128 and 64 x 64 product tiles accumulate every element in the
-    same K order: identical bits."""
+    """128 x 128 and 64 x 64 product tiles, K staged 16 or 32 at a time,
+    accumulate every element in the same K order: identical bits."""
     import paper_2512_06729_amd as xod
     net, col = synth.make_config(3)
     stream = torch.cuda.current_stream().cuda_stream
     gnet = xod.Network(net)
     out = []
+    default_k = xod.get_option("gemm_k")
     try:
-        for large in (0, 1):
+        for large, kstep in ((0, 16), (1, 16), (0, 32), (1, 32)):
             xod.set_option("gemm_large", large)
+            xod.set_option("gemm_k", kstep)
             g = xod.Column(gnet, col, stream=stream, solver=xod.XOD_SOLVER_CR)
             xod.xod_step(g, 1e-5)
             out.append(g.state())
             g.close()
     finally:
         xod.set_option("gemm_large", 1)
-    np.testing.assert_array_equal(out[0], out[1])
+        xod.set_option("gemm_k", default_k)
+    for o in out[1:]:
+        np.testing.assert_array_equal(out[0], o)
 
 
 @pytest.mark.parametrize("solver", [0, 1])
