@@ -270,16 +270,25 @@ extern "C" xod_status xod_network_create(const xod_network_desc *d, xod_network 
         ent[{kv.first, xs[u]}].push_back({6 * r + (int)u, kv.second});
     }
   }
-  std::vector<int> jmap((size_t)S * S, -1), jptr(1, 0), jc_ru;
+  // Nonzero entries in row-major order (the map's order): row y holds
+  // entries jrow[y] .. jrow[y+1]-1, entry e sits in column jcol[e] and sums
+  // contributions jptr[e] .. jptr[e+1]-1, so row y's contributions are
+  // jptr[jrow[y]] .. jptr[jrow[y+1]]-1; jc_col names each one's column.
+  std::vector<int> jrow(S + 1, 0), jcol, jptr(1, 0), jc_ru;
   std::vector<double> jc_nu;
   for (auto &kv : ent) {
-    jmap[(size_t)kv.first.first * S + kv.first.second] = (int)jptr.size() - 1;
+    jrow[kv.first.first + 1]++;
+    jcol.push_back(kv.first.second);
     for (auto &e : kv.second) {
       jc_ru.push_back(e.first);
       jc_nu.push_back(e.second);
     }
     jptr.push_back((int)jc_ru.size());
   }
+  for (int y = 0; y < S; ++y) jrow[y + 1] += jrow[y];
+  std::vector<int> jc_col(jc_ru.size());   // column of each contribution's entry
+  for (size_t e = 0; e + 1 < jptr.size(); ++e)
+    for (int q = jptr[e]; q < jptr[e + 1]; ++q) jc_col[q] = jcol[e];
   net->nnz = (int)jptr.size() - 1;
   net->ncontrib = (int)jc_ru.size();
 
@@ -296,7 +305,8 @@ extern "C" xod_status xod_network_create(const xod_network_desc *d, xod_network 
   XOD_TRY(nalloc(n, &n->inc_ptr, S + 1, inc_ptr.data()));
   XOD_TRY(nalloc(n, &n->inc_r, inc_r.size(), inc_r.data()));
   XOD_TRY(nalloc(n, &n->inc_nu, inc_nu.size(), inc_nu.data()));
-  XOD_TRY(nalloc(n, &n->jmap, jmap.size(), jmap.data()));
+  XOD_TRY(nalloc(n, &n->jrow, jrow.size(), jrow.data()));
+  XOD_TRY(nalloc(n, &n->jc_col, jc_col.size(), jc_col.data()));
   XOD_TRY(nalloc(n, &n->jptr, jptr.size(), jptr.data()));
   XOD_TRY(nalloc(n, &n->jc_ru, jc_ru.size(), jc_ru.data()));
   XOD_TRY(nalloc(n, &n->rsp, rsp.size(), rsp.data()));

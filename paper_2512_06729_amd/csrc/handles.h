@@ -24,7 +24,7 @@ struct xod_network {
   double *params = nullptr, *nasa7 = nullptr, *mass = nullptr;
   int *inc_ptr = nullptr, *inc_r = nullptr;
   double *inc_nu = nullptr;
-  int *jmap = nullptr, *jptr = nullptr, *jc_ru = nullptr, *rsp = nullptr;
+  int *jrow = nullptr, *jc_col = nullptr, *jptr = nullptr, *jc_ru = nullptr, *rsp = nullptr;
   double *jc_nu = nullptr;
   std::vector<double> mass_h;
   int nnz = 0, ncontrib = 0;
@@ -85,7 +85,8 @@ struct xod_column {
     a_.inc_ptr = net->inc_ptr;
     a_.inc_r = net->inc_r;
     a_.inc_nu = net->inc_nu;
-    a_.jmap = net->jmap;
+    a_.jrow = net->jrow;
+    a_.jc_col = net->jc_col;
     a_.jptr = net->jptr;
     a_.jc_ru = net->jc_ru;
     a_.jc_nu = net->jc_nu;

@@ -10,6 +10,7 @@
 // All arithmetic is FP64.  HBM-bound: one thread per output element, reads
 // of per-layer vectors hit L1/L2.
 #include "xod_internal.h"
+#include "mfma.h"
 
 namespace xod {
 
@@ -270,14 +271,39 @@ __global__ void __launch_bounds__(256) k_dwd(Acc acc) {
 
 constexpr int kJacMaxPer = kMaxLd / 64;
 
+// One wave per (layer, block row): the row is assembled in LDS (zeros, the
+// contributions of the row's nonzero entries added in, then the diagonal), then
+// read back by columns and stored with full-row coalesced writes (scaled to
+// unit max-norm in the mixed path).
 template <class Acc, bool kMixed>
 __global__ void __launch_bounds__(256) k_jac(Acc acc) {
   const ColArgs &c = acc(blockIdx.z);
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blockIdx.x * 4 + w;
   const int k = blockIdx.y;
   const int ld = c.ld, S = c.S;
-  if (k >= c.N || i >= ld) return;
+  const bool on = k < c.N && i < ld;
+  __shared__ double rowbuf[4][kMaxLd];
+  double *rb = rowbuf[w];
+  if (on) {
+    for (int j = lane; j < ld; j += 64) rb[j] = 0.0;
+  }
+  __syncthreads();
+  if (on && i < S) {
+    // the row's contributions, spread evenly over the lanes (an entry of a
+    // species in many reactions has hundreds), added into LDS
+    const auto dk = gmem((const double *)c.dwd) + (size_t)k * c.R * 6;
+    const auto jptr = gmem(c.jptr), jrow = gmem(c.jrow);
+    const int q1 = jptr[jrow[i + 1]];
+#pragma unroll 4
+    for (int q = jptr[jrow[i]] + lane; q < q1; q += 64)
+      atomicAdd(&rb[gmem(c.jc_col)[q]], -gmem(c.jc_nu)[q] * dk[gmem(c.jc_ru)[q]]);
+  }
+  __syncthreads();
+  if (on && lane == 0)
+    rb[i] = i < S ? rb[i] + 1.0 / c.dt - c.trd[(size_t)k * S + i] : 1.0;   // identity padding
+  __syncthreads();
+  if (!on) return;
   const size_t ro = (size_t)k * ld + i;
   const size_t so = (size_t)k * S + i;
   const double av = i < S ? -c.trl[so] : 0.0;
@@ -287,41 +313,34 @@ __global__ void __launch_bounds__(256) k_jac(Acc acc) {
 #pragma unroll
   for (int q = 0; q < kJacMaxPer; ++q) {
     const int j = lane + 64 * q;
-    double v = 0.0;
-    if (j < ld) {
-      if (i < S && j < S) {
-        const int idx = c.jmap[(size_t)i * S + j];
-        if (idx >= 0) {
-          double s = 0.0;
-          const double *dk = c.dwd + (size_t)k * c.R * 6;
-          for (int e = c.jptr[idx]; e < c.jptr[idx + 1]; ++e) s += c.jc_nu[e] * dk[c.jc_ru[e]];
-          v = -s;
-        }
-        if (i == j) v += 1.0 / c.dt - c.trd[so];
-      } else if (i == j) {
-        v = 1.0;   // identity padding
-      }
-      if (!kMixed) c.B[ro * ld + j] = v;
-    }
-    vals[q] = v;
-    amax = fmax(amax, fabs(v));
+    vals[q] = j < ld ? rb[j] : 0.0;
+    amax = fmax(amax, fabs(vals[q]));
   }
   if (kMixed) {
     for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
     const double sc = amax > 0.0 ? 1.0 / amax : 1.0;
+    const auto Bf = gmem(c.Bf) + ro * ld;
 #pragma unroll
     for (int q = 0; q < kJacMaxPer; ++q) {
       const int j = lane + 64 * q;
-      if (j < ld) c.Bf[ro * ld + j] = (float)(sc * vals[q]);
+      if (j < ld) Bf[j] = (float)(sc * vals[q]);
     }
     if (lane == 0) {
       c.rs[ro] = sc;
       c.a[ro] = sc * av;
       c.c[ro] = sc * cv;
     }
-  } else if (lane == 0) {
-    c.a[ro] = av;
-    c.c[ro] = cv;
+  } else {
+    const auto B = gmem(c.B) + ro * ld;
+#pragma unroll
+    for (int q = 0; q < kJacMaxPer; ++q) {
+      const int j = lane + 64 * q;
+      if (j < ld) B[j] = vals[q];
+    }
+    if (lane == 0) {
+      c.a[ro] = av;
+      c.c[ro] = cv;
+    }
   }
 }
 

@@ -31,7 +31,8 @@ struct ColArgs {
   const double *params;
   const int *inc_ptr, *inc_r;
   const double *inc_nu;
-  const int *jmap, *jptr, *jc_ru;   // contribution e: slot jc_ru[e] = 6 r + u
+  const int *jrow, *jptr;           // Jacobian nonzeros by row, their contributions
+  const int *jc_ru, *jc_col;        // contribution e: slot jc_ru[e] = 6 r + u, column
   const double *jc_nu;
   const int *rsp;                   // [R*6] distinct species of each reaction
   // grid (device, owned by the column)
