@@ -47,8 +47,11 @@ def cr_levels(N):
     """Layers eliminated / kept at each level of block cyclic reduction."""
     out, rem, h = [], list(range(N)), 1
     while len(rem) > 1:
-        elim = [k for k in rem if (k // h) % 2]
-        kept = [k for k in rem if not (k // h) % 2]
+        if len(rem) == 3 and h > 1:      # both ends of {0, h, 2h} at once
+            elim, kept = [rem[0], rem[2]], [rem[1]]
+        else:
+            elim = [k for k in rem if (k // h) % 2]
+            kept = [k for k in rem if not (k // h) % 2]
         out.append((h, elim, kept))
         rem, h = kept, 2 * h
     return out

@@ -7,7 +7,9 @@
 //   D_k <- D_k - A_k E_{k-h} C_{k-h} - C_k E_{k+h} A_{k+h}
 //   A_k <- -A_k E_{k-h} A_{k-h},   C_k <- -C_k E_{k+h} C_{k+h}
 //   g_k <- g_k - A_k E_{k-h} g_{k-h} - C_k E_{k+h} g_{k+h}
-// until layer 0 alone remains.  Back substitution runs the levels in reverse:
+// until one layer, the root, remains: layer 0, or the middle one when the
+// last level takes both ends of {0, h, 2h}.  Back substitution runs the
+// levels in reverse:
 //   x_k = E_k (g_k - A_k x_{k-h} - C_k x_{k+h})  for the eliminated layers.
 // The result is the solution of the same block system as block Thomas (both
 // are block Gaussian elimination, in different orders); the critical path is
@@ -62,12 +64,24 @@ std::vector<CrLevel> cr_levels(int N) {
   while (rem.size() > 1) {
     CrLevel L;
     L.h = h;
-    for (int k : rem) ((k / h) % 2 ? L.elim : L.kept).push_back(k);
+    if (rem.size() == 3 && h > 1) {
+      // {0, h, 2h}: both ends go at once (neither couples to the other) and
+      // the middle layer is the root, one level sooner than keeping layer 0
+      L.elim = {rem[0], rem[2]};
+      L.kept = {rem[1]};
+    } else {
+      for (int k : rem) ((k / h) % 2 ? L.elim : L.kept).push_back(k);
+    }
     rem = L.kept;
     out.push_back(L);
     h *= 2;
   }
   return out;
+}
+
+int cr_root(int N) {
+  const std::vector<CrLevel> lv = cr_levels(N);
+  return lv.empty() ? 0 : lv.back().kept[0];
 }
 
 size_t cr_extra_blocks(int N) {
@@ -226,14 +240,15 @@ xod_status CrPlan<T>::build(xod_column *c) {
     fwd_cnt[l] = (int)mv.size() - fwd_off[l];
   }
   // root
+  const int root = cr_root(N);
   inv_off[nlev] = (int)inv.size();
-  inv.push_back(MatRef<T>{blk(0), pv(0), rq(0), c->flag, 0});
+  inv.push_back(MatRef<T>{blk(root), pv(root), rq(root), c->flag, root});
   inv_cnt[nlev] = 1;
   root_off = (int)mv.size();
   {
     MvOp<T> o{};
-    o.y = xsv(0);
-    o.t[o.nterm++] = MvTerm<T>{blk(0), pv(0), pv(0), gsv(0), nullptr, 1.0};
+    o.y = xsv(root);
+    o.t[o.nterm++] = MvTerm<T>{blk(root), pv(root), pv(root), gsv(root), nullptr, 1.0};
     mv.push_back(o);
   }
   // back substitution, per level
@@ -245,8 +260,10 @@ xod_status CrPlan<T>::build(xod_column *c) {
       MvOp<T> o{};
       o.b = gsv(k);
       o.y = gsv(k);
-      o.t[o.nterm++] = (l == 0) ? MvTerm<T>{nullptr, nullptr, nullptr, xsv(k - 1), av(k), -1.0}
-                                : MvTerm<T>{aslot(k), nullptr, nullptr, xsv(k - h), nullptr, -1.0};
+      if (k - h >= 0)
+        o.t[o.nterm++] = (l == 0)
+            ? MvTerm<T>{nullptr, nullptr, nullptr, xsv(k - 1), av(k), -1.0}
+            : MvTerm<T>{aslot(k), nullptr, nullptr, xsv(k - h), nullptr, -1.0};
       if (k + h <= N - 1)
         o.t[o.nterm++] = (l == 0)
             ? MvTerm<T>{nullptr, nullptr, nullptr, xsv(k + 1), cv(k), -1.0}

@@ -20,8 +20,10 @@ struct CrLevel {
   std::vector<int> elim, kept; // layers eliminated / kept at this level
 };
 
-// Levels of the reduction of N layers (empty for N = 1); layer 0 is the root.
+// Levels of the reduction of N layers (empty for N = 1).
 std::vector<CrLevel> cr_levels(int N);
+// The layer left after the last level (inverted alone).
+int cr_root(int N);
 // Dense blocks the reduction needs besides the N diagonal blocks.
 size_t cr_extra_blocks(int N);
 
