@@ -271,6 +271,8 @@ xod_status xod_last_error(char *buf, size_t len);
  *   "update32": 1 = MFMA trailing update in 32-column strips by four-wave
  *            work-groups when a launch updates many blocks (default);
  *            0 = always 16-column strips by 16-wave work-groups.
+ *   "update32_min": "many" above: at least this many (block, 32-column
+ *            strip) pairs in the launch (default 200).
  *   "gemm_large": 1 = cyclic-reduction block products of large batches use
  *            128 x 128 output tiles (default); 0 = always 64 x 64.
  *   "gemm_k": K step of the block products staged through LDS, 16 or 32

@@ -133,6 +133,11 @@ extern "C" xod_status xod_set_option(const char *name, int64_t value) {
     options().outer_nmat = (int)value;
     return XOD_OK;
   }
+  if (std::strcmp(name, "update32_min") == 0) {
+    XOD_CHECK(value >= 0 && value <= 1000000, "xod_set_option: update32_min must be in 0..1000000");
+    options().update32_min = (int)value;
+    return XOD_OK;
+  }
   if (std::strcmp(name, "update32") == 0) {
     XOD_CHECK(value == 0 || value == 1, "xod_set_option: update32 must be 0 or 1");
     options().update32 = (int)value;
@@ -165,6 +170,7 @@ extern "C" xod_status xod_get_option(const char *name, int64_t *value) {
       {"gemm", o.gemm_mfma},           {"gemm_large", o.gemm_large},
       {"gemm_k", o.gemm_k},            {"outer", o.outer},
       {"outer_nmat", o.outer_nmat},    {"update32", o.update32},
+      {"update32_min", o.update32_min},
       {"graph", o.graph},              {"profile", o.profile},
       {"profile_every", o.profile_every},
       {"refine_tol_exp", (int64_t)std::lround(-std::log10(o.refine_tol))},

@@ -326,7 +326,8 @@ template <class T>
 xod_status CrPlan<T>::replay(hipGraphExec_t *g, bool factor, xod_column *c) {
   const long long key = (((long long)options().outer_nmat * 256 + options().outer) * 64 +
                          options().gemm_k) * 8 +
-                        options().gemm_large * 4 + options().gemm_mfma * 2 + options().update32;
+                        options().gemm_large * 4 + options().gemm_mfma * 2 + options().update32 +
+                        (long long)options().update32_min * (1LL << 40);
   if (graph_gemm != key) {
     if (gfactor) XOD_HIP(hipGraphExecDestroy(gfactor));
     if (gsolve) XOD_HIP(hipGraphExecDestroy(gsolve));

@@ -515,7 +515,7 @@ void launch_update(const MA &ma, int nmat, int ld, int k, int p, hipStream_t s, 
   // Four-wave 32-column strips when the launch has work-groups enough to
   // fill the chip (many blocks); 16-wave 16-column strips keep more waves
   // per block in flight when only a few blocks are updated.
-  const bool many = (size_t)nmat * (ld / kNB) >= 512;
+  const bool many = (size_t)nmat * (ld / kNB) >= (size_t)options().update32_min;
   if (options().gemm_mfma && options().update32 && many && s0 % spp == 0 &&
       nstrip % spp == 0 && skip0 % spp == 0 && skip1 - skip0 <= spp)
     hipLaunchKernelGGL((k_update32<MA, T>), dim3(nstrip / spp, nmat), dim3(kUpd32Threads), 0, s,

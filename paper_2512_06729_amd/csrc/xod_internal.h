@@ -83,6 +83,7 @@ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 struct Options {
   int gemm_mfma = 1;
   int update32 = 1;       // trailing update in panel-wide strips (0: 16-wide)
+  int update32_min = 200; // ... for launches of at least this many (block, strip) pairs
   int outer = 32;         // Gauss-Jordan outer panel width (32: unblocked)
   int outer_nmat = 1;     // ... for launches of at least this many blocks
   double refine_tol = 1e-10;   // mixed refinement: converged at this correction ratio
