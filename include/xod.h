@@ -72,10 +72,11 @@ typedef enum {
   XOD_SOLVER_THOMAS = 0,  /* block Thomas: layers eliminated bottom to top,
                              N dependent block inversions                     */
   XOD_SOLVER_CR = 1       /* block cyclic reduction: odd-indexed layers of
-                             each level eliminated together, ceil(log2 N)+1
-                             dependent batched inversions plus dense block
-                             products on the matrix cores; needs about 2N
-                             further ld x ld blocks of workspace            */
+                             each level eliminated together (both ends when
+                             three remain), at most ceil(log2 N)+1 dependent
+                             batched inversions (8 for N = 150) plus dense
+                             block products on the matrix cores; needs about
+                             2N further ld x ld blocks of workspace         */
 } xod_solver;
 
 enum { XOD_MAX_REAC = 3, XOD_MAX_PROD = 3 };

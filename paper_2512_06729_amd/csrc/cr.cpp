@@ -13,7 +13,7 @@
 //   x_k = E_k (g_k - A_k x_{k-h} - C_k x_{k+h})  for the eliminated layers.
 // The result is the solution of the same block system as block Thomas (both
 // are block Gaussian elimination, in different orders); the critical path is
-// ceil(log2 N) + 1 block inversions instead of N.
+// at most ceil(log2 N) + 1 block inversions instead of N.
 //
 // Storage besides the blocks themselves: dense A / C blocks for the even
 // layers (levels >= 1 have dense couplings), the products T1 = A_k E_{k-h}
