@@ -287,6 +287,9 @@ xod_status xod_last_error(char *buf, size_t len);
  *            update only its own columns, then one rank-width update covers
  *            the rest of the block (fewer passes over the block, more
  *            launches); 32 = every panel updates the whole block.
+ *   "panel_sync": barriers per Gauss-Jordan pivot column, 2 (default: the
+ *            wave keys, then the winning row alone) or 1 (every wave's best
+ *            row published before one barrier); same pivots, same bits.
  *   "outer_nmat": the outer panel width applies to launches of at least
  *            this many blocks (default 1); smaller launches use 32.
  *   "graph": 1 = the cyclic-reduction factor and solve launch sequences of a

@@ -112,6 +112,11 @@ extern "C" xod_status xod_set_option(const char *name, int64_t value) {
     options().gemm_large = (int)value;
     return XOD_OK;
   }
+  if (std::strcmp(name, "panel_sync") == 0) {
+    XOD_CHECK(value == 1 || value == 2, "xod_set_option: panel_sync must be 1 or 2");
+    options().panel_sync = (int)value;
+    return XOD_OK;
+  }
   if (std::strcmp(name, "gemm_k") == 0) {
     XOD_CHECK(value == 16 || value == 32, "xod_set_option: gemm_k must be 16 or 32");
     options().gemm_k = (int)value;
@@ -169,6 +174,7 @@ extern "C" xod_status xod_get_option(const char *name, int64_t *value) {
   const Entry entries[] = {
       {"gemm", o.gemm_mfma},           {"gemm_large", o.gemm_large},
       {"gemm_k", o.gemm_k},            {"outer", o.outer},
+      {"panel_sync", o.panel_sync},
       {"outer_nmat", o.outer_nmat},    {"update32", o.update32},
       {"update32_min", o.update32_min},
       {"graph", o.graph},              {"profile", o.profile},

@@ -325,7 +325,7 @@ xod_status CrPlan<T>::enqueue_solve(hipStream_t s, xod_column *c) {
 template <class T>
 xod_status CrPlan<T>::replay(hipGraphExec_t *g, bool factor, xod_column *c) {
   const long long key = (((long long)options().outer_nmat * 256 + options().outer) * 64 +
-                         options().gemm_k) * 8 +
+                         options().gemm_k * 4 + options().panel_sync) * 8 +
                         options().gemm_large * 4 + options().gemm_mfma * 2 + options().update32 +
                         (long long)options().update32_min * (1LL << 40);
   if (graph_gemm != key) {

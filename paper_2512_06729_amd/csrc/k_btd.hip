@@ -103,20 +103,18 @@ struct ListMats {
 // implicit partial pivoting.
 //
 // Thread t owns rows R*t .. R*t+R-1 as register vectors (64*ceil(ld/128)
-// threads).  Per column, one barrier:
+// threads).  Per column:
 //   - every unused row forms a key: |x| with its 10 lowest mantissa bits
 //     replaced by (1023 - row), so the largest key is the largest magnitude
 //     (to 42 mantissa bits) and, among equals, the lowest row; used rows
 //     give 0;
-//   - a DPP max gives each wave's best key, which names the wave's
-//     candidate row: its owning lane publishes the row in LDS
-//     (double-buffered by column parity) with the reciprocal of its pivot
-//     entry in the pivot column's slot, lane 0 the key;
-//   - after the barrier every lane reads the wave keys; their maximum names
-//     the pivot row, whose values (and reciprocal pivot) every thread reads.
-// The code from the elimination update of one column to the wave maximum of
-// the next has no branches, so the compiler can overlap the next column's
-// key reduction with the update (the next column is updated first).
+//   - a DPP max gives each wave's best key, lane 0 stores it in LDS;
+//   - after a barrier every lane reduces the wave keys: the maximum names
+//     the pivot row; its owning lane stores the row in LDS (16-byte stores)
+//     with the reciprocal of its pivot entry in the pivot column's slot;
+//   - after a second barrier every thread reads the row and updates its own.
+// (Option panel_sync = 1: every wave publishes its best row before a single
+// barrier instead.)  LDS buffers alternate with the column parity.
 // Pivot rows are kept unscaled while the panel runs (the elimination update
 // is linear in each row, so scaling commutes with it): the pivot row's own
 // column is set to 1 and the row is multiplied by its reciprocal pivot when
@@ -126,7 +124,8 @@ constexpr int kPanelWaves = kMaxLd / (64 * kPanelRows);     // up to 8 waves
 constexpr int kGroup = 8;                                   // columns per unrolled group
 
 // cand[w][b]: wave w's candidate row for columns of parity b (one base
-// address per wave, so every write of a row folds into the LDS offset field).
+// address per wave, so every write of a row folds into the LDS offset field);
+// with two barriers per column only cand[0] holds the pivot row.
 struct PanelShared {
   alignas(16) double cand[kPanelWaves][2][kNB];
   double key[2][kPanelWaves];
@@ -173,7 +172,33 @@ __device__ __forceinline__ int key_row(double k) {
 
 // One Gauss-Jordan column at static position U of the (rotated) rows.
 // umask[i]: all ones while row R*t+i is unused.
+// The owner lane of row rw (wave-uniform register index rw % R) writes the
+// row to slot, with the reciprocal of its column-U entry (NaN if that entry
+// is zero or not finite) in place of the entry.
 template <int R, int U>
+__device__ __forceinline__ void publish_row(const double (&row)[R][kNB], int t, int rw,
+                                            double *slot) {
+  const int iw = rw % R;
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+    if (i == iw) {
+      if (R * t + i == rw) {
+        const double pv = row[i][U];
+        const double rp = (fabs(pv) > 0.0 && isfinite(pv)) ? 1.0 / pv : __builtin_nan("");
+        double2 *dst = reinterpret_cast<double2 *>(slot);
+#pragma unroll
+        for (int q = 0; q < kNB; q += 2)   // 16-byte stores
+          dst[q / 2] = make_double2(q == U ? rp : row[i][q], q + 1 == U ? rp : row[i][q + 1]);
+      }
+    }
+}
+
+// The pivot row of column U reaches every thread one of two ways:
+//   kTwo = false: each wave's best row is published before the one barrier
+//                 (every wave writes a row, all read the winner's);
+//   kTwo = true:  the keys alone go before a first barrier, then the wave
+//                 holding the winner publishes it before a second one.
+template <int R, int U, bool kTwo>
 __device__ __forceinline__ void gj_col(double (&row)[R][kNB], double (&sig)[R],
                                        unsigned (&umask)[R], int (&mystep)[R], PanelShared &sh,
                                        int t, int jcol, int j0) {
@@ -183,22 +208,7 @@ __device__ __forceinline__ void gj_col(double (&row)[R][kNB], double (&sig)[R],
 #pragma unroll
   for (int i = 0; i < R; ++i) key = fmax(key, pivot_key(row[i][U], R * t + i, umask[i]));
   const double m = wave_max(key);
-  if (m > 0.0) {                       // this wave has an unused row: publish its best
-    const int rw = key_row(m);
-    const int iw = rw % R;             // wave-uniform register index, owner lane below
-#pragma unroll
-    for (int i = 0; i < R; ++i)
-      if (i == iw) {
-        if (R * t + i == rw) {
-          const double pv = row[i][U];
-          const double rp = (fabs(pv) > 0.0 && isfinite(pv)) ? 1.0 / pv : __builtin_nan("");
-          double2 *dst = reinterpret_cast<double2 *>(sh.cand[wid][buf]);
-#pragma unroll
-          for (int q = 0; q < kNB; q += 2)   // 16-byte stores
-            dst[q / 2] = make_double2(q == U ? rp : row[i][q], q + 1 == U ? rp : row[i][q + 1]);
-        }
-      }
-  }
+  if (!kTwo && m > 0.0) publish_row<R, U>(row, t, key_row(m), sh.cand[wid][buf]);   // wave's best
   if (lane == 0) sh.key[buf][wid] = m;
   __syncthreads();
   double K = sh.key[buf][0];
@@ -209,7 +219,11 @@ __device__ __forceinline__ void gj_col(double (&row)[R][kNB], double (&sig)[R],
     return;
   }
   const int r = key_row(K);
-  const double2 *prow = reinterpret_cast<const double2 *>(sh.cand[r / (64 * R)][buf]);
+  if (kTwo) {
+    if (r / (64 * R) == wid) publish_row<R, U>(row, t, r, sh.cand[0][buf]);
+    __syncthreads();
+  }
+  const double2 *prow = reinterpret_cast<const double2 *>(sh.cand[kTwo ? 0 : r / (64 * R)][buf]);
   double pr[kNB];
 #pragma unroll
   for (int q = 0; q < kNB; q += 2) {     // 16-byte loads
@@ -246,15 +260,16 @@ __device__ __forceinline__ void gj_col(double (&row)[R][kNB], double (&sig)[R],
   }
 }
 
-template <int R, int U>
+template <int R, int U, bool kTwo>
 __device__ __forceinline__ void gj_group(double (&row)[R][kNB], double (&sig)[R],
                                          unsigned (&umask)[R], int (&mystep)[R],
                                          PanelShared &sh, int t, int jbase, int j0) {
-  gj_col<R, U>(row, sig, umask, mystep, sh, t, jbase + U, j0);
-  if constexpr (U + 1 < kGroup) gj_group<R, U + 1>(row, sig, umask, mystep, sh, t, jbase, j0);
+  gj_col<R, U, kTwo>(row, sig, umask, mystep, sh, t, jbase + U, j0);
+  if constexpr (U + 1 < kGroup)
+    gj_group<R, U + 1, kTwo>(row, sig, umask, mystep, sh, t, jbase, j0);
 }
 
-template <class MA, class T, int R>
+template <class MA, class T, int R, bool kTwo>
 __global__ void __launch_bounds__(64 * kPanelWaves) k_panel(MA ma, int k, int p, int ld) {
   MatRef<T> mat;
   if (!ma(blockIdx.x, k, mat)) return;
@@ -292,7 +307,7 @@ __global__ void __launch_bounds__(64 * kPanelWaves) k_panel(MA ma, int k, int p,
   // back in panel order.
 #pragma unroll 1
   for (int jb = 0; jb < kNB; jb += kGroup) {
-    gj_group<R, 0>(row, sig, umask, mystep, sh, t, jb, j0);
+    gj_group<R, 0, kTwo>(row, sig, umask, mystep, sh, t, jb, j0);
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       double tmp[kGroup];
@@ -322,8 +337,12 @@ __global__ void __launch_bounds__(64 * kPanelWaves) k_panel(MA ma, int k, int p,
 template <class MA, class T>
 void launch_panel(const MA &ma, int nmat, int ld, int k, int p, hipStream_t s) {
   const int threads = 64 * ((ld + 64 * kPanelRows - 1) / (64 * kPanelRows));
-  hipLaunchKernelGGL((k_panel<MA, T, kPanelRows>), dim3(nmat), dim3(threads), 0, s, ma, k, p,
-                     ld);
+  if (options().panel_sync == 2)
+    hipLaunchKernelGGL((k_panel<MA, T, kPanelRows, true>), dim3(nmat), dim3(threads), 0, s, ma, k,
+                       p, ld);
+  else
+    hipLaunchKernelGGL((k_panel<MA, T, kPanelRows, false>), dim3(nmat), dim3(threads), 0, s, ma,
+                       k, p, ld);
 }
 
 // ---------------------------------------------------------------------------

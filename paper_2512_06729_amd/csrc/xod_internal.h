@@ -89,6 +89,7 @@ struct Options {
   double refine_tol = 1e-10;   // mixed refinement: converged at this correction ratio
   int gemm_large = 1;     // 128 x 128 product tiles for large batches
   int gemm_k = 32;        // K step of the block products staged in LDS (16 or 32)
+  int panel_sync = 2;     // barriers per Gauss-Jordan column (1 or 2)
   int graph = 1;          // replay captured launch sequences (cyclic reduction)
   int profile = 0;        // record HIP events around profiled launches
   int profile_every = 1;  // profile layers k with k % profile_every == 0

@@ -256,3 +256,26 @@ def test_outer_panel_blocking_agrees(solver):
     finally:
         xod.set_option("outer", 32)
     G.assert_state_agrees(out[1], out[0], out[0] - n0, rel=1e-9)
+
+
+@pytest.mark.parametrize("solver,precision", [(1, 0), (0, 0), (1, 1)])
+def test_panel_exchange_variants_agree(solver, precision):
+    """The pivot row exchanged after one barrier (every wave publishes its
+    best row) or after two (only the winner's): the same pivots and the same
+    arithmetic, identical bits."""
+    import paper_2512_06729_amd as xod
+    net, col = synth.make_config(2 if solver == 0 else 3)
+    stream = torch.cuda.current_stream().cuda_stream
+    gnet = xod.Network(net)
+    out = []
+    default = xod.get_option("panel_sync")
+    try:
+        for sync in (1, 2):
+            xod.set_option("panel_sync", sync)
+            g = xod.Column(gnet, col, precision=precision, stream=stream, solver=solver)
+            xod.xod_step(g, 1e-5)
+            out.append(g.state())
+            g.close()
+    finally:
+        xod.set_option("panel_sync", default)
+    np.testing.assert_array_equal(out[0], out[1])
