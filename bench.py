@@ -385,14 +385,35 @@ def main():
     rl.update({"achieved": achieved, "unit": "TFLOP/s",
                "frac": achieved / rl["peak"] if achieved else None, "traffic": traffic,
                "flops_per_launch": per_launch_flops, "avg_launch_us": dk["avg_us"]})
-    gemm = kern["gemm"]
-    gemm_rl = None
-    if gemm["avg_us"]:
-        g_ach = gemm_flops * args.steps / (gemm["total_ms"] * 1e-3) / 1e12
-        gemm_rl = {"bound": "mfma", "kernel": "k_gemm", "achieved": g_ach,
-                   "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
-                   "frac": g_ach / PEAK_FP64_MFMA_TFLOPS,
-                   "flops_per_step": gemm_flops}
+    def gemm_roofline(g, kernel):
+        if not g["avg_us"]:
+            return None
+        g_ach = gemm_flops * args.steps / (g["total_ms"] * 1e-3) / 1e12
+        return {"bound": "mfma", "kernel": kernel, "achieved": g_ach,
+                "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": g_ach / PEAK_FP64_MFMA_TFLOPS, "flops_per_step": gemm_flops,
+                "launches_per_step": g["launches"] / args.steps}
+
+    lib = xod.get_option("gemm_lib")
+    names = {0: "k_gemm (hand-written FP64 MFMA, row gathers fused)",
+             1: "rocBLAS dgemm_batched (products of row-gathered operands; the gathers are "
+                "not included)"}
+    gemm_rl = gemm_roofline(kern["gemm"], names[lib])
+    gemm_alt = None
+    if args.solver == "cr":
+        # the other block-product path on the same steps, for comparison
+        xod.set_option("gemm_lib", 1 - lib)
+        xod.profile_reset()
+        xod.set_option("profile", 1)
+        el_alt = timed_steps(xod, torch, gcol, args.dt, args.steps)
+        xod.set_option("profile", 0)
+        xod.set_option("gemm_lib", lib)
+        ms, cnt = xod.profile_read("gemm")
+        gemm_alt = gemm_roofline({"total_ms": ms, "launches": cnt,
+                                  "avg_us": 1e3 * ms / cnt if cnt else None}, names[1 - lib])
+        if gemm_alt:
+            gemm_alt["ms_per_step_with_kernel_events"] = 1e3 * el_alt / args.steps
+        progress("other block-product path profiled for comparison")
 
     steps_per_s = args.steps / el
     line = {
@@ -415,6 +436,7 @@ def main():
                    "solver": "block cyclic reduction" if args.solver == "cr" else "block Thomas"},
         "roofline": dict(rl),
         "roofline_schur_gemm": gemm_rl,
+        "roofline_schur_gemm_other_path": gemm_alt,
         "kernels": kern,
         "ms_per_step_with_kernel_events": 1e3 * el_prof / args.steps,
     }

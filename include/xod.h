@@ -276,6 +276,12 @@ xod_status xod_last_error(char *buf, size_t len);
  *            strip) pairs in the launch (default 200).
  *   "gemm_large": 1 = cyclic-reduction block products of large batches use
  *            128 x 128 output tiles (default); 0 = always 64 x 64.
+ *   "gemm_lib": 0 = the cyclic-reduction block products run in the
+ *            hand-written MFMA kernel, which gathers the permuted rows as it
+ *            stages them (default); 1 = as rocBLAS batched GEMMs, after a
+ *            gather kernel copies each product's row-permuted operand into
+ *            scratch blocks.  The two sum in different orders (same to
+ *            rounding).
  *   "gemm_k": K step of the block products staged through LDS, 16 or 32
  *            (default 32); every element sums its K terms in the same order
  *            with either.

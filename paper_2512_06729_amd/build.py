@@ -55,7 +55,8 @@ def build(verbose=False):
         list(ex.map(lambda j: _run(j[0]), jobs))
     objs = [obj for _, obj in jobs]
     tmp = LIB + ".tmp"
-    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs +
+         ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocblas"])
     os.replace(tmp, LIB)
     return LIB
 

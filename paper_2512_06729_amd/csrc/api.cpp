@@ -112,6 +112,11 @@ extern "C" xod_status xod_set_option(const char *name, int64_t value) {
     options().gemm_large = (int)value;
     return XOD_OK;
   }
+  if (std::strcmp(name, "gemm_lib") == 0) {
+    XOD_CHECK(value == 0 || value == 1, "xod_set_option: gemm_lib must be 0 or 1");
+    options().gemm_lib = (int)value;
+    return XOD_OK;
+  }
   if (std::strcmp(name, "panel_sync") == 0) {
     XOD_CHECK(value == 1 || value == 2, "xod_set_option: panel_sync must be 1 or 2");
     options().panel_sync = (int)value;
@@ -174,7 +179,7 @@ extern "C" xod_status xod_get_option(const char *name, int64_t *value) {
   const Entry entries[] = {
       {"gemm", o.gemm_mfma},           {"gemm_large", o.gemm_large},
       {"gemm_k", o.gemm_k},            {"outer", o.outer},
-      {"panel_sync", o.panel_sync},
+      {"panel_sync", o.panel_sync},    {"gemm_lib", o.gemm_lib},
       {"outer_nmat", o.outer_nmat},    {"update32", o.update32},
       {"update32_min", o.update32_min},
       {"graph", o.graph},              {"profile", o.profile},

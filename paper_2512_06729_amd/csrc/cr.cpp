@@ -26,6 +26,8 @@
 #include <memory>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "cr.h"
 
 namespace xod {
@@ -50,6 +52,7 @@ xod_status CrPlan<T>::upload(U **dst, const std::vector<U> &v) {
 
 template <class T>
 CrPlan<T>::~CrPlan() {
+  if (blas) (void)rocblas_destroy_handle((rocblas_handle)blas);
   if (gfactor) (void)hipGraphExecDestroy(gfactor);
   if (gsolve) (void)hipGraphExecDestroy(gsolve);
   if (cap) (void)hipStreamDestroy(cap);
@@ -95,7 +98,7 @@ size_t cr_extra_blocks(int N) {
 
 size_t cr_footprint(const xod_network *net, int N, xod_precision prec) {
   const size_t ld = net->ld, bs = ld * ld;
-  const size_t nblk = std::max<size_t>(cr_extra_blocks(N), 1);
+  const size_t nblk = std::max<size_t>(cr_extra_blocks(N), 1) + (N > 2 ? kGatherBlocks : 0);
   const size_t per = (size_t)N * ld * sizeof(double) + 1024 * (size_t)N + 64 * 1024;
   size_t b = nblk * bs * sizeof(double) + per;                   // FP64 workspace
   if (prec == XOD_MIXED) b += nblk * bs * sizeof(float) + per;   // + FP32 workspace
@@ -285,6 +288,118 @@ xod_status CrPlan<T>::build(xod_column *c) {
   XOD_TRY(upload(&d_l0, l0));
   XOD_TRY(upload(&d_g, gops));
   XOD_TRY(upload(&d_mv, mv));
+  return build_lib(gops);
+}
+
+template <class T>
+xod_status CrPlan<T>::build_lib(const std::vector<GemmOp<T>> &gops) {
+  const int nlev = (int)levels.size();
+  pieces_g1.assign(nlev, {});
+  pieces_g2.assign(nlev, {});
+  if (gops.empty()) return XOD_OK;
+  const size_t bs = (size_t)ld * ld;
+  XOD_HIP(hipMalloc((void **)&gtemp, (size_t)kGatherBlocks * bs * sizeof(T)));
+  owned.push_back(gtemp);
+  std::vector<GatherOp<T>> gat;
+  std::vector<const T *> pa, pb;
+  std::vector<T *> pc;
+  struct Term {
+    const T *A, *B;
+    const int *bg;
+    T *C;
+    double alpha, beta;
+  };
+  // One product launch: its first terms grouped by (alpha, beta), then the
+  // second terms (accumulated onto the first, beta = 1); cut into pieces of
+  // at most kGatherBlocks gathered operands.
+  auto split = [&](int off, int cnt, std::vector<BlasPiece> &out) {
+    std::vector<Term> first, second;
+    for (int i = off; i < off + cnt; ++i) {
+      const GemmOp<T> &g = gops[i];
+      first.push_back(Term{g.A, g.B, g.bg, g.C, g.alpha, g.beta ? 1.0 : 0.0});
+      if (g.A2) second.push_back(Term{g.A2, g.B2, g.bg2, g.C, g.alpha, 1.0});
+    }
+    std::stable_sort(first.begin(), first.end(), [](const Term &a, const Term &b) {
+      return a.alpha != b.alpha ? a.alpha < b.alpha : a.beta < b.beta;
+    });
+    std::vector<Term> seq = first;
+    seq.insert(seq.end(), second.begin(), second.end());
+    BlasPiece cur{};
+    bool open = false;
+    for (const Term &t : seq) {
+      if (open && (t.alpha != cur.alpha || t.beta != cur.beta ||
+                   (t.bg && cur.gat_cnt == kGatherBlocks))) {
+        out.push_back(cur);
+        open = false;
+      }
+      if (!open) {
+        cur = BlasPiece{(int)gat.size(), 0, (int)pa.size(), 0, t.alpha, t.beta};
+        open = true;
+      }
+      const T *B = t.B;
+      if (t.bg) {
+        T *dst = gtemp + (size_t)cur.gat_cnt * bs;
+        gat.push_back(GatherOp<T>{t.B, t.bg, dst});
+        ++cur.gat_cnt;
+        B = dst;
+      }
+      pa.push_back(t.A);
+      pb.push_back(B);
+      pc.push_back(t.C);
+      ++cur.count;
+    }
+    if (open) out.push_back(cur);
+  };
+  for (int l = 1; l < nlev; ++l) {
+    split(g1_off[l], g1_cnt[l], pieces_g1[l]);
+    split(g2_off[l], g2_cnt[l], pieces_g2[l]);
+  }
+  XOD_TRY(upload(&d_gat, gat));
+  XOD_TRY(upload(&d_pa, pa));
+  XOD_TRY(upload(&d_pb, pb));
+  XOD_TRY(upload(&d_pc, pc));
+  rocblas_handle h = nullptr;
+  if (rocblas_create_handle(&h) != rocblas_status_success) {
+    set_error("rocblas_create_handle failed");
+    return XOD_EHIP;
+  }
+  blas = h;
+  return XOD_OK;
+}
+
+// C = alpha A B + beta C on row-major ld x ld blocks: in rocBLAS's
+// column-major terms C^T = alpha B^T A^T + beta C^T.
+static rocblas_status blas_gemm(rocblas_handle h, int ld, double alpha, const double *const *A,
+                                const double *const *B, double beta, double *const *C, int n) {
+  return rocblas_dgemm_batched(h, rocblas_operation_none, rocblas_operation_none, ld, ld, ld,
+                               &alpha, B, ld, A, ld, &beta, C, ld, n);
+}
+static rocblas_status blas_gemm(rocblas_handle h, int ld, double alpha, const float *const *A,
+                                const float *const *B, double beta, float *const *C, int n) {
+  const float a = (float)alpha, b = (float)beta;
+  return rocblas_sgemm_batched(h, rocblas_operation_none, rocblas_operation_none, ld, ld, ld, &a,
+                               B, ld, A, ld, &b, C, ld, n);
+}
+
+template <class T>
+xod_status CrPlan<T>::enqueue_gemm_lib(const std::vector<BlasPiece> &pcs, hipStream_t s) {
+  rocblas_handle h = (rocblas_handle)blas;
+  if (rocblas_set_stream(h, s) != rocblas_status_success) {
+    set_error("rocblas_set_stream failed");
+    return XOD_EHIP;
+  }
+  const bool prof = options().profile != 0;
+  for (const BlasPiece &p : pcs) {
+    XOD_HIP(launch_gather_rows<T>(d_gat + p.gat_off, p.gat_cnt, ld, s));
+    if (prof) prof_begin(kProfGemm, s);
+    const rocblas_status st = blas_gemm(h, ld, p.alpha, d_pa + p.ptr_off, d_pb + p.ptr_off, p.beta,
+                                        d_pc + p.ptr_off, p.count);
+    if (prof) prof_end(kProfGemm, s);
+    if (st != rocblas_status_success) {
+      set_error("rocBLAS batched GEMM failed");
+      return XOD_EHIP;
+    }
+  }
   return XOD_OK;
 }
 
@@ -297,8 +412,13 @@ xod_status CrPlan<T>::enqueue_factor(hipStream_t s) {
     if (l == 0) {
       XOD_HIP(launch_cr_level0<T>(d_l0, l0_cnt, ld, s));
     } else {
-      XOD_HIP(launch_gemm<T>(d_g + g1_off[l], g1_cnt[l], ld, s));
-      XOD_HIP(launch_gemm<T>(d_g + g2_off[l], g2_cnt[l], ld, s));
+      if (options().gemm_lib) {
+        XOD_TRY(enqueue_gemm_lib(pieces_g1[l], s));
+        XOD_TRY(enqueue_gemm_lib(pieces_g2[l], s));
+      } else {
+        XOD_HIP(launch_gemm<T>(d_g + g1_off[l], g1_cnt[l], ld, s));
+        XOD_HIP(launch_gemm<T>(d_g + g2_off[l], g2_cnt[l], ld, s));
+      }
     }
   }
   XOD_HIP(launch_invert_list<T>(d_inv + inv_off[nlev], 1, ld, s));
@@ -325,7 +445,7 @@ xod_status CrPlan<T>::enqueue_solve(hipStream_t s, xod_column *c) {
 template <class T>
 xod_status CrPlan<T>::replay(hipGraphExec_t *g, bool factor, xod_column *c) {
   const long long key = (((long long)options().outer_nmat * 256 + options().outer) * 64 +
-                         options().gemm_k * 4 + options().panel_sync) * 8 +
+                         options().gemm_k * 4 + options().panel_sync * 2 + options().gemm_lib) * 8 +
                         options().gemm_large * 4 + options().gemm_mfma * 2 + options().update32 +
                         (long long)options().update32_min * (1LL << 40);
   if (graph_gemm != key) {

@@ -26,6 +26,8 @@ std::vector<CrLevel> cr_levels(int N);
 int cr_root(int N);
 // Dense blocks the reduction needs besides the N diagonal blocks.
 size_t cr_extra_blocks(int N);
+// Scratch blocks of the library block-product path (gathered operands).
+constexpr int kGatherBlocks = 64;
 
 template <class T>
 struct CrPlan {
@@ -42,6 +44,22 @@ struct CrPlan {
   int l0_cnt = 0, root_off = 0;
   std::vector<int> inv_off, inv_cnt, g1_off, g1_cnt, g2_off, g2_cnt;
   std::vector<int> fwd_off, fwd_cnt, bwd1_off, bwd1_cnt, bwd2_off, bwd2_cnt;
+
+  // Library block products (option gemm_lib): each product launch becomes
+  // pieces, each a row gather of its products' gathered operands into the
+  // scratch blocks gtemp, then one rocBLAS batched GEMM of products sharing
+  // (alpha, beta).
+  struct BlasPiece {
+    int gat_off, gat_cnt;   // into d_gat
+    int ptr_off, count;     // into the device pointer arrays
+    double alpha, beta;
+  };
+  std::vector<std::vector<BlasPiece>> pieces_g1, pieces_g2;   // per level
+  GatherOp<T> *d_gat = nullptr;
+  const T **d_pa = nullptr, **d_pb = nullptr;
+  T **d_pc = nullptr;
+  T *gtemp = nullptr;
+  void *blas = nullptr;   // rocblas_handle
 
   // captured launch sequences (kernel nodes only), replayed on the
   // column's stream; built on first use with the options then in force
@@ -63,6 +81,8 @@ struct CrPlan {
   xod_status enqueue_factor(hipStream_t s);
   xod_status enqueue_solve(hipStream_t s, xod_column *c);
   xod_status replay(hipGraphExec_t *g, bool factor, xod_column *c);
+  xod_status build_lib(const std::vector<GemmOp<T>> &gops);
+  xod_status enqueue_gemm_lib(const std::vector<BlasPiece> &pieces, hipStream_t s);
 };
 
 }  // namespace xod

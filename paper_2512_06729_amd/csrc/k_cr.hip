@@ -162,6 +162,24 @@ hipError_t launch_gemm(const GemmOp<T> *dops, int count, int ld, hipStream_t s) 
   return hipGetLastError();
 }
 
+// Row gathers of block-product operands (for the library GEMM path).  One
+// work-group per (row, op).
+template <class T>
+__global__ void __launch_bounds__(256) k_gather_rows(const GatherOp<T> *ops, int ld) {
+  const GatherOp<T> &o = ops[blockIdx.y];
+  const int r = blockIdx.x;
+  const auto src = gmem(o.src) + (size_t)in_block(gmem(o.idx)[r], ld) * ld;
+  const auto dst = gmem(o.dst) + (size_t)r * ld;
+  for (int j = threadIdx.x; j < ld; j += blockDim.x) dst[j] = src[j];
+}
+
+template <class T>
+hipError_t launch_gather_rows(const GatherOp<T> *dops, int count, int ld, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_gather_rows<T>), dim3(ld, count), dim3(256), 0, s, dops, ld);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Level-0 Schur terms.  One work-group per (row r, kept layer).
 template <class T>
@@ -307,6 +325,8 @@ hipError_t launch_cr_reset(int *rstep, size_t n, int *flag, hipStream_t s) {
 }
 
 template hipError_t launch_gemm<double>(const GemmOp<double> *, int, int, hipStream_t);
+template hipError_t launch_gather_rows<double>(const GatherOp<double> *, int, int, hipStream_t);
+template hipError_t launch_gather_rows<float>(const GatherOp<float> *, int, int, hipStream_t);
 template hipError_t launch_gemm<float>(const GemmOp<float> *, int, int, hipStream_t);
 template hipError_t launch_cr_level0<double>(const CrLevel0Op<double> *, int, int, hipStream_t);
 template hipError_t launch_cr_level0<float>(const CrLevel0Op<float> *, int, int, hipStream_t);

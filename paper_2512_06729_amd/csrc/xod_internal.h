@@ -90,6 +90,7 @@ struct Options {
   int gemm_large = 1;     // 128 x 128 product tiles for large batches
   int gemm_k = 32;        // K step of the block products staged in LDS (16 or 32)
   int panel_sync = 2;     // barriers per Gauss-Jordan column (1 or 2)
+  int gemm_lib = 0;       // cyclic-reduction block products: 1 = rocBLAS batched GEMM
   int graph = 1;          // replay captured launch sequences (cyclic reduction)
   int profile = 0;        // record HIP events around profiled launches
   int profile_every = 1;  // profile layers k with k % profile_every == 0
@@ -168,6 +169,15 @@ struct GemmOp {
 };
 template <class T>
 hipError_t launch_gemm(const GemmOp<T> *dops, int count, int ld, hipStream_t s);
+// dst[r][:] = src[idx[r]][:] for the ld rows of one ld x ld block per op.
+template <class T>
+struct GatherOp {
+  const T *src;
+  const int *idx;
+  T *dst;
+};
+template <class T>
+hipError_t launch_gather_rows(const GatherOp<T> *dops, int count, int ld, hipStream_t s);
 
 // Batched matrix-vector terms on padded vectors of length ld:
 //   y[j] = (b ? b[j] : 0) + sum_t sgn_t * (s_t ? s_t[j] : 1) * v_t[j]
