@@ -153,3 +153,39 @@ def poisson_arrivals(n, rate, seed=5_000_000):
     """Arrival times (s) of n requests at a Poisson rate (per second)."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
+def make_spectrum(net, L=10000, seed=7000):
+    """Wavelength grid, top-of-atmosphere flux and cross sections for the
+    spectral photolysis rates of net's photolysis reactions (Section 2.3.3:
+    10,000 bins of about 1 A from 1 to 10,000 A).  Returns a dict:
+      lam, dlam [L] (A); J0 [L] photons cm^-2 s^-1 A^-1 (a smooth stellar-like
+      shape falling into the far UV); photo [P] reaction indices; sig_ph [P, L]
+      cm^2, one Gaussian band per reaction (centre 900-3000 A, width 30-300 A,
+      peak 1e-19 to 1e-17 cm^2) cut off beyond 4 widths; absorbers [A] the
+      distinct photolysed species; sig_ext [A, L] cm^2, the sum of their
+      reactions' bands plus a Rayleigh-like 1e-27 (5000/lam)^4 term.
+    Inputs only: no rate, flux attenuation or optical depth is evaluated."""
+    rng = np.random.default_rng(seed)
+    lam = np.linspace(1.0, 10000.0, L) if L > 1 else np.array([2000.0])
+    dlam = np.full(L, (lam[-1] - lam[0]) / max(L - 1, 1) if L > 1 else 1.0)
+    x = lam / 5000.0
+    J0 = 1e13 * x ** 3 / np.expm1(np.minimum(2.5 / x, 50.0))
+    photo = np.nonzero(np.asarray(net.rtype) == 2)[0]
+    P = len(photo)
+    sig_ph = np.zeros((P, L))
+    centre = rng.uniform(900.0, 3000.0, P)
+    width = rng.uniform(30.0, 300.0, P)
+    peak = 10.0 ** rng.uniform(-19.0, -17.0, P)
+    for p in range(P):
+        u = (lam - centre[p]) / width[p]
+        band = peak[p] * np.exp(-0.5 * u * u)
+        band[np.abs(u) > 4.0] = 0.0
+        sig_ph[p] = band
+    reac = np.asarray(net.reac)[photo, 0] if P else np.zeros(0, int)
+    absorbers = np.unique(reac).astype(np.int32)
+    sig_ext = np.zeros((len(absorbers), L))
+    for a, sp in enumerate(absorbers):
+        sig_ext[a] = sig_ph[reac == sp].sum(axis=0) + 1e-27 * (5000.0 / lam) ** 4
+    return dict(lam=lam, dlam=dlam, J0=J0, photo=photo.astype(np.int32), sig_ph=sig_ph,
+                absorbers=absorbers, sig_ext=sig_ext)
