@@ -267,6 +267,31 @@ xod_status xod_integrate_to_steady_state(xod_column *col,
 /* Copy of the last error message of this thread (always NUL-terminated). */
 xod_status xod_last_error(char *buf, size_t len);
 
+/* Spectral photolysis rate coefficients (Section 2.3.3: the actinic flux
+ * J = J0 exp(-tau/mu) with no diffuse part, the optical depth as the sum of
+ * the absorbers' extinction cross sections times their columns, and the rate
+ * integral over wavelength bins), FP64:
+ *   Ncol[k][a] = n[k][absorbers[a]] dz[k]/2 + sum_{j>k} n[j][absorbers[a]] dz[j]
+ *   tau[k][b]  = sum_a Ncol[k][a] sig_ext[a*L + b]
+ *   kph[k*P+p] = t_f sum_b J0[b] exp(-tau[k][b]/mu) sig_ph[p*L + b] dlam[b]
+ * N layers (0 at the bottom), S species, A absorbers (A = 0: no
+ * attenuation), L wavelength bins, P photolysis reactions.  n [N*S] and dz
+ * [N] as for the column; absorbers [A] species indices in 0..S-1;
+ * sig_ext [A*L], J0 [L], dlam [L], sig_ph [P*L], kph [N*P] out; all DEVICE
+ * pointers owned by the caller, row-major.  work: device scratch of at
+ * least xod_photolysis_workspace(N, A, L, P) bytes.  Enqueued on `stream`
+ * (a hipStream_t, NULL for the default stream), asynchronous.  XOD_EINVAL
+ * for sizes out of range (N, S, L > 0; A, P >= 0), mu <= 0, a null pointer
+ * the sizes need, or a short workspace; absorber indices are not checked
+ * against S on the device. */
+size_t xod_photolysis_workspace(int32_t N, int32_t A, int32_t L, int32_t P);
+xod_status xod_photolysis_spectral(int32_t N, int32_t S, int32_t A, int32_t L, int32_t P,
+                                   const double *n, const double *dz,
+                                   const int32_t *absorbers, const double *sig_ext,
+                                   const double *J0, const double *dlam, const double *sig_ph,
+                                   double t_f, double mu, void *work, size_t work_bytes,
+                                   double *kph, void *stream);
+
 /* Kernel options (process-wide; for tests and tuning).
  *   "gemm": 0 = VALU FMA Schur update, 1 = MFMA Schur update (default).
  *   "update32": 1 = MFMA trailing update in 32-column strips by four-wave
@@ -314,7 +339,7 @@ xod_status xod_get_option(const char *name, int64_t *value);
 
 /* Sum of the recorded launch durations (ms) and the launch count of one
  * kernel kind: "panel", "update", "prologue", "solve", "jacobian", "rates",
- * "rhs".  Waits for the recorded events.  xod_profile_reset() drops them. */
+ * "rhs", "gemm", "photolysis" (the spectral-photolysis product).  Waits for the recorded events.  xod_profile_reset() drops them. */
 xod_status xod_profile_read(const char *kernel, double *total_ms, int64_t *launches);
 xod_status xod_profile_reset(void);
 

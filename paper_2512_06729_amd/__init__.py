@@ -120,6 +120,11 @@ _f = {
                                           ctypes.POINTER(SSOpts), ctypes.POINTER(SSResult)),
     "xod_last_error": _sig("xod_last_error", ctypes.c_char_p, ctypes.c_size_t),
     "xod_set_option": _sig("xod_set_option", ctypes.c_char_p, ctypes.c_int64),
+    "xod_photolysis_spectral": _sig("xod_photolysis_spectral", ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, c_void_p,
+                                    c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                    c_double, c_double, c_void_p, ctypes.c_size_t, c_void_p,
+                                    c_void_p),
     "xod_get_option": _sig("xod_get_option", ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)),
     "xod_batch_create": _sig("xod_batch_create", ctypes.POINTER(c_void_p), c_int32,
                              ctypes.POINTER(c_void_p)),
@@ -175,6 +180,31 @@ def _check(status):
 
 def set_option(name, value):
     _check(_f["xod_set_option"](name.encode(), int(value)))
+
+
+_lib.xod_photolysis_workspace.restype = ctypes.c_size_t
+_lib.xod_photolysis_workspace.argtypes = [ctypes.c_int32] * 4
+
+
+def photolysis_workspace(N, A, L, P):
+    """Bytes of device scratch xod_photolysis_spectral needs."""
+    return int(_lib.xod_photolysis_workspace(int(N), int(A), int(L), int(P)))
+
+
+def photolysis_spectral(n, dz, absorbers, sig_ext, J0, dlam, sig_ph, kph, work, t_f=1.0,
+                        mu=1.0, stream=None):
+    """Spectral photolysis rate coefficients into kph [N, P] (device tensors;
+    n [N, S], dz [N], absorbers [A] int32, sig_ext [A, L], J0 [L], dlam [L],
+    sig_ph [P, L], work a device byte buffer of photolysis_workspace() bytes)."""
+    N, S = n.shape
+    A = absorbers.shape[0]
+    L = J0.shape[0]
+    P = sig_ph.shape[0]
+    _check(_f["xod_photolysis_spectral"](
+        N, S, A, L, P, _dev(n), _dev(dz), _dev(absorbers) if A else None,
+        _dev(sig_ext) if A else None, _dev(J0), _dev(dlam), _dev(sig_ph) if P else None,
+        float(t_f), float(mu), _dev(work), work.numel() * work.element_size(),
+        _dev(kph) if P else None, stream))
 
 
 def get_option(name):

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxod.so")
 ARCH = os.environ.get("XOD_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "k_chem.hip", "k_btd.hip", "k_mixed.hip", "k_step.hip", "k_cr.hip",
+SOURCES = ["api.cpp", "k_chem.hip", "k_btd.hip", "k_mixed.hip", "k_step.hip", "k_cr.hip", "k_photo.hip",
            "cr.cpp", "batch.cpp", "prof.cpp", "serve.cpp"]
 
 HIP_FLAGS = [

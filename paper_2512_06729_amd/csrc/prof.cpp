@@ -36,7 +36,7 @@ hipEvent_t get_event(Prof &p) {
   return e;
 }
 const char *kNames[kProfNum] = {"panel", "update", "prologue", "solve", "jacobian", "rates",
-                                "rhs", "gemm"};
+                                "rhs", "gemm", "photolysis"};
 
 }  // namespace
 

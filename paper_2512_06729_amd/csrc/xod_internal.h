@@ -99,7 +99,7 @@ Options &options();
 
 // Event-based launch timing (enabled with the "profile" option).  Kinds:
 enum ProfKind { kProfPanel = 0, kProfUpdate, kProfPrologue, kProfSolve, kProfJac,
-                kProfRates, kProfRhs, kProfGemm, kProfNum };
+                kProfRates, kProfRhs, kProfGemm, kProfPhoto, kProfNum };
 // Record an event pair around the next launch of `kind` on stream s.
 void prof_begin(int kind, hipStream_t s);
 void prof_end(int kind, hipStream_t s);

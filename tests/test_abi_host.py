@@ -60,3 +60,25 @@ def test_null_arguments_are_einval():
     buf = ctypes.create_string_buffer(8)
     assert xod._f["xod_last_error"](buf, 8) == xod.XOD_OK
     assert len(buf.value) <= 7
+
+
+def test_photolysis_entry_validates_before_any_launch():
+    """Size, mu and workspace checks of xod_photolysis_spectral need no GPU."""
+    import ctypes
+    import paper_2512_06729_amd as xod
+    f = xod._f["xod_photolysis_spectral"]
+    fake = ctypes.c_void_p(16)
+    assert xod.photolysis_workspace(0, 1, 1, 1) == 0
+    assert xod.photolysis_workspace(150, 463, 10000, 772) > 8 * 150 * 10000
+    args = dict(N=2, S=2, A=1, L=3, P=1)
+    def call(N=2, S=2, A=1, L=3, P=1, mu=1.0, work=fake, nbytes=1 << 30):
+        return f(N, S, A, L, P, fake, fake, fake, fake, fake, fake, fake, 1.0, mu, work, nbytes,
+                 fake, None)
+    assert call(N=0) == xod.XOD_EINVAL
+    assert call(L=0) == xod.XOD_EINVAL
+    assert call(A=-1) == xod.XOD_EINVAL
+    assert call(mu=0.0) == xod.XOD_EINVAL
+    assert call(work=None) == xod.XOD_EINVAL
+    assert call(nbytes=8) == xod.XOD_EINVAL
+    assert "workspace" in xod.last_error()
+    del args
