@@ -183,6 +183,50 @@ def bench_batch(xod, torch, args, precision):
     return out
 
 
+def bench_photolysis(xod, torch, net, col, dz, calls=20):
+    """Spectral photolysis rates of the 594-species network's 772 photolysis
+    reactions on the 150-layer column: 10,000 wavelength bins, 463
+    absorbers (Section 2.3.3).  Inputs resident on the device; the rate
+    product is the MFMA-bound part (2 N L P flop)."""
+    import numpy as np
+    import synth
+    sp = synth.make_spectrum(net)
+    dev = torch.device("cuda:0")
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev)   # noqa: E731
+    n, dzt = d(col.n0), d(dz)
+    ab, se, J0, dl, sph = (d(sp["absorbers"]), d(sp["sig_ext"]), d(sp["J0"]), d(sp["dlam"]),
+                           d(sp["sig_ph"]))
+    N, L, P, A = col.N, len(sp["J0"]), sp["sig_ph"].shape[0], len(sp["absorbers"])
+    kph = torch.empty((N, P), dtype=torch.float64, device=dev)
+    work = torch.empty(xod.photolysis_workspace(N, A, L, P), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    call = lambda: xod.photolysis_spectral(n, dzt, ab, se, J0, dl, sph, kph, work, 0.5, 1.0,   # noqa: E731
+                                           stream)
+    call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        call()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / calls
+    xod.profile_reset()
+    xod.set_option("profile", 1)
+    for _ in range(calls):
+        call()
+    torch.cuda.synchronize()
+    xod.set_option("profile", 0)
+    ms, cnt = xod.profile_read("photolysis")
+    flops = 2.0 * N * L * P
+    g_us = 1e3 * ms / cnt if cnt else None
+    ach = flops / (g_us * 1e-6) / 1e12 if g_us else None
+    return {"us_per_call": 1e6 * el, "N": N, "L": L, "P": P, "A": A,
+            "tau_product_flop": 2.0 * N * A * L, "rate_product_flop": flops,
+            "roofline_rate_product": {"bound": "mfma", "kernel": "k_ph_gemm (FP64 MFMA, split K)",
+                                      "avg_launch_us": g_us, "achieved": ach,
+                                      "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                                      "frac": ach / PEAK_FP64_MFMA_TFLOPS if ach else None}}
+
+
 def bench_serve(xod, torch, args, precision, gnet, net):
     """Poisson arrivals of steady-state solves (594 species x 150 layers,
     per-request T offset / Kzz scale / initial state, t_end 1e12 s,
@@ -300,6 +344,7 @@ def main():
     ap.add_argument("--batch-cols", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--skip-serve", action="store_true")
+    ap.add_argument("--skip-photolysis", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=4)
     ap.add_argument("--serve-rate", type=float, default=5.0)
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -335,6 +380,7 @@ def main():
     solver = xod.XOD_SOLVER_CR if args.solver == "cr" else xod.XOD_SOLVER_THOMAS
     gcol = xod.Column(gnet, col, precision=xod.XOD_FP64, stream=stream, solver=solver)
 
+    col_dz = gcol.grid()["dz"]            # layer thicknesses of the library's column grid
     progress("config-3 column on the device")
     for _ in range(args.warmup):
         xod.xod_step(gcol, args.dt)
@@ -470,6 +516,9 @@ def main():
         if smx:
             smx["max_rel_diff_vs_fp64_steady_state"] = diffs
         line["serve"] = {"fp64": s64, "mixed": smx or None}
+    if not args.skip_photolysis:
+        line["photolysis_spectral"] = bench_photolysis(xod, torch, net, col, col_dz)
+        progress("spectral photolysis: %.1f us per call" % line["photolysis_spectral"]["us_per_call"])
     if not args.skip_batch:
         b64 = bench_batch(xod, torch, args, xod.XOD_FP64)
         progress(f"batch fp64: {b64['value']:.1f} column-steps/s")
