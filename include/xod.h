@@ -285,6 +285,21 @@ xod_status xod_last_error(char *buf, size_t len);
  * the sizes need, or a short workspace; absorber indices are not checked
  * against S on the device. */
 size_t xod_photolysis_workspace(int32_t N, int32_t A, int32_t L, int32_t P);
+/* Use spectral photolysis rates in this column's steps: every xod_step (and
+ * xod_rates) first computes kph from the column's state at that moment, as
+ * xod_photolysis_spectral does with the column's layer thicknesses, and the
+ * photolysis reactions take k_f = kph[k][p] (p = the reaction's index among
+ * the network's photolysis reactions, in reaction order) instead of
+ * J0 exp(-tau_k).  Within a step the rates stay those of its starting state
+ * (lagged: the Jacobian holds them fixed).  The tables are DEVICE pointers
+ * the caller keeps valid while the setting is in force: absorbers [A],
+ * sig_ext [A*L], J0 [L], dlam [L], sig_ph [nph*L] for the network's nph
+ * photolysis reactions.  L = 0 returns to the gray law.  Batches reject
+ * columns with a spectrum (XOD_EINVAL at xod_batch_create). */
+xod_status xod_column_set_photolysis_spectrum(xod_column *col, int32_t A, int32_t L,
+                                              const int32_t *absorbers, const double *sig_ext,
+                                              const double *J0, const double *dlam,
+                                              const double *sig_ph, double t_f, double mu);
 xod_status xod_photolysis_spectral(int32_t N, int32_t S, int32_t A, int32_t L, int32_t P,
                                    const double *n, const double *dz,
                                    const int32_t *absorbers, const double *sig_ext,

@@ -10,6 +10,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import grid as grid_mod
+from . import photolysis
 from . import rates as rates_mod
 from .rhs import rhs
 from .jacobian import step_matrix
@@ -20,11 +21,25 @@ class Problem:
     """Network + column with the grid and rate coefficients precomputed (the
     coefficients depend on T, n_gas and tau only, which are fixed)."""
 
-    def __init__(self, net, col):
+    def __init__(self, net, col, spectrum=None):
         self.net = net
         self.col = col
         self.grid = grid_mod.make_grid(col, net.mass_amu)
         self.kf, self.kr = rates_mod.rates(net, self.grid)
+        # spectral photolysis (Section 2.3.3): dict with absorbers, sig_ext,
+        # J0, dlam, sig_ph (rows in the order of the photolysis reactions),
+        # t_f, mu; None keeps the gray law
+        self.spectrum = spectrum
+
+    def lag_photolysis(self, n):
+        """The photolysis coefficients of state n (spectral rates), held for
+        the step that starts from n."""
+        sp = self.spectrum
+        photo = np.nonzero(np.asarray(self.net.rtype) == rates_mod.RT_PHOTO)[0]
+        self.kf = self.kf.copy()
+        self.kf[:, photo] = photolysis.spectral_rates(n, self.grid.dz, sp["absorbers"],
+                                                      sp["sig_ext"], sp["J0"], sp["dlam"],
+                                                      sp["sig_ph"], sp["t_f"], sp["mu"])
 
     def rhs(self, n):
         return rhs(self.net, self.grid, self.kf, self.kr, n)
@@ -37,6 +52,8 @@ def be_step(prob, n, dt, solver="btd", newton_iters=1):
     """One linearly implicit BE step; newton_iters > 1 adds frozen-Jacobian
     corrections of the nonlinear BE equation n1 - n - dt F(n1) = 0.
     Returns (n_new, delta)."""
+    if getattr(prob, "spectrum", None) is not None:
+        prob.lag_photolysis(n)
     B, a, c = prob.step_matrix(n, dt)
     solve = btd if solver == "btd" else dense_solve
     delta = solve(B, a, c, prob.rhs(n))

@@ -120,6 +120,10 @@ _f = {
                                           ctypes.POINTER(SSOpts), ctypes.POINTER(SSResult)),
     "xod_last_error": _sig("xod_last_error", ctypes.c_char_p, ctypes.c_size_t),
     "xod_set_option": _sig("xod_set_option", ctypes.c_char_p, ctypes.c_int64),
+    "xod_column_set_photolysis_spectrum": _sig("xod_column_set_photolysis_spectrum", c_void_p,
+                                               ctypes.c_int32, ctypes.c_int32, c_void_p,
+                                               c_void_p, c_void_p, c_void_p, c_void_p, c_double,
+                                               c_double),
     "xod_photolysis_spectral": _sig("xod_photolysis_spectral", ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, c_void_p,
                                     c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
@@ -318,6 +322,23 @@ class Column:
         _check(_f["xod_column_grid"](self.handle, _ptr(ng, c_double), _ptr(tau, c_double),
                                      _ptr(dz, c_double), ctypes.byref(mix)))
         return dict(ngas=ng, tau=tau, dz=dz, mix_time=mix.value)
+
+    def set_photolysis_spectrum(self, absorbers=None, sig_ext=None, J0=None, dlam=None,
+                                sig_ph=None, t_f=1.0, mu=1.0):
+        """Spectral photolysis in this column's steps (device tensors, kept
+        referenced here while in force); no J0: back to the gray law."""
+        if J0 is None:
+            _check(_f["xod_column_set_photolysis_spectrum"](self.handle, 0, 0, None, None, None,
+                                                             None, None, 1.0, 1.0))
+            self._spectrum = None
+            return
+        A = 0 if absorbers is None else absorbers.shape[0]
+        L = J0.shape[0]
+        _check(_f["xod_column_set_photolysis_spectrum"](
+            self.handle, A, L, _dev(absorbers) if A else None, _dev(sig_ext) if A else None,
+            _dev(J0), _dev(dlam), _dev(sig_ph) if sig_ph is not None and sig_ph.numel() else None,
+            float(t_f), float(mu)))
+        self._spectrum = (absorbers, sig_ext, J0, dlam, sig_ph)
 
     def close(self):
         if getattr(self, "handle", None):

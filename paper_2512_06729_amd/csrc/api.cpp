@@ -306,6 +306,11 @@ extern "C" xod_status xod_network_create(const xod_network_desc *d, xod_network 
   std::vector<int> jc_col(jc_ru.size());   // column of each contribution's entry
   for (size_t e = 0; e + 1 < jptr.size(); ++e)
     for (int q = jptr[e]; q < jptr[e + 1]; ++q) jc_col[q] = jcol[e];
+  std::vector<int> photo_idx(R, -1);
+  int nph = 0;
+  for (int r = 0; r < R; ++r)
+    if (d->rtype[r] == XOD_RT_PHOTO) photo_idx[r] = nph++;
+  net->nph = nph;
   net->nnz = (int)jptr.size() - 1;
   net->ncontrib = (int)jc_ru.size();
 
@@ -328,6 +333,7 @@ extern "C" xod_status xod_network_create(const xod_network_desc *d, xod_network 
   XOD_TRY(nalloc(n, &n->jc_ru, jc_ru.size(), jc_ru.data()));
   XOD_TRY(nalloc(n, &n->rsp, rsp.size(), rsp.data()));
   XOD_TRY(nalloc(n, &n->jc_nu, jc_nu.size(), jc_nu.data()));
+  XOD_TRY(nalloc(n, &n->photo_idx, photo_idx.size(), photo_idx.data()));
   *out = net.release();
   return XOD_OK;
 }
@@ -517,8 +523,56 @@ extern "C" xod_status xod_column_grid(const xod_column *col, double *ngas, doubl
 
 // ---------------------------------------------------------------------------
 // Hot-path calls on caller-owned device buffers.
+namespace xod {
+// The column's spectral photolysis rates at its current state, if set.
+static xod_status enqueue_photolysis(xod_column *c) {
+  if (c->ph_L <= 0 || c->net->nph == 0) return XOD_OK;
+  XOD_HIP(launch_photolysis(c->N, c->S, c->ph_A, c->ph_L, c->net->nph, c->n, c->dz, c->ph_abs,
+                            c->ph_ext, c->ph_J0, c->ph_dlam, c->ph_sig, c->ph_tf, c->ph_mu,
+                            c->ph_work, c->kph, c->stream));
+  return XOD_OK;
+}
+}  // namespace xod
+
+extern "C" xod_status xod_column_set_photolysis_spectrum(xod_column *col, int32_t A, int32_t L,
+                                                         const int32_t *absorbers,
+                                                         const double *sig_ext, const double *J0,
+                                                         const double *dlam,
+                                                         const double *sig_ph, double t_f,
+                                                         double mu) {
+  XOD_CHECK(col, "xod_column_set_photolysis_spectrum: null column");
+  if (L == 0) {             // back to the gray law
+    col->ph_L = 0;
+    return XOD_OK;
+  }
+  XOD_CHECK(L > 0 && A >= 0, "xod_column_set_photolysis_spectrum: need L > 0 and A >= 0");
+  XOD_CHECK(mu > 0.0, "xod_column_set_photolysis_spectrum: mu must be positive");
+  XOD_CHECK(J0 && dlam && (A == 0 || (absorbers && sig_ext)) && (col->net->nph == 0 || sig_ph),
+            "xod_column_set_photolysis_spectrum: null table");
+  const int P = col->net->nph;
+  if (!col->kph && P > 0) XOD_TRY(calloc_(col, &col->kph, (size_t)col->N * P));
+  const size_t need = photolysis_work_bytes(col->N, A, L, P);
+  if (need > col->ph_work_bytes) {
+    double *w = nullptr;
+    XOD_TRY(calloc_(col, &w, (need + sizeof(double) - 1) / sizeof(double)));
+    col->ph_work = w;
+    col->ph_work_bytes = need;
+  }
+  col->ph_A = A;
+  col->ph_L = L;
+  col->ph_abs = absorbers;
+  col->ph_ext = sig_ext;
+  col->ph_J0 = J0;
+  col->ph_dlam = dlam;
+  col->ph_sig = sig_ph;
+  col->ph_tf = t_f;
+  col->ph_mu = mu;
+  return XOD_OK;
+}
+
 extern "C" xod_status xod_rates(xod_column *col, double *kf, double *kr) {
   XOD_CHECK(col && kf && kr, "xod_rates: null argument");
+  XOD_TRY(enqueue_photolysis(col));
   ColArgs a = col->args();
   a.kf = kf;
   a.kr = kr;
@@ -677,6 +731,7 @@ xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, do
   *iters = 0;
   *fallback = 0;
   *resid = 0.0;
+  XOD_TRY(enqueue_photolysis(c));
   XOD_HIP(launch_rates(one, 1, c->N, c->R, c->stream));
   XOD_HIP(launch_rhs(one, 1, c->N, c->R, c->S, c->stream));
   const bool cr = c->solver == XOD_SOLVER_CR;

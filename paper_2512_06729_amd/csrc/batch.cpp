@@ -277,6 +277,7 @@ extern "C" xod_status xod_batch_create(xod_column *const *cols, int32_t ncols, x
     BCHECK(cols[i] != nullptr, "xod_batch_create: null column");
     BCHECK(!cols[i]->in_batch, "xod_batch_create: column already in a batch");
     BCHECK(cols[i]->prec == cols[0]->prec, "xod_batch_create: columns of one precision");
+    BCHECK(cols[i]->ph_L == 0, "xod_batch_create: spectral photolysis is not supported in batches");
     for (int j = 0; j < i; ++j) BCHECK(cols[j] != cols[i], "xod_batch_create: duplicate column");
   }
   std::unique_ptr<xod_batch> b(new xod_batch());

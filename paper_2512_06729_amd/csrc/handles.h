@@ -28,6 +28,8 @@ struct xod_network {
   double *jc_nu = nullptr;
   std::vector<double> mass_h;
   int nnz = 0, ncontrib = 0;
+  int *photo_idx = nullptr;   // [R]: index among the photolysis reactions, -1 for others
+  int nph = 0;                // number of photolysis reactions
   ~xod_network() {
     for (void *p : owned) (void)hipFree(p);
   }
@@ -42,6 +44,15 @@ struct xod_column {
   double *P = nullptr, *T = nullptr, *K = nullptr, *D = nullptr, *alpha = nullptr;
   double *ngas = nullptr, *tau = nullptr, *lnpref = nullptr, *g = nullptr, *trl = nullptr,
          *trd = nullptr, *tru = nullptr, *dz = nullptr, *dzh = nullptr, *mix = nullptr;
+  // Spectral photolysis (xod_column_set_photolysis_spectrum): the caller's
+  // device tables, the library's rates [N*nph] and scratch.  ph_L = 0: gray.
+  int ph_A = 0, ph_L = 0;
+  const int *ph_abs = nullptr;
+  const double *ph_ext = nullptr, *ph_J0 = nullptr, *ph_dlam = nullptr, *ph_sig = nullptr;
+  double ph_tf = 1.0, ph_mu = 1.0;
+  double *kph = nullptr;
+  void *ph_work = nullptr;
+  size_t ph_work_bytes = 0;
   double mix_time = 0.0;
   double *dwd = nullptr;   // [N*R*6] reaction-rate derivatives of the last Jacobian
   double *n = nullptr, *ntmp = nullptr, *kf = nullptr, *kr = nullptr, *w = nullptr,
@@ -85,6 +96,9 @@ struct xod_column {
     a_.inc_ptr = net->inc_ptr;
     a_.inc_r = net->inc_r;
     a_.inc_nu = net->inc_nu;
+    a_.photo_idx = net->photo_idx;
+    a_.nph = net->nph;
+    a_.kph = ph_L > 0 ? kph : nullptr;
     a_.jrow = net->jrow;
     a_.jc_col = net->jc_col;
     a_.jptr = net->jptr;

@@ -139,6 +139,8 @@ __global__ void __launch_bounds__(256) k_rates(Acc acc) {
     const double ki = exp(p[3] + p[4] * lnTb - p[5] / T);
     const double k0M = k0 * c.ngas[k];
     kf = k0M / (1.0 + k0M / ki);
+  } else if (c.kph) {             // spectral rates of this step's starting state
+    kf = c.kph[(size_t)k * c.nph + c.photo_idx[r]];
   } else {
     kf = exp(p[0] - c.tau[k]);
   }

@@ -166,31 +166,14 @@ size_t ph_work_doubles(int N, int A, int L, int P) {
 
 }  // namespace
 
-}  // namespace xod
-
-using namespace xod;
-
-extern "C" size_t xod_photolysis_workspace(int32_t N, int32_t A, int32_t L, int32_t P) {
-  if (N <= 0 || A < 0 || L <= 0 || P < 0) return 0;
+size_t photolysis_work_bytes(int N, int A, int L, int P) {
   return ph_work_doubles(N, A, L, P) * sizeof(double);
 }
 
-extern "C" xod_status xod_photolysis_spectral(int32_t N, int32_t S, int32_t A, int32_t L,
-                                              int32_t P, const double *n, const double *dz,
-                                              const int32_t *absorbers, const double *sig_ext,
-                                              const double *J0, const double *dlam,
-                                              const double *sig_ph, double t_f, double mu,
-                                              void *work, size_t work_bytes, double *kph,
-                                              void *stream) {
-  PH_CHECK(N > 0 && S > 0 && A >= 0 && L > 0 && P >= 0,
-            "xod_photolysis_spectral: need N, S, L > 0 and A, P >= 0");
-  PH_CHECK(mu > 0.0, "xod_photolysis_spectral: mu must be positive");
-  PH_CHECK(n && dz && J0 && dlam && work, "xod_photolysis_spectral: null pointer");
-  PH_CHECK(A == 0 || (absorbers && sig_ext), "xod_photolysis_spectral: null absorber table");
-  PH_CHECK(P == 0 || (sig_ph && kph), "xod_photolysis_spectral: null cross-section table");
-  PH_CHECK(work_bytes >= ph_work_doubles(N, A, L, P) * sizeof(double),
-            "xod_photolysis_spectral: workspace smaller than xod_photolysis_workspace()");
-  hipStream_t s = (hipStream_t)stream;
+hipError_t launch_photolysis(int N, int S, int A, int L, int P, const double *n, const double *dz,
+                             const int *absorbers, const double *sig_ext, const double *J0,
+                             const double *dlam, const double *sig_ph, double t_f, double mu,
+                             void *work, double *kph, hipStream_t s) {
   double *ncol = (double *)work;
   double *E = ncol + (size_t)N * A;
   double *part = E + (size_t)N * L;
@@ -214,6 +197,34 @@ extern "C" xod_status xod_photolysis_spectral(int32_t N, int32_t S, int32_t A, i
     if (options().profile) prof_end(kProfPhoto, s);
     hipLaunchKernelGGL(k_ph_sum, dim3(256), dim3(256), 0, s, part, pk, (size_t)N * P, kph);
   }
-  XOD_HIP(hipGetLastError());
+  return hipGetLastError();
+}
+
+}  // namespace xod
+
+using namespace xod;
+
+extern "C" size_t xod_photolysis_workspace(int32_t N, int32_t A, int32_t L, int32_t P) {
+  if (N <= 0 || A < 0 || L <= 0 || P < 0) return 0;
+  return photolysis_work_bytes(N, A, L, P);
+}
+
+extern "C" xod_status xod_photolysis_spectral(int32_t N, int32_t S, int32_t A, int32_t L,
+                                              int32_t P, const double *n, const double *dz,
+                                              const int32_t *absorbers, const double *sig_ext,
+                                              const double *J0, const double *dlam,
+                                              const double *sig_ph, double t_f, double mu,
+                                              void *work, size_t work_bytes, double *kph,
+                                              void *stream) {
+  PH_CHECK(N > 0 && S > 0 && A >= 0 && L > 0 && P >= 0,
+           "xod_photolysis_spectral: need N, S, L > 0 and A, P >= 0");
+  PH_CHECK(mu > 0.0, "xod_photolysis_spectral: mu must be positive");
+  PH_CHECK(n && dz && J0 && dlam && work, "xod_photolysis_spectral: null pointer");
+  PH_CHECK(A == 0 || (absorbers && sig_ext), "xod_photolysis_spectral: null absorber table");
+  PH_CHECK(P == 0 || (sig_ph && kph), "xod_photolysis_spectral: null cross-section table");
+  PH_CHECK(work_bytes >= photolysis_work_bytes(N, A, L, P),
+           "xod_photolysis_spectral: workspace smaller than xod_photolysis_workspace()");
+  XOD_HIP(launch_photolysis(N, S, A, L, P, n, dz, absorbers, sig_ext, J0, dlam, sig_ph, t_f, mu,
+                            work, kph, (hipStream_t)stream));
   return XOD_OK;
 }

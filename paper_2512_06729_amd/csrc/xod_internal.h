@@ -35,6 +35,9 @@ struct ColArgs {
   const int *jc_ru, *jc_col;        // contribution e: slot jc_ru[e] = 6 r + u, column
   const double *jc_nu;
   const int *rsp;                   // [R*6] distinct species of each reaction
+  const int *photo_idx;             // [R] index among the photolysis reactions (-1: none)
+  int nph;                          // photolysis reactions
+  const double *kph;                // [N*nph] spectral photolysis rates, or null (gray)
   // grid (device, owned by the column)
   const double *T, *ngas, *tau, *lnpref, *g, *trl, *trd, *tru;
   // operands
@@ -167,6 +170,14 @@ struct GemmOp {
   double alpha;
   int beta;
 };
+// Spectral photolysis rates kph [N*P] (see xod_photolysis_spectral); work of
+// photolysis_work_bytes(N, A, L, P) bytes.
+size_t photolysis_work_bytes(int N, int A, int L, int P);
+hipError_t launch_photolysis(int N, int S, int A, int L, int P, const double *n, const double *dz,
+                             const int *absorbers, const double *sig_ext, const double *J0,
+                             const double *dlam, const double *sig_ph, double t_f, double mu,
+                             void *work, double *kph, hipStream_t s);
+
 template <class T>
 hipError_t launch_gemm(const GemmOp<T> *dops, int count, int ld, hipStream_t s);
 // dst[r][:] = src[idx[r]][:] for the ld rows of one ld x ld block per op.

@@ -82,3 +82,49 @@ def test_rejects_bad_arguments():
         run_gpu(np.ones((2, 2)), np.ones(2), [0], np.ones((1, 3)), np.ones(3), np.ones(3),
                 np.ones((1, 3)), t_f=1.0, mu=0.0)
     assert e.value.status == xod.XOD_EINVAL
+
+
+@pytest.mark.parametrize("solver,dt", [(0, 1e-6), (1, 1e-6), (1, 1e-3)])
+def test_step_with_lagged_spectrum_matches_oracle(solver, dt):
+    """xod_step with the spectral rates of the step's starting state (2000
+    bins, the 90-species network's 120 photolysis reactions) against the
+    oracle's step with the same lagged rates."""
+    import paper_2512_06729_amd as xod
+    from oracle import integrate
+    from tests import gpu_common as G
+    net, col = synth.make_config(2)
+    sp = synth.make_spectrum(net, L=2000)
+    spec = dict(absorbers=sp["absorbers"], sig_ext=sp["sig_ext"], J0=sp["J0"], dlam=sp["dlam"],
+                sig_ph=sp["sig_ph"], t_f=0.5, mu=0.7)
+    prob, gnet, gcol = G.make_pair(net, col)
+    gcol.set_solver(solver)
+    dev = torch.device("cuda:0")
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev)   # noqa: E731
+    gcol.set_photolysis_spectrum(d(sp["absorbers"]), d(sp["sig_ext"]), d(sp["J0"]),
+                                 d(sp["dlam"]), d(sp["sig_ph"]), t_f=0.5, mu=0.7)
+    ref_prob = integrate.Problem(net, col, spectrum=spec)
+    ref, delta = integrate.be_step(ref_prob, col.n0, dt)
+    gray, _ = integrate.be_step(prob, col.n0, dt)
+    xod.xod_step(gcol, dt)
+    got = gcol.state()
+    assert np.max(np.abs(ref - gray)) > 0          # the spectrum changes the step
+    G.assert_state_agrees(got, ref, delta, rel=1e-9)
+
+
+def test_back_to_gray_gives_the_gray_bits():
+    import paper_2512_06729_amd as xod
+    from tests import gpu_common as G
+    net, col = synth.make_config(2)
+    sp = synth.make_spectrum(net, L=500)
+    dev = torch.device("cuda:0")
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev)   # noqa: E731
+    _, gnet, a = G.make_pair(net, col)
+    b = xod.Column(gnet, col, stream=torch.cuda.current_stream().cuda_stream)
+    b.set_photolysis_spectrum(d(sp["absorbers"]), d(sp["sig_ext"]), d(sp["J0"]), d(sp["dlam"]),
+                              d(sp["sig_ph"]))
+    xod.xod_step(b, 1e-6)
+    b.set_state(col.n0)
+    b.set_photolysis_spectrum()
+    xod.xod_step(a, 1e-6)
+    xod.xod_step(b, 1e-6)
+    np.testing.assert_array_equal(a.state(), b.state())

@@ -86,3 +86,28 @@ def test_linear_in_tf_and_flux_and_cross_section():
     assert np.all(ph.spectral_rates(n, dz, [1, 3], sig_ext, J0, dl, sig, 0.5, 0.9) >= k)
     # rates grow with height (less column above)
     assert np.all(np.diff(k, axis=0) >= 0)
+
+
+def test_lagged_spectrum_in_the_step_reduces_to_gray():
+    """A one-bin spectrum that reproduces the gray law (sigma dlam = 1, the
+    total gas as the single absorber with the gray cross section) gives the
+    gray step: the lagged coupling adds nothing else."""
+    import synth
+    from oracle import integrate
+    net = synth.make_network("c2", seed=1002)
+    col = synth.make_column("c2", net, seed=301, N=6)
+    prob = integrate.Problem(net, col)
+    n0 = col.n0
+    photo = np.nonzero(np.asarray(net.rtype) == 2)[0]
+    lnJ0 = np.asarray(net.params)[photo, 0]
+    # one bin per reaction would need per-reaction fluxes: use L = 1 with
+    # J0 = 1 and sig_ph = J0_r, and the total gas column as the absorber
+    ngas = prob.grid.ngas
+    S = n0.shape[1]
+    nn = np.concatenate([n0, ngas[:, None]], axis=1)      # extra "species": the total gas
+    sp = dict(absorbers=np.array([S]), sig_ext=np.array([[col.sigma_tau]]), J0=np.array([1.0]),
+              dlam=np.array([1.0]), sig_ph=np.exp(lnJ0)[:, None], t_f=1.0, mu=1.0)
+    kph = __import__("oracle").photolysis.spectral_rates(nn, prob.grid.dz, sp["absorbers"],
+                                                         sp["sig_ext"], sp["J0"], sp["dlam"],
+                                                         sp["sig_ph"])
+    np.testing.assert_allclose(kph, prob.kf[:, photo], rtol=1e-13)
