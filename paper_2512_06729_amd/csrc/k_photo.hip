@@ -25,7 +25,7 @@ namespace xod {
 
 namespace {
 
-constexpr int kPhTile = 64, kPhK = 16, kPhThreads = 256;
+constexpr int kPhTile = 64, kPhK = 32, kPhThreads = 256;
 
 // Column densities above each layer midpoint, one thread per absorber.
 __global__ void __launch_bounds__(256) k_ph_column(const double *n, const double *dz,
@@ -45,62 +45,80 @@ __global__ void __launch_bounds__(256) k_ph_column(const double *n, const double
 // Part z of C[M][Nc] = A[M][K] B, with B stored as [K][Nc] (kBT = false) or
 // as [Nc][K] (kBT = true); part z sums k in [z*kc, min(K, (z+1)*kc)).
 // Four waves in a 2 x 2 grid, each owning a 32 x 32 sub-tile (2 x 2 MFMA
-// accumulators); K staged through LDS 16 at a time.
+// accumulators); K staged through LDS kPhK at a time, double-buffered: the
+// next step's global loads are issued before the current step's MFMAs.
 template <bool kBT>
 __global__ void __launch_bounds__(kPhThreads) k_ph_gemm(const double *A, const double *B,
                                                         double *part, int M, int Nc, int K,
                                                         int kc) {
+  constexpr int kE = kPhTile * kPhK / kPhThreads;   // staged elements per thread and operand
   const int tm0 = blockIdx.y * kPhTile, tn0 = blockIdx.x * kPhTile;
   const int z = blockIdx.z;
   const int kb = z * kc, ke = min(K, kb + kc);
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   const int wr = wid >> 1, wc = wid & 1;
-  __shared__ double As[kPhTile][kPhK + 1];
-  __shared__ double Bs[kPhK][kPhTile + 2];
+  __shared__ double As[2][kPhTile][kPhK + 1];
+  __shared__ double Bs[2][kPhK][kPhTile + 2];
   double4_t acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = (double4_t){0, 0, 0, 0};
   const auto Ag = gmem(A), Bg = gmem(B);
-  for (int k0 = kb; k0 < ke; k0 += kPhK) {
-    // stage A (64 x 16) and B (16 x 64): four elements each per thread
+  double ra[kE], rb[kE];
+  auto gload = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < kE; ++e) {
       const int idx = t + e * kPhThreads;
-      const int r = idx / kPhK, kk = idx % kPhK;
-      const int gr = tm0 + r, gk = k0 + kk;
-      As[r][kk] = (gr < M && gk < ke) ? Ag[(size_t)gr * K + gk] : 0.0;
+      const int gr = tm0 + idx / kPhK, gk = k0 + idx % kPhK;
+      ra[e] = (gr < M && gk < ke) ? Ag[(size_t)gr * K + gk] : 0.0;
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < kE; ++e) {
       const int idx = t + e * kPhThreads;
-      int kk, c;
-      if (kBT) {            // consecutive threads walk K of one column
-        c = idx / kPhK;
-        kk = idx % kPhK;
-      } else {              // consecutive threads walk the columns of one k
-        kk = idx / kPhTile;
-        c = idx % kPhTile;
-      }
+      // consecutive threads walk K of one column (kBT) or the columns of one k
+      const int c = kBT ? idx / kPhK : idx % kPhTile;
+      const int kk = kBT ? idx % kPhK : idx / kPhTile;
       const int gc = tn0 + c, gk = k0 + kk;
       double v = 0.0;
       if (gc < Nc && gk < ke) v = kBT ? Bg[(size_t)gc * K + gk] : Bg[(size_t)gk * Nc + gc];
-      Bs[kk][c] = v;
+      rb[e] = v;
     }
-    __syncthreads();
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+      const int idx = t + e * kPhThreads;
+      As[buf][idx / kPhK][idx % kPhK] = ra[e];
+      const int c = kBT ? idx / kPhK : idx % kPhTile;
+      const int kk = kBT ? idx % kPhK : idx / kPhTile;
+      Bs[buf][kk][c] = rb[e];
+    }
+  };
+  const int nsteps = ke > kb ? (ke - kb + kPhK - 1) / kPhK : 0;
+  if (nsteps > 0) {
+    gload(kb);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int st = 0; st < nsteps; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nsteps) gload(kb + (st + 1) * kPhK);
 #pragma unroll
     for (int q = 0; q < kPhK / 4; ++q) {
       double av[2], bv[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) av[i] = As[wr * 32 + i * 16 + (lane & 15)][q * 4 + (lane >> 4)];
+      for (int i = 0; i < 2; ++i)
+        av[i] = As[buf][wr * 32 + i * 16 + (lane & 15)][q * 4 + (lane >> 4)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) bv[j] = Bs[q * 4 + (lane >> 4)][wc * 32 + j * 16 + (lane & 15)];
+      for (int j = 0; j < 2; ++j)
+        bv[j] = Bs[buf][q * 4 + (lane >> 4)][wc * 32 + j * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = mfma16(av[i], bv[j], acc[i][j]);
     }
+    if (st + 1 < nsteps) sstore(buf ^ 1);
     __syncthreads();
   }
   const auto P = gmem(part) + (size_t)z * M * Nc;
