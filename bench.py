@@ -461,6 +461,21 @@ def main():
             gemm_alt["ms_per_step_with_kernel_events"] = 1e3 * el_alt / args.steps
         progress("other block-product path profiled for comparison")
 
+    # factor reuse: steps that solve with the last step's factorisation
+    frozen = None
+    if args.solver == "cr":
+        xod.xod_step(gcol, args.dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            xod.xod_step_frozen(gcol, args.dt)
+        torch.cuda.synchronize()
+        el_fr = (time.perf_counter() - t0) / args.steps
+        frozen = {"value": 1.0 / el_fr, "unit": "steps/s", "ms_per_step": 1e3 * el_fr,
+                  "what": "xod_step_frozen: rates, F, solve with the last xod_step's factors, "
+                          "update (no Jacobian, no factorisation)"}
+        progress(f"frozen-matrix steps: {1.0 / el_fr:.1f} steps/s")
+
     steps_per_s = args.steps / el
     line = {
         "metric": "implicit steps/sec at 594 sp x 150 layers (FP64)",
@@ -483,6 +498,7 @@ def main():
         "roofline": dict(rl),
         "roofline_schur_gemm": gemm_rl,
         "roofline_schur_gemm_other_path": gemm_alt,
+        "frozen_matrix_steps": frozen,
         "kernels": kern,
         "ms_per_step_with_kernel_events": 1e3 * el_prof / args.steps,
     }

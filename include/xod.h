@@ -251,7 +251,18 @@ typedef struct {
   double dt0;        /* [1e-8 s] */
   int32_t max_steps; /* [5000]  */
   int32_t max_consec_rejects; /* [30] */
-  int32_t use_mix_rule;       /* 0/1 [1 if the struct is NULL] */
+  int32_t use_mix_rule;       /* One backward-Euler step with the step matrix of the last xod_step
+ * frozen (the factor-reusing family of stiff integrators): solve
+ * (I/dt - J(n_f)) Delta = F(n) with the factorisation xod_step left for the
+ * state n_f it started from, at the current state n, then n <- n + Delta.
+ * Rates and F are those of n (spectral photolysis too).  Costs the rates,
+ * F, the solve and the update, no Jacobian and no factorisation.  FP64
+ * columns; dt must equal the dt of that xod_step (XOD_EINVAL otherwise, or
+ * when no factorisation is held: after creation, a solver switch or a
+ * mixed-precision step).  st as for xod_step (resid_inf, refine_iters 0). */
+xod_status xod_step_frozen(xod_column *col, double dt, xod_step_stats *st);
+
+/* 0/1 [1 if the struct is NULL] */
   int32_t pad_;
 } xod_ss_opts;
 typedef struct {

@@ -64,6 +64,18 @@ def be_step(prob, n, dt, solver="btd", newton_iters=1):
     return n + delta, delta
 
 
+def frozen_step(prob, n, frozen):
+    """One backward-Euler step with a step matrix frozen at an earlier state
+    (the factor-reusing family of stiff integrators the paper's solver
+    belongs to): solve M_f Delta = F(n) with frozen = (B, a, c) of
+    prob.step_matrix(n_f, dt), rates and F at n.  Returns (n_new, delta)."""
+    if getattr(prob, "spectrum", None) is not None:
+        prob.lag_photolysis(n)
+    B, a, c = frozen
+    delta = btd(B, a, c, prob.rhs(n))
+    return n + delta, delta
+
+
 def fixed_schedule(nsteps=200, dt0=1.0e-8, growth=1.2):
     """dt_j = dt0 * growth^j, j = 0 .. nsteps-1."""
     return [dt0 * growth ** j for j in range(nsteps)]

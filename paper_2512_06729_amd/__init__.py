@@ -116,6 +116,7 @@ _f = {
     "xod_btd_solve": _sig("xod_btd_solve", c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
                           c_void_p, c_void_p),
     "xod_step": _sig("xod_step", c_void_p, c_double, ctypes.POINTER(StepStats)),
+    "xod_step_frozen": _sig("xod_step_frozen", c_void_p, c_double, ctypes.POINTER(StepStats)),
     "xod_integrate_to_steady_state": _sig("xod_integrate_to_steady_state", c_void_p,
                                           ctypes.POINTER(SSOpts), ctypes.POINTER(SSResult)),
     "xod_last_error": _sig("xod_last_error", ctypes.c_char_p, ctypes.c_size_t),
@@ -379,6 +380,13 @@ def xod_btd_solve(col, B, a, c, piv, rhs):
 def xod_step(col, dt):
     st = StepStats()
     _check(_f["xod_step"](col.handle, float(dt), ctypes.byref(st)))
+    return st.as_dict()
+
+
+def xod_step_frozen(col, dt):
+    """A step reusing the factorisation of the last xod_step (same dt)."""
+    st = StepStats()
+    _check(_f["xod_step_frozen"](col.handle, float(dt), ctypes.byref(st)))
     return st.as_dict()
 
 

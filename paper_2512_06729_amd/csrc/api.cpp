@@ -639,6 +639,7 @@ extern "C" xod_status xod_column_set_solver(xod_column *col, xod_solver solver) 
       col->cr32 = p.release();
     }
   }
+  if (col->solver != solver) col->fact_dt = 0.0;
   col->solver = solver;
   return XOD_OK;
 }
@@ -735,6 +736,7 @@ xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, do
   XOD_HIP(launch_rates(one, 1, c->N, c->R, c->stream));
   XOD_HIP(launch_rhs(one, 1, c->N, c->R, c->S, c->stream));
   const bool cr = c->solver == XOD_SOLVER_CR;
+  c->fact_dt = 0.0;
   if (c->prec == XOD_FP64) {
     XOD_HIP(launch_jacobian(one, 1, c->N, c->R, c->ld, false, c->stream));
     if (cr)
@@ -747,6 +749,7 @@ xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, do
       XOD_TRY(c->cr64->solve(c));
     else
       XOD_HIP(launch_solve_fp64(one, 1, c->N, c->ld, c->stream));
+    c->fact_dt = dt;
     return XOD_OK;
   }
   // Mixed precision: row-scaled FP32 Schur complements, FP64 refinement with a
@@ -834,6 +837,43 @@ extern "C" xod_status xod_step(xod_column *col, double dt, xod_step_stats *st) {
   std::swap(col->n, col->ntmp);
   col->t += dt;
   col->dt = dt;
+  return XOD_OK;
+}
+
+extern "C" xod_status xod_step_frozen(xod_column *col, double dt, xod_step_stats *st) {
+  XOD_CHECK(col, "xod_step_frozen: null column");
+  XOD_CHECK(!col->in_batch, "xod_step_frozen: column belongs to a batch");
+  XOD_CHECK(col->prec == XOD_FP64, "xod_step_frozen: FP64 columns only");
+  XOD_CHECK(col->fact_dt > 0 && dt == col->fact_dt,
+            "xod_step_frozen: dt must equal that of the factorisation of the last xod_step");
+  ColArgs a = col->args();
+  OneCol one{a};
+  XOD_TRY(enqueue_photolysis(col));
+  XOD_HIP(launch_rates(one, 1, col->N, col->R, col->stream));
+  XOD_HIP(launch_rhs(one, 1, col->N, col->R, col->S, col->stream));
+  XOD_HIP(hipMemcpyAsync(col->x, col->f, (size_t)col->N * col->S * sizeof(double),
+                         hipMemcpyDeviceToDevice, col->stream));
+  if (col->solver == XOD_SOLVER_CR)
+    XOD_TRY(col->cr64->solve(col));
+  else
+    XOD_HIP(launch_solve_fp64(one, 1, col->N, col->ld, col->stream));
+  double s[kStatLen];
+  XOD_TRY(run_update(col, false, 1e-30, 1e-10, s));
+  XOD_TRY(check_flags(col, s + kNStat));
+  if (st) {
+    st->max_rel_change = s[0];
+    st->min_ratio = s[1];
+    st->resid_inf = 0.0;
+    st->refine_iters = 0;
+    st->fp64_fallback = 0;
+    st->nonfinite = s[5] > 0 ? 1 : 0;
+  }
+  if (s[5] > 0) {
+    set_error("xod_step_frozen: non-finite state after the step");
+    return XOD_ENONFINITE;
+  }
+  std::swap(col->n, col->ntmp);
+  col->t += dt;
   return XOD_OK;
 }
 

@@ -67,6 +67,7 @@ struct xod_column {
   UpdArgs *upd_dev = nullptr, *upd_host = nullptr;   // host side pinned
   RedArgs *red_dev = nullptr, *red_host = nullptr;
   double t = 0.0, dt = 0.0;
+  double fact_dt = 0.0;   // dt of the FP64 factorisation held in the blocks (0: none)
   bool in_batch = false;
   xod_solver solver = XOD_SOLVER_THOMAS;
   xod::CrPlan<double> *cr64 = nullptr;   // block cyclic reduction (FP64 column)

@@ -175,3 +175,18 @@ def test_steady_state_of_closed_layers_is_element_potential_equilibrium():
         rev = prob.kr[k] * np.prod([np.where(net.prod[:, j] >= 0, res.n[k, net.prod[:, j]], 1.0) for j in range(3)], axis=0)
         big = fwd > 1e-300
         np.testing.assert_allclose(rev[big] / fwd[big], 1.0, rtol=1e-5)
+
+
+def test_frozen_step_with_the_current_matrix_is_the_be_step():
+    """With the matrix of the current state, the frozen step is the
+    backward-Euler step; repeated frozen steps at a fixed point stay there."""
+    import synth
+    from oracle import integrate
+    net = synth.make_network("c1", seed=1001)
+    col = synth.make_column("c1", net, seed=305, N=5)
+    prob = integrate.Problem(net, col)
+    n0 = col.n0
+    dt = 1e-4
+    ref, _ = integrate.be_step(prob, n0, dt)
+    got, _ = integrate.frozen_step(prob, n0, prob.step_matrix(n0, dt))
+    np.testing.assert_array_equal(got, ref)
