@@ -76,6 +76,30 @@ def frozen_step(prob, n, frozen):
     return n + delta, delta
 
 
+ROS2_GAMMA = 1.0 + 1.0 / np.sqrt(2.0)
+
+
+def ros2_step(prob, n, dt):
+    """One step of the two-stage, second-order, L-stable Rosenbrock method
+    ROS2 (Verwer, Spee, Blom and Hundsdorfer, SIAM J. Sci. Comput. 20, 1999),
+    one of the stiff integrators Section 2.1 lists for this problem, built on
+    the same step matrix and block-tridiagonal solve as the backward-Euler
+    step.  With gamma = 1 + 1/sqrt(2) and W = I - gamma dt J(n):
+        W k1 = F(n),  W k2 = F(n + dt k1) - 2 k1,
+        n_new = n + dt (3/2 k1 + 1/2 k2).
+    W = gamma dt M with M = prob.step_matrix(n, gamma dt), so each stage is a
+    solve with M and a division by gamma dt.  Rates (the lagged photolysis
+    too) are those of n for both stages.  Returns (n_new, delta)."""
+    if getattr(prob, "spectrum", None) is not None:
+        prob.lag_photolysis(n)
+    gdt = ROS2_GAMMA * dt
+    B, a, c = prob.step_matrix(n, gdt)
+    k1 = btd(B, a, c, prob.rhs(n)) / gdt
+    k2 = btd(B, a, c, prob.rhs(n + dt * k1) - 2.0 * k1) / gdt
+    delta = dt * (1.5 * k1 + 0.5 * k2)
+    return n + delta, delta
+
+
 def fixed_schedule(nsteps=200, dt0=1.0e-8, growth=1.2):
     """dt_j = dt0 * growth^j, j = 0 .. nsteps-1."""
     return [dt0 * growth ** j for j in range(nsteps)]
