@@ -484,6 +484,23 @@ def main():
         except xod.XodError as e:
             frozen = {"error": str(e)}
 
+    # Rosenbrock ROS2: one factorisation, two solves per step
+    ros2 = None
+    if args.solver == "cr":
+        try:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                xod.xod_step_ros2(gcol, args.dt)
+            torch.cuda.synchronize()
+            el_r = (time.perf_counter() - t0) / args.steps
+            ros2 = {"value": 1.0 / el_r, "unit": "steps/s", "ms_per_step": 1e3 * el_r,
+                    "what": "xod_step_ros2: two-stage Rosenbrock step (rates, two F, "
+                            "Jacobian, one factorisation, two solves, update)"}
+            progress(f"ROS2 steps: {1.0 / el_r:.2f} steps/s")
+        except xod.XodError as e:
+            ros2 = {"error": str(e)}
+
     steps_per_s = args.steps / el
     line = {
         "metric": "implicit steps/sec at 594 sp x 150 layers (FP64)",
@@ -507,6 +524,7 @@ def main():
         "roofline_schur_gemm": gemm_rl,
         "roofline_schur_gemm_other_path": gemm_alt,
         "frozen_matrix_steps": frozen,
+        "ros2_steps": ros2,
         "kernels": kern,
         "ms_per_step_with_kernel_events": 1e3 * el_prof / args.steps,
     }

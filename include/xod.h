@@ -235,6 +235,29 @@ typedef struct {
 } xod_step_stats;
 xod_status xod_step(xod_column *col, double dt, xod_step_stats *stats);
 
+/* One backward-Euler step with the step matrix of the last xod_step
+ * frozen (the factor-reusing family of stiff integrators): solve
+ * (I/dt - J(n_f)) Delta = F(n) with the factorisation xod_step left for the
+ * state n_f it started from, at the current state n, then n <- n + Delta.
+ * Rates and F are those of n (spectral photolysis too).  Costs the rates,
+ * F, the solve and the update, no Jacobian and no factorisation.  FP64
+ * columns; dt must equal the dt of that xod_step (XOD_EINVAL otherwise, or
+ * when no factorisation is held: after creation, a solver switch or a
+ * mixed-precision step).  st as for xod_step (resid_inf, refine_iters 0). */
+xod_status xod_step_frozen(xod_column *col, double dt, xod_step_stats *st);
+
+/* One step of the two-stage, second-order, L-stable Rosenbrock method ROS2
+ * (Verwer, Spee, Blom and Hundsdorfer 1999; Section 2.1 names Rosenbrock
+ * solvers among the stiff integrators for this problem) on the same step
+ * matrix and block-tridiagonal solver as xod_step: with g = 1 + 1/sqrt 2,
+ * M = I/(g dt) - J(n) is factored once and solved twice,
+ *   M d1 = F(n),  M d2 = F(n + d1/g) - 2 d1/(g dt),  n <- n + (3 d1 + d2)/(2g).
+ * Rates (spectral photolysis too) are those of n for both stages.  FP64
+ * columns (XOD_EINVAL for mixed), dt > 0.  Leaves the factorisation of
+ * g dt held, so xod_step_frozen(col, g*dt) may follow.  st as for xod_step
+ * (resid_inf, refine_iters 0); XOD_ENONFINITE leaves the state unchanged. */
+xod_status xod_step_ros2(xod_column *col, double dt, xod_step_stats *st);
+
 /* Adaptive driver to steady state.
  *   reject (dt /= 2) if the step is not finite or a species whose mixing
  *   ratio exceeded y_sig turns negative; accept otherwise, clip negatives to
@@ -251,18 +274,7 @@ typedef struct {
   double dt0;        /* [1e-8 s] */
   int32_t max_steps; /* [5000]  */
   int32_t max_consec_rejects; /* [30] */
-  int32_t use_mix_rule;       /* One backward-Euler step with the step matrix of the last xod_step
- * frozen (the factor-reusing family of stiff integrators): solve
- * (I/dt - J(n_f)) Delta = F(n) with the factorisation xod_step left for the
- * state n_f it started from, at the current state n, then n <- n + Delta.
- * Rates and F are those of n (spectral photolysis too).  Costs the rates,
- * F, the solve and the update, no Jacobian and no factorisation.  FP64
- * columns; dt must equal the dt of that xod_step (XOD_EINVAL otherwise, or
- * when no factorisation is held: after creation, a solver switch or a
- * mixed-precision step).  st as for xod_step (resid_inf, refine_iters 0). */
-xod_status xod_step_frozen(xod_column *col, double dt, xod_step_stats *st);
-
-/* 0/1 [1 if the struct is NULL] */
+  int32_t use_mix_rule;       /* 0/1 [1 if the struct is NULL] */
   int32_t pad_;
 } xod_ss_opts;
 typedef struct {

@@ -79,7 +79,7 @@ def frozen_step(prob, n, frozen):
 ROS2_GAMMA = 1.0 + 1.0 / np.sqrt(2.0)
 
 
-def ros2_step(prob, n, dt):
+def ros2_step(prob, n, dt, stages=False):
     """One step of the two-stage, second-order, L-stable Rosenbrock method
     ROS2 (Verwer, Spee, Blom and Hundsdorfer, SIAM J. Sci. Comput. 20, 1999),
     one of the stiff integrators Section 2.1 lists for this problem, built on
@@ -89,7 +89,8 @@ def ros2_step(prob, n, dt):
         n_new = n + dt (3/2 k1 + 1/2 k2).
     W = gamma dt M with M = prob.step_matrix(n, gamma dt), so each stage is a
     solve with M and a division by gamma dt.  Rates (the lagged photolysis
-    too) are those of n for both stages.  Returns (n_new, delta)."""
+    too) are those of n for both stages.  Returns (n_new, delta), and with
+    stages=True also the two terms of delta, (3/2 dt k1, 1/2 dt k2)."""
     if getattr(prob, "spectrum", None) is not None:
         prob.lag_photolysis(n)
     gdt = ROS2_GAMMA * dt
@@ -97,6 +98,8 @@ def ros2_step(prob, n, dt):
     k1 = btd(B, a, c, prob.rhs(n)) / gdt
     k2 = btd(B, a, c, prob.rhs(n + dt * k1) - 2.0 * k1) / gdt
     delta = dt * (1.5 * k1 + 0.5 * k2)
+    if stages:
+        return n + delta, delta, (1.5 * dt * k1, 0.5 * dt * k2)
     return n + delta, delta
 
 

@@ -117,6 +117,7 @@ _f = {
                           c_void_p, c_void_p),
     "xod_step": _sig("xod_step", c_void_p, c_double, ctypes.POINTER(StepStats)),
     "xod_step_frozen": _sig("xod_step_frozen", c_void_p, c_double, ctypes.POINTER(StepStats)),
+    "xod_step_ros2": _sig("xod_step_ros2", c_void_p, c_double, ctypes.POINTER(StepStats)),
     "xod_integrate_to_steady_state": _sig("xod_integrate_to_steady_state", c_void_p,
                                           ctypes.POINTER(SSOpts), ctypes.POINTER(SSResult)),
     "xod_last_error": _sig("xod_last_error", ctypes.c_char_p, ctypes.c_size_t),
@@ -387,6 +388,13 @@ def xod_step_frozen(col, dt):
     """A step reusing the factorisation of the last xod_step (same dt)."""
     st = StepStats()
     _check(_f["xod_step_frozen"](col.handle, float(dt), ctypes.byref(st)))
+    return st.as_dict()
+
+
+def xod_step_ros2(col, dt):
+    """One two-stage Rosenbrock (ROS2) step: one factorisation, two solves."""
+    st = StepStats()
+    _check(_f["xod_step_ros2"](col.handle, float(dt), ctypes.byref(st)))
     return st.as_dict()
 
 

@@ -877,6 +877,54 @@ extern "C" xod_status xod_step_frozen(xod_column *col, double dt, xod_step_stats
   return XOD_OK;
 }
 
+// Two-stage Rosenbrock step ROS2 (Verwer et al. 1999): one factorisation of
+// M = I/(g dt) - J(n), g = 1 + 1/sqrt 2, and two solves.  With d_i = g dt k_i,
+//   M d1 = F(n),   M d2 = F(n + d1/g) - 2 d1/(g dt),   n_new = n + (3 d1 + d2)/(2g).
+// The stage state lives in ntmp (the update writes it only afterwards) and
+// d1 in dx (used by the mixed-precision refinement only).
+extern "C" xod_status xod_step_ros2(xod_column *col, double dt, xod_step_stats *st) {
+  XOD_CHECK(col, "xod_step_ros2: null column");
+  XOD_CHECK(!col->in_batch, "xod_step_ros2: column belongs to a batch");
+  XOD_CHECK(col->prec == XOD_FP64, "xod_step_ros2: FP64 columns only");
+  XOD_CHECK(std::isfinite(dt) && dt > 0, "xod_step_ros2: dt must be > 0");
+  const double g = 1.0 + 1.0 / std::sqrt(2.0);
+  int iters, fb;
+  double res;
+  XOD_TRY(enqueue_solve(col, g * dt, &iters, &fb, &res));      // x = d1
+  const size_t NS = (size_t)col->N * col->S;
+  XOD_HIP(hipMemcpyAsync(col->dx, col->x, NS * sizeof(double), hipMemcpyDeviceToDevice,
+                         col->stream));
+  XOD_HIP(launch_lincomb(col->ntmp, col->n, 1.0, col->x, 1.0 / g, NS, col->stream));
+  ColArgs a = col->args();
+  a.n = col->ntmp;
+  XOD_HIP(launch_rhs(OneCol{a}, 1, col->N, col->R, col->S, col->stream));   // f = F(stage)
+  XOD_HIP(launch_lincomb(col->x, col->f, 1.0, col->dx, -2.0 / (g * dt), NS, col->stream));
+  if (col->solver == XOD_SOLVER_CR)
+    XOD_TRY(col->cr64->solve(col));
+  else
+    XOD_HIP(launch_solve_fp64(OneCol{col->args()}, 1, col->N, col->ld, col->stream));  // x = d2
+  XOD_HIP(launch_lincomb(col->x, col->dx, 1.5 / g, col->x, 0.5 / g, NS, col->stream));
+  double s[kStatLen];
+  XOD_TRY(run_update(col, false, 1e-30, 1e-10, s));
+  XOD_TRY(check_flags(col, s + kNStat));
+  if (st) {
+    st->max_rel_change = s[0];
+    st->min_ratio = s[1];
+    st->resid_inf = 0.0;
+    st->refine_iters = 0;
+    st->fp64_fallback = 0;
+    st->nonfinite = s[5] > 0 ? 1 : 0;
+  }
+  if (s[5] > 0) {
+    set_error("xod_step_ros2: non-finite state after the step");
+    return XOD_ENONFINITE;
+  }
+  std::swap(col->n, col->ntmp);
+  col->t += dt;
+  col->dt = dt;
+  return XOD_OK;
+}
+
 extern "C" xod_status xod_integrate_to_steady_state(xod_column *col, const xod_ss_opts *o,
                                                     xod_ss_result *res) {
   XOD_CHECK(col && res, "xod_integrate_to_steady_state: null argument");

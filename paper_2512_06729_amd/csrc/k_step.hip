@@ -1,5 +1,7 @@
 // State update and step statistics (n_new = n + delta), deterministic
 // two-stage reductions (no floating-point atomics).
+#include <algorithm>
+
 #include "xod_internal.h"
 
 namespace xod {
@@ -86,6 +88,24 @@ __global__ void k_invperm(const int *piv, int *rstep, int N, int ld) {
 
 hipError_t launch_invperm(const int *piv, int *rstep, int N, int ld, hipStream_t s) {
   hipLaunchKernelGGL(k_invperm, dim3(256), dim3(256), 0, s, piv, rstep, N, ld);
+  return hipGetLastError();
+}
+
+// out = alpha p + beta q, elementwise over n doubles (the Rosenbrock stage
+// state, stage right-hand side and final combination).  out may be p or q.
+__global__ void __launch_bounds__(256) k_lincomb(double *out, const double *p, double alpha,
+                                                 const double *q, double beta, size_t n) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    out[e] = alpha * p[e] + beta * q[e];
+}
+
+hipError_t launch_lincomb(double *out, const double *p, double alpha, const double *q,
+                          double beta, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_lincomb, dim3((unsigned)blocks), dim3(256), 0, s, out, p, alpha, q,
+                     beta, n);
   return hipGetLastError();
 }
 

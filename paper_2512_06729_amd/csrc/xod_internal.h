@@ -269,6 +269,9 @@ hipError_t launch_setup(const SetupArgs &a, hipStream_t st);
 hipError_t launch_update_state(const UpdArgs *dargs, const RedArgs *dred, int ncols,
                                hipStream_t s);
 hipError_t launch_invperm(const int *piv, int *rstep, int N, int ld, hipStream_t s);
+// out = alpha p + beta q over n doubles
+hipError_t launch_lincomb(double *out, const double *p, double alpha, const double *q,
+                          double beta, size_t n, hipStream_t s);
 
 }  // namespace xod
 

@@ -23,6 +23,24 @@ def test_library_exports_every_header_symbol():
     assert missing == []
 
 
+def test_header_is_plain_c(tmp_path):
+    """include/xod.h compiles as C99 with every warning an error, and each
+    declared entry point is a file-scope function of that name."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    import paper_2512_06729_amd as xod
+    src = tmp_path / "h.c"
+    calls = "\n".join(f"  (void)&{s};" for s in xod.header_symbols())
+    src.write_text('#include "xod.h"\nint main(void) {\n' + calls + "\n  return 0;\n}\n")
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
+                        "-I", os.path.join(ROOT, "include"), "-c", str(src), "-o",
+                        str(tmp_path / "h.o")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
 def _desc(xod, S=3, reac=None):
     keep = dict(comp=np.ones((1, S), np.int32), mass=np.full(S, 10.0),
                 nasa=np.zeros((S, 2, 7)), rtype=np.zeros(1, np.int32),

@@ -1,0 +1,75 @@
+"""GPU parity of the Rosenbrock step (xod_step_ros2: two stages on one
+factorisation) against the oracle's ros2_step, up to three steps in a row, each
+from the oracle's state, for block Thomas and cyclic reduction.
+
+Tolerance: per-layer rel 1e-9 as for the other solve tests, applied to the
+scale of the terms the increment sums, max(|3/2 dt k1|, |1/2 dt k2|, |delta|):
+for stiff species the two stage terms nearly cancel (L-stability sends
+them to equilibrium), and a sum is only determined relative to its terms."""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import synth  # noqa: E402
+from oracle import integrate  # noqa: E402
+from tests import gpu_common as G  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    import paper_2512_06729_amd  # noqa: F401  (fails loudly if not built)
+
+
+# The 594-species column takes one step at dt 1e-7 and two at 1e-8: its
+# first ROS2 step at 1e-7 leaves densities down to -27 % of the gas density
+# (backward Euler: -7e-5), and from there even a backward-Euler step differs
+# from the oracle by the right-hand side's rounding (production and loss
+# cancel), 3e-12 of each layer's largest increment for either solver.
+@pytest.mark.parametrize("solver,cfg,dt,steps", [(0, 1, 1e-6, 3), (1, 1, 1e-6, 3),
+                                                 (0, 2, 1e-6, 3), (1, 2, 1e-6, 3),
+                                                 (1, 3, 1e-7, 1), (0, 3, 1e-8, 2),
+                                                 (1, 3, 1e-8, 2), (0, 1, 1e-3, 3),
+                                                 (1, 1, 1e-3, 3)])
+def test_ros2_steps_match_oracle(solver, cfg, dt, steps):
+    import paper_2512_06729_amd as xod
+    print(f"ros2 solver={solver} config {cfg} dt={dt}", flush=True)
+    net, col = synth.make_config(cfg)
+    prob, gnet, gcol = G.make_pair(net, col)
+    gcol.set_solver(solver)
+    n = col.n0
+    for i in range(steps):
+        n_ref, delta, (t1, t2) = integrate.ros2_step(prob, n, dt, stages=True)
+        gcol.set_state(n, t=i * dt)
+        xod.xod_step_ros2(gcol, dt)
+        scale = np.maximum(np.maximum(np.abs(t1), np.abs(t2)), np.abs(delta))
+        G.assert_state_agrees(gcol.state(), n_ref, scale, rel=1e-9)
+        n = n_ref
+
+
+def test_ros2_then_frozen_and_errors():
+    import paper_2512_06729_amd as xod
+    net, col = synth.make_config(1)
+    prob, gnet, gcol = G.make_pair(net, col)
+    dt = 1e-6
+    g = 1.0 + 1.0 / np.sqrt(2.0)
+    n1, _ = integrate.ros2_step(prob, col.n0, dt)
+    xod.xod_step_ros2(gcol, dt)
+    # the factorisation of g*dt at the starting state is held
+    frozen = prob.step_matrix(col.n0, g * dt)
+    n2, d2 = integrate.frozen_step(prob, n1, frozen)
+    xod.xod_step_frozen(gcol, g * dt)
+    G.assert_state_agrees(gcol.state(), n2, d2, rel=1e-9)
+    with pytest.raises(xod.XodError) as e:
+        xod.xod_step_ros2(gcol, 0.0)
+    assert e.value.status == xod.XOD_EINVAL
+    gm = xod.Column(gnet, col, precision=xod.XOD_MIXED)
+    with pytest.raises(xod.XodError) as e:
+        xod.xod_step_ros2(gm, dt)
+    assert e.value.status == xod.XOD_EINVAL
+    gm.close()
