@@ -29,6 +29,9 @@ class Grid:
     beta: np.ndarray    # [N-1, S] 1/cm, drift coefficient
     tau: np.ndarray     # [N] optical depth at layer midpoints
     mix_time: float     # max over half levels/species of dzh^2 / (K + D)
+    v_top: np.ndarray = None     # [S] cm/s upward escape velocity at the top
+    v_dep: np.ndarray = None     # [S] cm/s deposition velocity at the bottom
+    phi_surf: np.ndarray = None  # [S] cm^-2 s^-1 surface emission into the bottom layer
 
 
 def make_grid(col, mass_amu):
@@ -96,5 +99,37 @@ def make_grid(col, mass_amu):
             if kd > 0.0:
                 mix = max(mix, dzh[k] ** 2 / kd)
 
+    v_top, v_dep, phi_surf = boundary_velocities(col, T, D, m, mbar, g)
     return Grid(N=N, S=S, T=T, ngas=ngas, z=z, dzh=dzh, dz=dz, Th=Th, nh=nh,
-                Kh=Kh, Dh=Dh, beta=beta, tau=tau, mix_time=mix)
+                Kh=Kh, Dh=Dh, beta=beta, tau=tau, mix_time=mix, v_top=v_top,
+                v_dep=v_dep, phi_surf=phi_surf)
+
+
+def boundary_velocities(col, T, D, m_amu, mbar, g):
+    """Boundary exchange of the column (zero everywhere when closed).
+
+    Top (Section 2.4): species flagged in col.escape_diff_limited leave with
+    the diffusion-limited velocity V_lim = D (1/H_0 - 1/H_y), H_0 = k_B T /
+    (mbar g) the atmosphere's and H_y = k_B T / (m_y g) the species' scale
+    height.  Readings: D and T are the top layer's (no half level lies above
+    it), and V_lim < 0 (a species heavier than the mean) gives no escape.
+    col.v_top adds set velocities (the paper's user-defined escape).
+    Bottom (Section 2.5): deposition velocities col.v_dep and surface
+    emission fluxes col.phi_surf."""
+    S = m_amu.shape[0]
+    v_top = np.zeros(S)
+    flags = getattr(col, "escape_diff_limited", None)
+    if flags is not None:
+        H0 = KB * T[-1] / (mbar * g)
+        for y in range(S):
+            if flags[y]:
+                Hy = KB * T[-1] / (m_amu[y] * AMU * g)
+                v_top[y] = max(D[-1, y] * (1.0 / H0 - 1.0 / Hy), 0.0)
+    extra = getattr(col, "v_top", None)
+    if extra is not None:
+        v_top = v_top + np.asarray(extra, float)
+    v_dep = getattr(col, "v_dep", None)
+    v_dep = np.zeros(S) if v_dep is None else np.asarray(v_dep, float).copy()
+    phi = getattr(col, "phi_surf", None)
+    phi = np.zeros(S) if phi is None else np.asarray(phi, float).copy()
+    return v_top, v_dep, phi

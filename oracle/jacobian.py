@@ -50,7 +50,9 @@ def transport_coefficients(grid):
       q_k = dF_{k+1/2}/dn_k     = n_h [ -(K+D)/dzh + D beta / 2 ] / n_gas,k
 
     so that df_tr,k/dn_{k+1} = p_k / dz_k, df_tr,k/dn_{k-1} = -q_{k-1} / dz_k,
-    df_tr,k/dn_k = (q_k - p_{k-1}) / dz_k, with the boundary terms absent.
+    df_tr,k/dn_k = (q_k - p_{k-1}) / dz_k; the boundary fluxes add
+    -v_dep / dz_0 at the bottom and -v_top / dz_{N-1} at the top (their
+    surface emission is constant).
     Returns (lower, diag, upper) arrays [N, S] of these derivatives."""
     N, S = grid.N, grid.S
     p = np.zeros((N - 1, S))
@@ -70,6 +72,10 @@ def transport_coefficients(grid):
         if k <= N - 2:
             upper[k] = p[k] / grid.dz[k]
             diag[k] += q[k] / grid.dz[k]
+    if grid.v_dep is not None:
+        diag[0] -= grid.v_dep / grid.dz[0]
+    if grid.v_top is not None:
+        diag[N - 1] -= grid.v_top / grid.dz[N - 1]
     return lower, diag, upper
 
 

@@ -57,14 +57,29 @@ def half_level_flux(grid, n):
     return F
 
 
+def boundary_flux(grid, n):
+    """F (= -phi, upward-positive phi) through the bottom and top of the
+    column: phi_bottom = phi_surf - v_dep n_0 (emission up, deposition down),
+    phi_top = v_top n_{N-1} (escape up); zero for a closed column
+    (Sections 2.4, 2.5)."""
+    zero = np.zeros(n.shape[1])
+    v_top = zero if grid.v_top is None else grid.v_top
+    v_dep = zero if grid.v_dep is None else grid.v_dep
+    phi = zero if grid.phi_surf is None else grid.phi_surf
+    F_bottom = -(phi - v_dep * n[0])
+    F_top = -(v_top * n[grid.N - 1])
+    return F_bottom, F_top
+
+
 def transport_rhs(grid, n):
-    """-d(phi)/dz at layer k = (F_{k+1/2} - F_{k-1/2}) / dz_k with zero flux
-    through the bottom and top boundaries (Section 2.5)."""
+    """-d(phi)/dz at layer k = (F_{k+1/2} - F_{k-1/2}) / dz_k, the outermost
+    F being the boundary fluxes."""
     F = half_level_flux(grid, n)
+    F_bottom, F_top = boundary_flux(grid, n)
     f = np.zeros_like(n)
     for k in range(grid.N):
-        up = F[k] if k <= grid.N - 2 else 0.0
-        down = F[k - 1] if k >= 1 else 0.0
+        up = F[k] if k <= grid.N - 2 else F_top
+        down = F[k - 1] if k >= 1 else F_bottom
         f[k] = (up - down) / grid.dz[k]
     return f
 

@@ -41,6 +41,14 @@ class Column:
     sigma_tau: float = 1.0e-22
     seed: int = 0
     info: dict = field(default_factory=dict)
+    # boundary fluxes, None = closed: escape at the top (Section 2.4) as 0/1
+    # flags for the diffusion-limited velocity and/or set velocities (cm/s),
+    # deposition velocities (cm/s) and surface emission fluxes (cm^-2 s^-1)
+    # at the bottom (Section 2.5); each [S]
+    escape_diff_limited: np.ndarray | None = None
+    v_top: np.ndarray | None = None
+    v_dep: np.ndarray | None = None
+    phi_surf: np.ndarray | None = None
 
     @property
     def N(self):
@@ -189,3 +197,26 @@ def make_spectrum(net, L=10000, seed=7000):
         sig_ext[a] = sig_ph[reac == sp].sum(axis=0) + 1e-27 * (5000.0 / lam) ** 4
     return dict(lam=lam, dlam=dlam, J0=J0, photo=photo.astype(np.int32), sig_ph=sig_ph,
                 absorbers=absorbers, sig_ext=sig_ext)
+
+
+def with_boundary(net, col, seed=8000, open_top=True, open_bottom=True):
+    """A copy of col with boundary exchange (Sections 2.4, 2.5): the species
+    lighter than the mean molecular mass flagged for diffusion-limited escape
+    (the paper's H/He case), set escape velocities of 0.1-10 cm/s on 10 % of
+    the others (its user-defined case), deposition velocities of 1e-3-1 cm/s
+    on 30 % of the species and surface emission of 1e8-1e11 cm^-2 s^-1 on
+    10 %, log-uniform.  Inputs only: no velocity or flux is derived here."""
+    import dataclasses
+    rng = np.random.default_rng(seed)
+    S = len(net.mass_amu)
+    light = (np.asarray(net.mass_amu) < col.mbar_amu).astype(np.int32)
+    pick_top = (rng.random(S) < 0.1) & (light == 0)
+    v_top = np.where(pick_top, 10.0 ** rng.uniform(-1.0, 1.0, S), 0.0)
+    v_dep = np.where(rng.random(S) < 0.3, 10.0 ** rng.uniform(-3.0, 0.0, S), 0.0)
+    phi = np.where(rng.random(S) < 0.1, 10.0 ** rng.uniform(8.0, 11.0, S), 0.0)
+    return dataclasses.replace(
+        col,
+        escape_diff_limited=light if open_top else None,
+        v_top=v_top if open_top else None,
+        v_dep=v_dep if open_bottom else None,
+        phi_surf=phi if open_bottom else None)
