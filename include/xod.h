@@ -308,6 +308,30 @@ xod_status xod_last_error(char *buf, size_t len);
  * the sizes need, or a short workspace; absorber indices are not checked
  * against S on the device. */
 size_t xod_photolysis_workspace(int32_t N, int32_t A, int32_t L, int32_t P);
+/* Exchange through the column's ends (Section 2.4 escape, Section 2.5
+ * boundary conditions), in the flux divergence of the bottom and top layers
+ * (upward flux positive):
+ *   top:    phi = v_top,y n_{y,N-1}                (escape)
+ *   bottom: phi = phi_surf,y - v_dep,y n_{y,0}     (emission, deposition)
+ * so df_{y,N-1} -= v_top n_{y,N-1} / dz_{N-1} and df_{y,0} += (phi_surf -
+ * v_dep n_{y,0}) / dz_0, and the step matrix gains v/dz on those diagonals.
+ * v_top,y = V_lim,y for species flagged in escape_diff_limited, V_lim =
+ * D (1/H_0 - 1/H_y) with H_0 = k_B T/(mbar g), H_y = k_B T/(m_y g) and the
+ * top layer's D and T, clamped at 0 (no escape for heavier-than-mean
+ * species), plus v_top[y] when given (set velocities).  Each member is a
+ * HOST array [S] or NULL (none of that kind): flags 0/1; v_top, v_dep cm/s,
+ * finite, >= 0; phi_surf cm^-2 s^-1, finite.  Copied; b == NULL (or all
+ * members NULL) closes the column again.  XOD_EINVAL for invalid entries
+ * (nothing changed) or a column in a batch.  Synchronous; a held
+ * factorisation is dropped (xod_step_frozen needs a new xod_step). */
+typedef struct {
+  const int32_t *escape_diff_limited;
+  const double *v_top;
+  const double *v_dep;
+  const double *phi_surf;
+} xod_boundary;
+xod_status xod_column_set_boundary(xod_column *col, const xod_boundary *b);
+
 /* Use spectral photolysis rates in this column's steps: every xod_step (and
  * xod_rates) first computes kph from the column's state at that moment, as
  * xod_photolysis_spectral does with the column's layer thicknesses, and the

@@ -63,6 +63,13 @@ class Profile(ctypes.Structure):
                 ("g_cgs", c_double), ("sigma_tau", c_double)]
 
 
+class Boundary(ctypes.Structure):
+    _fields_ = [("escape_diff_limited", ctypes.POINTER(c_int32)),
+                ("v_top", ctypes.POINTER(c_double)),
+                ("v_dep", ctypes.POINTER(c_double)),
+                ("phi_surf", ctypes.POINTER(c_double))]
+
+
 class StepStats(ctypes.Structure):
     _fields_ = [("max_rel_change", c_double), ("min_ratio", c_double),
                 ("resid_inf", c_double), ("refine_iters", c_int32),
@@ -118,6 +125,8 @@ _f = {
     "xod_step": _sig("xod_step", c_void_p, c_double, ctypes.POINTER(StepStats)),
     "xod_step_frozen": _sig("xod_step_frozen", c_void_p, c_double, ctypes.POINTER(StepStats)),
     "xod_step_ros2": _sig("xod_step_ros2", c_void_p, c_double, ctypes.POINTER(StepStats)),
+    "xod_column_set_boundary": _sig("xod_column_set_boundary", c_void_p,
+                                    ctypes.POINTER(Boundary)),
     "xod_integrate_to_steady_state": _sig("xod_integrate_to_steady_state", c_void_p,
                                           ctypes.POINTER(SSOpts), ctypes.POINTER(SSResult)),
     "xod_last_error": _sig("xod_last_error", ctypes.c_char_p, ctypes.c_size_t),
@@ -302,6 +311,30 @@ class Column:
         self.handle = h
         if solver != XOD_SOLVER_THOMAS:
             self.set_solver(solver)
+        bnd = {name: getattr(col, name, None)
+               for name in ("escape_diff_limited", "v_top", "v_dep", "phi_surf")}
+        if any(v is not None for v in bnd.values()):
+            self.set_boundary(**bnd)
+
+    def set_boundary(self, escape_diff_limited=None, v_top=None, v_dep=None, phi_surf=None):
+        """Open the column's ends (xod_column_set_boundary); all None closes them."""
+        S = self.S
+        keep = {}
+
+        def arr(name, v, dtype, ctype):
+            if v is None:
+                return None
+            a = np.ascontiguousarray(v, dtype)
+            if a.shape != (S,):
+                raise ValueError(f"{name} must have shape ({S},)")
+            keep[name] = a
+            return _ptr(a, ctype)
+
+        b = Boundary(arr("escape_diff_limited", escape_diff_limited, np.int32, c_int32),
+                     arr("v_top", v_top, np.float64, c_double),
+                     arr("v_dep", v_dep, np.float64, c_double),
+                     arr("phi_surf", phi_surf, np.float64, c_double))
+        _check(_f["xod_column_set_boundary"](self.handle, ctypes.byref(b)))
 
     def set_solver(self, solver):
         """XOD_SOLVER_THOMAS or XOD_SOLVER_CR (xod_column_set_solver)."""

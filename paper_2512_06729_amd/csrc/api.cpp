@@ -396,6 +396,12 @@ extern "C" xod_status xod_column_create(const xod_network *net, const xod_profil
   XOD_TRY(calloc_(c, &c->P, N, p->P_bar));
   XOD_TRY(calloc_(c, &c->T, N, p->T_K));
   XOD_TRY(calloc_(c, &c->K, N, p->Kzz));
+  c->T_top = p->T_K[N - 1];
+  c->mbar_amu = p->mbar_amu;
+  c->g_cgs = p->g_cgs;
+  c->D_top.assign(S, 0.0);
+  if (p->Dmol)
+    for (int y = 0; y < S; ++y) c->D_top[y] = p->Dmol[(size_t)(N - 1) * S + y];
   if (p->Dmol) XOD_TRY(calloc_(c, &c->D, NS, p->Dmol));
   if (p->alphaT) XOD_TRY(calloc_(c, &c->alpha, (size_t)S, p->alphaT));
   XOD_TRY(calloc_(c, &c->ngas, N));
@@ -525,6 +531,80 @@ extern "C" xod_status xod_column_grid(const xod_column *col, double *ngas, doubl
 // Hot-path calls on caller-owned device buffers.
 namespace xod {
 // The column's spectral photolysis rates at its current state, if set.
+extern "C" xod_status xod_column_set_boundary(xod_column *col, const xod_boundary *b) {
+  XOD_CHECK(col, "xod_column_set_boundary: null column");
+  XOD_CHECK(!col->in_batch, "xod_column_set_boundary: column belongs to a batch");
+  const int N = col->N, S = col->S;
+  std::vector<double> vt(S, 0.0), vd(S, 0.0), phi(S, 0.0);
+  if (b) {
+    if (b->escape_diff_limited) {
+      // V_lim = D (1/H_0 - 1/H_y) with the top layer's D and T, no escape
+      // for species heavier than the mean (V_lim < 0)
+      const double H0 = kBoltz * col->T_top / (col->mbar_amu * kAmu * col->g_cgs);
+      for (int y = 0; y < S; ++y) {
+        const int32_t fl = b->escape_diff_limited[y];
+        XOD_CHECK(fl == 0 || fl == 1, "xod_column_set_boundary: escape flags must be 0 or 1");
+        if (!fl) continue;
+        const double Hy = kBoltz * col->T_top / (col->net->mass_h[y] * kAmu * col->g_cgs);
+        vt[y] = std::max(col->D_top[y] * (1.0 / H0 - 1.0 / Hy), 0.0);
+      }
+    }
+    for (int y = 0; y < S; ++y) {
+      if (b->v_top) {
+        XOD_CHECK(std::isfinite(b->v_top[y]) && b->v_top[y] >= 0,
+                  "xod_column_set_boundary: v_top must be finite and >= 0");
+        vt[y] += b->v_top[y];
+      }
+      if (b->v_dep) {
+        XOD_CHECK(std::isfinite(b->v_dep[y]) && b->v_dep[y] >= 0,
+                  "xod_column_set_boundary: v_dep must be finite and >= 0");
+        vd[y] = b->v_dep[y];
+      }
+      if (b->phi_surf) {
+        XOD_CHECK(std::isfinite(b->phi_surf[y]), "xod_column_set_boundary: phi_surf not finite");
+        phi[y] = b->phi_surf[y];
+      }
+    }
+  }
+  const size_t rowb = (size_t)S * sizeof(double);
+  double dz[2];
+  XOD_HIP(hipMemcpyAsync(&dz[0], col->dz, sizeof(double), hipMemcpyDeviceToHost, col->stream));
+  XOD_HIP(hipMemcpyAsync(&dz[1], col->dz + (N - 1), sizeof(double), hipMemcpyDeviceToHost,
+                         col->stream));
+  if (col->trd_bot0.empty()) {
+    col->trd_bot0.resize(S);
+    col->trd_top0.resize(S);
+    XOD_HIP(hipMemcpyAsync(col->trd_bot0.data(), col->trd, rowb, hipMemcpyDeviceToHost,
+                           col->stream));
+    XOD_HIP(hipMemcpyAsync(col->trd_top0.data(), col->trd + (size_t)(N - 1) * S, rowb,
+                           hipMemcpyDeviceToHost, col->stream));
+  }
+  XOD_HIP(hipStreamSynchronize(col->stream));
+  // a single layer is both the bottom and the top layer
+  std::vector<double> bot = col->trd_bot0, top = col->trd_top0;
+  std::vector<double> &toprow = N == 1 ? bot : top;
+  bool any_src = false;
+  std::vector<double> src(S, 0.0);
+  for (int y = 0; y < S; ++y) {
+    bot[y] -= vd[y] / dz[0];
+    toprow[y] -= vt[y] / dz[1];
+    src[y] = phi[y] / dz[0];
+    any_src = any_src || phi[y] != 0.0;
+  }
+  XOD_HIP(hipMemcpyAsync(col->trd, bot.data(), rowb, hipMemcpyHostToDevice, col->stream));
+  if (N > 1)
+    XOD_HIP(hipMemcpyAsync(col->trd + (size_t)(N - 1) * S, top.data(), rowb,
+                           hipMemcpyHostToDevice, col->stream));
+  if (any_src) {
+    if (!col->bsrc) XOD_TRY(calloc_(col, &col->bsrc, (size_t)S));
+    XOD_HIP(hipMemcpyAsync(col->bsrc, src.data(), rowb, hipMemcpyHostToDevice, col->stream));
+  }
+  XOD_HIP(hipStreamSynchronize(col->stream));
+  col->has_bsrc = any_src;
+  col->fact_dt = 0.0;     // the step matrix changed
+  return XOD_OK;
+}
+
 static xod_status enqueue_photolysis(xod_column *c) {
   if (c->ph_L <= 0 || c->net->nph == 0) return XOD_OK;
   XOD_HIP(launch_photolysis(c->N, c->S, c->ph_A, c->ph_L, c->net->nph, c->n, c->dz, c->ph_abs,

@@ -54,6 +54,14 @@ struct xod_column {
   void *ph_work = nullptr;
   size_t ph_work_bytes = 0;
   double mix_time = 0.0;
+  // Boundary exchange (xod_column_set_boundary): the velocities sit in the
+  // transport diagonal trd of the bottom and top layers (rows kept as set up
+  // in trd_bot0 / trd_top0), the surface emission in bsrc.
+  double T_top = 0.0, mbar_amu = 0.0, g_cgs = 0.0;
+  std::vector<double> D_top;               // [S] molecular diffusion of the top layer
+  std::vector<double> trd_bot0, trd_top0;  // trd rows 0 and N-1 of the closed column
+  double *bsrc = nullptr;
+  bool has_bsrc = false;
   double *dwd = nullptr;   // [N*R*6] reaction-rate derivatives of the last Jacobian
   double *n = nullptr, *ntmp = nullptr, *kf = nullptr, *kr = nullptr, *w = nullptr,
          *f = nullptr, *x = nullptr, *gs = nullptr, *resid = nullptr, *dx = nullptr;
@@ -115,6 +123,7 @@ struct xod_column {
     a_.trl = trl;
     a_.trd = trd;
     a_.tru = tru;
+    a_.bsrc = has_bsrc ? bsrc : nullptr;
     a_.kf_in = kf;
     a_.kr_in = kr;
     a_.n = n;

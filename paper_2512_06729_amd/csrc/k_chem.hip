@@ -209,6 +209,7 @@ __global__ void __launch_bounds__(256) k_rhs(Acc acc) {
   double tr = c.trd[o] * c.n[o];
   if (k >= 1) tr += c.trl[o] * c.n[o - c.S];
   if (k + 1 < c.N) tr += c.tru[o] * c.n[o + c.S];
+  if (k == 0 && c.bsrc) tr += c.bsrc[y];
   c.f[o] = f + tr;
 }
 

@@ -40,6 +40,7 @@ struct ColArgs {
   const double *kph;                // [N*nph] spectral photolysis rates, or null (gray)
   // grid (device, owned by the column)
   const double *T, *ngas, *tau, *lnpref, *g, *trl, *trd, *tru;
+  const double *bsrc;               // [S] surface emission / dz_0 into layer 0, or null
   // operands
   const double *kf_in, *kr_in, *n;
   double *kf, *kr, *w, *f;

@@ -205,7 +205,8 @@ def with_boundary(net, col, seed=8000, open_top=True, open_bottom=True):
     (the paper's H/He case), set escape velocities of 0.1-10 cm/s on 10 % of
     the others (its user-defined case), deposition velocities of 1e-3-1 cm/s
     on 30 % of the species and surface emission of 1e8-1e11 cm^-2 s^-1 on
-    10 %, log-uniform.  Inputs only: no velocity or flux is derived here."""
+    10 %, log-uniform, and at least one species of each kind.  Inputs only:
+    no velocity or flux is derived here."""
     import dataclasses
     rng = np.random.default_rng(seed)
     S = len(net.mass_amu)
@@ -214,6 +215,13 @@ def with_boundary(net, col, seed=8000, open_top=True, open_bottom=True):
     v_top = np.where(pick_top, 10.0 ** rng.uniform(-1.0, 1.0, S), 0.0)
     v_dep = np.where(rng.random(S) < 0.3, 10.0 ** rng.uniform(-3.0, 0.0, S), 0.0)
     phi = np.where(rng.random(S) < 0.1, 10.0 ** rng.uniform(8.0, 11.0, S), 0.0)
+    # at least one species of each kind, also on small networks
+    for arr, lo, hi, allowed in ((v_top, -1.0, 1.0, light == 0), (v_dep, -3.0, 0.0, None),
+                                 (phi, 8.0, 11.0, None)):
+        if not (arr > 0).any():
+            idx = np.nonzero(allowed)[0] if allowed is not None else np.arange(S)
+            if len(idx):
+                arr[rng.choice(idx)] = 10.0 ** rng.uniform(lo, hi)
     return dataclasses.replace(
         col,
         escape_diff_limited=light if open_top else None,

@@ -1,0 +1,146 @@
+"""GPU parity of the boundary exchange (xod_column_set_boundary: escape at
+the top, deposition and surface emission at the bottom; Sections 2.4, 2.5)
+against the oracle: right-hand side to 1e-12 of its summed terms, the step
+matrix's boundary diagonals, backward-Euler steps for both factorisations
+and the mixed-precision step, batches, closing the ends again, and the
+argument checks."""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import synth  # noqa: E402
+from oracle import integrate, jacobian  # noqa: E402
+from tests import gpu_common as G  # noqa: E402
+from tests.test_gpu_parity import _rhs_scale  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    import paper_2512_06729_amd  # noqa: F401  (fails loudly if not built)
+
+
+def open_pair(cfg, precision=0):
+    net, col = synth.make_config(cfg)
+    bcol = synth.with_boundary(net, col, seed=8000 + cfg)
+    prob, gnet, gcol = G.make_pair(net, bcol, precision)
+    return net, bcol, prob, gnet, gcol
+
+
+def gpu_rhs(gcol, kf, kr, n_np):
+    import paper_2512_06729_amd as xod
+    n = torch.from_numpy(np.ascontiguousarray(n_np)).to(G.dev()).reshape(-1)
+    f = torch.empty_like(n)
+    xod.xod_rhs(gcol, kf, kr, n, f)
+    return G.to_np(f, n_np.shape)
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_open_rhs_matches_oracle(cfg):
+    print(f"boundary rhs config {cfg}", flush=True)
+    net, col, prob, gnet, gcol = open_pair(cfg)
+    g = prob.grid
+    assert (g.v_top > 0).any() and (g.v_dep > 0).any() and (g.phi_surf > 0).any()
+    kf, kr = G.gpu_rates(gcol)
+    rng = np.random.default_rng(9)
+    for n_np in (col.n0, col.n0 * 10.0 ** rng.uniform(-1, 1, col.n0.shape)):
+        f = gpu_rhs(gcol, kf, kr, n_np)
+        ref = prob.rhs(n_np)
+        scale = _rhs_scale(prob, n_np)
+        scale[0] += np.abs(g.phi_surf) / g.dz[0]
+        assert np.all(np.abs(f - ref) <= 1e-12 * scale + 1e-300)
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_open_step_matrix_boundary_rows(cfg):
+    net, col, prob, gnet, gcol = open_pair(cfg)
+    kf, kr = G.gpu_rates(gcol)
+    dt = 1e4
+    n, B, a, c = G.gpu_blocks(gcol, kf, kr, col.n0, dt)
+    N, S, ld = gcol.N, gcol.S, gcol.ld
+    B = G.to_np(B, (N, ld, ld))
+    lo, di, up = jacobian.transport_coefficients(prob.grid)
+    J = jacobian.chem_jacobian(net, prob.kf[[0, N - 1]], prob.kr[[0, N - 1]], col.n0[[0, N - 1]])
+    for li, k in enumerate((0, N - 1)):
+        ref = -J[li] + np.eye(S) / dt - np.diag(di[k])
+        rowmax = np.abs(ref).max(axis=1, keepdims=True)
+        assert np.all(np.abs(B[k, :S, :S] - ref) <= 1e-12 * rowmax)
+
+
+@pytest.mark.parametrize("solver,cfg,dt", [(0, 1, 1e-6), (1, 1, 1e-6), (0, 2, 1e-6),
+                                           (1, 2, 1e-6), (1, 3, 1e-7), (0, 1, 1e-3),
+                                           (1, 1, 1e-3)])
+def test_open_steps_match_oracle(solver, cfg, dt):
+    import paper_2512_06729_amd as xod
+    print(f"boundary step solver={solver} config {cfg} dt={dt}", flush=True)
+    net, col, prob, gnet, gcol = open_pair(cfg)
+    gcol.set_solver(solver)
+    n = col.n0
+    for i in range(2):
+        ref, delta = integrate.be_step(prob, n, dt)
+        gcol.set_state(n, t=i * dt)
+        xod.xod_step(gcol, dt)
+        G.assert_state_agrees(gcol.state(), ref, delta, rel=1e-9)
+        n = ref
+
+
+def test_open_mixed_step_matches_fp64_oracle():
+    import paper_2512_06729_amd as xod
+    net, col, prob, gnet, gcol = open_pair(2, precision=xod.XOD_MIXED)
+    ref, delta = integrate.be_step(prob, col.n0, 1e-6)
+    st = xod.xod_step(gcol, 1e-6)
+    assert st["fp64_fallback"] == 0 and st["refine_iters"] >= 1
+    G.assert_state_agrees(gcol.state(), ref, delta, rel=1e-8)
+
+
+def test_open_columns_in_a_batch_equal_single_columns():
+    import paper_2512_06729_amd as xod
+    stream = torch.cuda.current_stream().cuda_stream
+    net = synth.make_network("c2", seed=1002)
+    cols = [synth.with_boundary(net, synth.make_column("c2", net, seed=21 + j, N=N), seed=j)
+            for j, N in enumerate((30, 9, 41))]
+    gnet = xod.Network(net)
+    alone = [xod.Column(gnet, c, stream=stream) for c in cols]
+    inb = [xod.Column(gnet, c, stream=stream) for c in cols]
+    batch = xod.Batch(inb)
+    dts = np.array([1e-6, 3e-5, 1e-4])
+    for _ in range(2):
+        for c, dt in zip(alone, dts):
+            xod.xod_step(c, dt)
+        batch.step(dts)
+    for c1, c2 in zip(alone, inb):
+        np.testing.assert_array_equal(c1.state(), c2.state())
+    with pytest.raises(xod.XodError) as e:
+        inb[0].set_boundary()
+    assert e.value.status == xod.XOD_EINVAL
+
+
+def test_closing_the_ends_restores_the_closed_column():
+    import paper_2512_06729_amd as xod
+    net, col = synth.make_config(2)
+    prob, gnet, gcol = G.make_pair(net, col)
+    kf, kr = G.gpu_rates(gcol)
+    f0 = gpu_rhs(gcol, kf, kr, col.n0)
+    bcol = synth.with_boundary(net, col)
+    gcol.set_boundary(bcol.escape_diff_limited, bcol.v_top, bcol.v_dep, bcol.phi_surf)
+    f1 = gpu_rhs(gcol, kf, kr, col.n0)
+    assert not np.array_equal(f0, f1)
+    # setting again replaces (does not add to) the earlier velocities
+    gcol.set_boundary(bcol.escape_diff_limited, bcol.v_top, bcol.v_dep, bcol.phi_surf)
+    np.testing.assert_array_equal(gpu_rhs(gcol, kf, kr, col.n0), f1)
+    gcol.set_boundary()
+    np.testing.assert_array_equal(gpu_rhs(gcol, kf, kr, col.n0), f0)
+    S = gcol.S
+    for kw in (dict(v_dep=np.full(S, -1.0)), dict(v_top=np.full(S, np.nan)),
+               dict(phi_surf=np.full(S, np.inf)),
+               dict(escape_diff_limited=np.full(S, 2, np.int32))):
+        with pytest.raises(xod.XodError) as e:
+            gcol.set_boundary(**kw)
+        assert e.value.status == xod.XOD_EINVAL
+    # a rejected call changed nothing
+    np.testing.assert_array_equal(gpu_rhs(gcol, kf, kr, col.n0), f0)
