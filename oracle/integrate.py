@@ -103,6 +103,25 @@ def ros2_step(prob, n, dt, stages=False):
     return n + delta, delta
 
 
+def bdf2_step(prob, n, n_prev, dt):
+    """One linearly implicit step of the second-order backward
+    differentiation formula (BDF2, the lowest member above backward Euler of
+    the BDF family that DLSODES, named in Section 2.1, integrates with) at
+    constant step dt:
+        n_new - 4/3 n + 1/3 n_prev = 2/3 dt F(n_new),
+    with F(n_new) linearised about n (one Newton iteration from n).  With
+    h = 2 dt / 3 and Delta = n_new - n this is the backward-Euler system of
+    step h with the history term added to the right-hand side:
+        (I/h - J(n)) Delta = F(n) + (n - n_prev) / (2 dt).
+    Returns (n_new, delta)."""
+    if getattr(prob, "spectrum", None) is not None:
+        prob.lag_photolysis(n)
+    h = 2.0 * dt / 3.0
+    B, a, c = prob.step_matrix(n, h)
+    delta = btd(B, a, c, prob.rhs(n) + (n - n_prev) / (2.0 * dt))
+    return n + delta, delta
+
+
 def fixed_schedule(nsteps=200, dt0=1.0e-8, growth=1.2):
     """dt_j = dt0 * growth^j, j = 0 .. nsteps-1."""
     return [dt0 * growth ** j for j in range(nsteps)]

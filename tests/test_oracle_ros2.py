@@ -1,5 +1,6 @@
-"""Pins of the oracle's Rosenbrock step (ROS2: Verwer, Spee, Blom and
-Hundsdorfer 1999; Section 2.1 lists Rosenbrock solvers for this problem).
+"""Pins of the oracle's second-order steps: the Rosenbrock step (ROS2:
+Verwer, Spee, Blom and Hundsdorfer 1999; Section 2.1 lists Rosenbrock
+solvers for this problem) and the linearly implicit BDF2 step.
 
 * With the chemistry switched off the right-hand side is the linear
   transport operator L (built here by probing F with unit vectors), and one
@@ -11,7 +12,12 @@ Hundsdorfer 1999; Section 2.1 lists Rosenbrock solvers for this problem).
   on the diffusive equilibrium exp(dt L) n0, as R(-inf) = 0.
 * Order: on the 12-species column with its full chemistry, against scipy's
   Radau at rtol 1e-12, halving the step divides the error by 4 (backward
-  Euler by 2)."""
+  Euler by 2).
+* BDF2 on the linear problem is the textbook recurrence
+  (I - 2/3 dt L) n_new = 4/3 n - 1/3 n_prev (the linearisation is exact
+  there); it reaches the diffusive equilibrium at huge dt; with the full
+  chemistry, started by one backward-Euler step, it is second order
+  against Radau."""
 
 import numpy as np
 import pytest
@@ -93,3 +99,45 @@ def test_ros2_is_second_order_on_the_chemistry():
     b = [err(integrate.be_step, m) for m in (4, 8)]
     assert 1.8 < b[0] / b[1] < 2.2
     assert r[2] < 1e-2 * b[1]
+
+
+@pytest.mark.parametrize("dt", [1e3, 1e6, 1e9])
+def test_bdf2_on_a_linear_problem_is_the_bdf2_recurrence(transport_only, dt):
+    prob, n0, L = transport_only
+    n_prev = n0 * (1.0 + 0.1 * np.random.default_rng(4).random(n0.shape))
+    eye = np.eye(L.shape[0])
+    want = np.linalg.solve(eye - (2.0 / 3.0) * dt * L,
+                           (4.0 / 3.0) * n0.ravel() - (1.0 / 3.0) * n_prev.ravel())
+    got, delta = integrate.bdf2_step(prob, n0, n_prev, dt)
+    assert np.abs(got.ravel() - want).max() <= 1e-12 * np.abs(want).max()
+    assert np.allclose(got - n0, delta, rtol=0, atol=1e-15 * np.abs(n0).max())
+
+
+def test_bdf2_reaches_the_equilibrium_at_huge_dt(transport_only):
+    prob, n0, L = transport_only
+    dt = 1e14
+    eq = expm(dt * L) @ n0.ravel()
+    n1, _ = integrate.bdf2_step(prob, n0, n0, dt)
+    n2, _ = integrate.bdf2_step(prob, n1, n0, dt)
+    assert np.abs(n2.ravel() - eq).max() <= 1e-6 * np.abs(eq).max()
+
+
+def test_bdf2_is_second_order_on_the_chemistry():
+    net, col = synth.make_config(1)
+    prob = integrate.Problem(net, col)
+    N, S = col.n0.shape
+    T = 1e-6
+    ref = solve_ivp(lambda t, y: prob.rhs(y.reshape(N, S)).ravel(), (0.0, T),
+                    col.n0.ravel(), method="Radau", rtol=1e-12, atol=1e-16)
+    yT = ref.y[:, -1]
+
+    def err(m):
+        h = T / m
+        prev = col.n0
+        n, _ = integrate.be_step(prob, prev, h)   # one O(h^2) starting step
+        for _ in range(m - 1):
+            n, prev = integrate.bdf2_step(prob, n, prev, h)[0], n
+        return np.abs(n.ravel() - yT).max() / np.abs(yT).max()
+
+    e = [err(m) for m in (8, 16, 32)]
+    assert 3.8 < e[0] / e[1] < 4.2 and 3.8 < e[1] / e[2] < 4.2
