@@ -501,6 +501,24 @@ def main():
         except xod.XodError as e:
             ros2 = {"error": str(e)}
 
+    # constant-step BDF2 (history: the previous step's starting state)
+    bdf2 = None
+    if args.solver == "cr":
+        try:
+            xod.xod_step(gcol, args.dt)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                xod.xod_step_bdf2(gcol, args.dt)
+            torch.cuda.synchronize()
+            el_b = (time.perf_counter() - t0) / args.steps
+            bdf2 = {"value": 1.0 / el_b, "unit": "steps/s", "ms_per_step": 1e3 * el_b,
+                    "what": "xod_step_bdf2: linearly implicit constant-step BDF2 (rates, F "
+                            "with the history term, Jacobian, factorisation, solve, update)"}
+            progress(f"BDF2 steps: {1.0 / el_b:.2f} steps/s")
+        except xod.XodError as e:
+            bdf2 = {"error": str(e)}
+
     steps_per_s = args.steps / el
     line = {
         "metric": "implicit steps/sec at 594 sp x 150 layers (FP64)",
@@ -525,6 +543,7 @@ def main():
         "roofline_schur_gemm_other_path": gemm_alt,
         "frozen_matrix_steps": frozen,
         "ros2_steps": ros2,
+        "bdf2_steps": bdf2,
         "kernels": kern,
         "ms_per_step_with_kernel_events": 1e3 * el_prof / args.steps,
     }

@@ -258,6 +258,20 @@ xod_status xod_step_frozen(xod_column *col, double dt, xod_step_stats *st);
  * (resid_inf, refine_iters 0); XOD_ENONFINITE leaves the state unchanged. */
 xod_status xod_step_ros2(xod_column *col, double dt, xod_step_stats *st);
 
+/* One step of the second-order backward differentiation formula BDF2 at
+ * constant step (the BDF family of the DLSODES solver Section 2.1 names),
+ * linearised about the current state n (one Newton iteration from n):
+ *   n_new - 4/3 n + 1/3 n_prev = 2/3 dt F(n_new)  becomes, with h = 2dt/3,
+ *   (I/h - J(n)) Delta = F(n) + (n - n_prev)/(2 dt),  n <- n + Delta.
+ * n_prev is the state the previous step started from; that step must be a
+ * completed xod_step, xod_step_frozen, xod_step_ros2 or xod_step_bdf2 of
+ * the same dt on this column (XOD_EINVAL otherwise: after creation,
+ * xod_column_set_state, a failed step, a batch step or the steady-state
+ * driver).  FP64 and mixed columns (the mixed solve refines against the
+ * same right-hand side).  Leaves the factorisation of h held.  st as for
+ * xod_step. */
+xod_status xod_step_bdf2(xod_column *col, double dt, xod_step_stats *st);
+
 /* Adaptive driver to steady state.
  *   reject (dt /= 2) if the step is not finite or a species whose mixing
  *   ratio exceeded y_sig turns negative; accept otherwise, clip negatives to

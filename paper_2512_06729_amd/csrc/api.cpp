@@ -506,6 +506,7 @@ extern "C" xod_status xod_column_set_state(xod_column *col, const double *n, dou
   XOD_HIP(hipStreamSynchronize(col->stream));
   col->t = t;
   col->dt = dt;
+  col->prev_dt = 0.0;
   return XOD_OK;
 }
 
@@ -805,7 +806,8 @@ xod_status run_update(xod_column *c, bool clip, double y_floor, double y_sig, do
   return XOD_OK;
 }
 
-xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, double *resid) {
+xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, double *resid,
+                         const double *hist, double hist_coef) {
   c->dt = dt;
   ColArgs a = c->args();
   OneCol one{a};
@@ -815,6 +817,11 @@ xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, do
   XOD_TRY(enqueue_photolysis(c));
   XOD_HIP(launch_rates(one, 1, c->N, c->R, c->stream));
   XOD_HIP(launch_rhs(one, 1, c->N, c->R, c->S, c->stream));
+  if (hist) {
+    const size_t NS = (size_t)c->N * c->S;
+    XOD_HIP(launch_lincomb(c->dx, c->n, 1.0, hist, -1.0, NS, c->stream));
+    XOD_HIP(launch_lincomb(c->f, c->f, 1.0, c->dx, hist_coef, NS, c->stream));
+  }
   const bool cr = c->solver == XOD_SOLVER_CR;
   c->fact_dt = 0.0;
   if (c->prec == XOD_FP64) {
@@ -900,6 +907,7 @@ extern "C" xod_status xod_step(xod_column *col, double dt, xod_step_stats *st) {
   double res;
   XOD_TRY(enqueue_solve(col, dt, &iters, &fb, &res));
   double s[kStatLen];
+  col->prev_dt = 0.0;   // ntmp is about to receive the new state
   XOD_TRY(run_update(col, false, 1e-30, 1e-10, s));
   XOD_TRY(check_flags(col, s + kNStat));
   if (st) {
@@ -917,6 +925,7 @@ extern "C" xod_status xod_step(xod_column *col, double dt, xod_step_stats *st) {
   std::swap(col->n, col->ntmp);
   col->t += dt;
   col->dt = dt;
+  col->prev_dt = dt;
   return XOD_OK;
 }
 
@@ -938,6 +947,7 @@ extern "C" xod_status xod_step_frozen(xod_column *col, double dt, xod_step_stats
   else
     XOD_HIP(launch_solve_fp64(one, 1, col->N, col->ld, col->stream));
   double s[kStatLen];
+  col->prev_dt = 0.0;   // ntmp is about to receive the new state
   XOD_TRY(run_update(col, false, 1e-30, 1e-10, s));
   XOD_TRY(check_flags(col, s + kNStat));
   if (st) {
@@ -954,6 +964,7 @@ extern "C" xod_status xod_step_frozen(xod_column *col, double dt, xod_step_stats
   }
   std::swap(col->n, col->ntmp);
   col->t += dt;
+  col->prev_dt = dt;
   return XOD_OK;
 }
 
@@ -974,6 +985,7 @@ extern "C" xod_status xod_step_ros2(xod_column *col, double dt, xod_step_stats *
   const size_t NS = (size_t)col->N * col->S;
   XOD_HIP(hipMemcpyAsync(col->dx, col->x, NS * sizeof(double), hipMemcpyDeviceToDevice,
                          col->stream));
+  col->prev_dt = 0.0;   // the stage state goes to ntmp
   XOD_HIP(launch_lincomb(col->ntmp, col->n, 1.0, col->x, 1.0 / g, NS, col->stream));
   ColArgs a = col->args();
   a.n = col->ntmp;
@@ -985,6 +997,7 @@ extern "C" xod_status xod_step_ros2(xod_column *col, double dt, xod_step_stats *
     XOD_HIP(launch_solve_fp64(OneCol{col->args()}, 1, col->N, col->ld, col->stream));  // x = d2
   XOD_HIP(launch_lincomb(col->x, col->dx, 1.5 / g, col->x, 0.5 / g, NS, col->stream));
   double s[kStatLen];
+  col->prev_dt = 0.0;   // ntmp is about to receive the new state
   XOD_TRY(run_update(col, false, 1e-30, 1e-10, s));
   XOD_TRY(check_flags(col, s + kNStat));
   if (st) {
@@ -1002,6 +1015,43 @@ extern "C" xod_status xod_step_ros2(xod_column *col, double dt, xod_step_stats *
   std::swap(col->n, col->ntmp);
   col->t += dt;
   col->dt = dt;
+  col->prev_dt = dt;
+  return XOD_OK;
+}
+
+// Linearly implicit constant-step BDF2: with h = 2 dt/3,
+//   (I/h - J(n)) Delta = F(n) + (n - n_prev) / (2 dt),   n <- n + Delta,
+// n_prev being the starting state of the previous step, which the state
+// swap leaves in ntmp.
+extern "C" xod_status xod_step_bdf2(xod_column *col, double dt, xod_step_stats *st) {
+  XOD_CHECK(col, "xod_step_bdf2: null column");
+  XOD_CHECK(!col->in_batch, "xod_step_bdf2: column belongs to a batch");
+  XOD_CHECK(std::isfinite(dt) && dt > 0, "xod_step_bdf2: dt must be > 0");
+  XOD_CHECK(col->prev_dt > 0 && dt == col->prev_dt,
+            "xod_step_bdf2: the previous step must be a completed step of the same dt");
+  int iters, fb;
+  double res;
+  XOD_TRY(enqueue_solve(col, 2.0 * dt / 3.0, &iters, &fb, &res, col->ntmp, 0.5 / dt));
+  double s[kStatLen];
+  col->prev_dt = 0.0;   // ntmp is about to receive the new state
+  XOD_TRY(run_update(col, false, 1e-30, 1e-10, s));
+  XOD_TRY(check_flags(col, s + kNStat));
+  if (st) {
+    st->max_rel_change = s[0];
+    st->min_ratio = s[1];
+    st->resid_inf = res;
+    st->refine_iters = iters;
+    st->fp64_fallback = fb;
+    st->nonfinite = s[5] > 0 ? 1 : 0;
+  }
+  if (s[5] > 0) {
+    set_error("xod_step_bdf2: non-finite state after the step");
+    return XOD_ENONFINITE;
+  }
+  std::swap(col->n, col->ntmp);
+  col->t += dt;
+  col->dt = dt;
+  col->prev_dt = dt;
   return XOD_OK;
 }
 
@@ -1021,6 +1071,7 @@ extern "C" xod_status xod_integrate_to_steady_state(xod_column *col, const xod_s
     if (o->max_consec_rejects > 0) maxrej = o->max_consec_rejects;
     mixrule = o->use_mix_rule;
   }
+  col->prev_dt = 0.0;   // rejected steps leave their output in ntmp
   const double mix = mixrule ? col->mix_time : 0.0;
   double t = 0.0, dt = dt0, clipped = 0.0;
   int64_t steps = 0, rejects = 0;
@@ -1054,6 +1105,7 @@ extern "C" xod_status xod_integrate_to_steady_state(xod_column *col, const xod_s
   }
   col->t = t;
   col->dt = dt;
+  col->prev_dt = 0.0;
   res->t = t;
   res->dt = dt;
   res->clipped = clipped;

@@ -327,6 +327,7 @@ extern "C" xod_status xod_batch_step(xod_batch *b, const double *dts, xod_step_s
     }
     std::swap(c->n, c->ntmp);
     c->t += c->dt;
+    c->prev_dt = 0.0;
   }
   return ret;
 }

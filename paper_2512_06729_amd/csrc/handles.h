@@ -76,6 +76,7 @@ struct xod_column {
   RedArgs *red_dev = nullptr, *red_host = nullptr;
   double t = 0.0, dt = 0.0;
   double fact_dt = 0.0;   // dt of the FP64 factorisation held in the blocks (0: none)
+  double prev_dt = 0.0;   // dt of the step whose starting state ntmp holds (0: none)
   bool in_batch = false;
   xod_solver solver = XOD_SOLVER_THOMAS;
   xod::CrPlan<double> *cr64 = nullptr;   // block cyclic reduction (FP64 column)
@@ -150,7 +151,10 @@ struct xod_column {
 namespace xod {
 // Enqueue rates + rhs + Jacobian + factor + solve of one column (FP64, or
 // mixed with refinement and FP64 fallback); delta ends in col->x.
-xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, double *resid);
+// hist != null adds hist_coef (n - hist) to the right-hand side (a
+// multistep history term) before the factorisation's solve.
+xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, double *resid,
+                         const double *hist = nullptr, double hist_coef = 0.0);
 // n_new = n + delta into col->ntmp plus statistics (host copy, kStatLen).
 xod_status run_update(xod_column *c, bool clip, double y_floor, double y_sig, double *out);
 // The same, enqueued only: the statistics land in c->stats_host once the

@@ -1,0 +1,70 @@
+"""GPU parity of the constant-step BDF2 step (xod_step_bdf2) against the
+oracle's bdf2_step: a backward-Euler starting step, then BDF2 steps whose
+history is the state the previous step started from, for block Thomas,
+cyclic reduction and mixed precision; per-layer tolerance as for the
+other solve tests.  Also the history bookkeeping: which calls leave a
+usable starting state and which drop it."""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import synth  # noqa: E402
+from oracle import integrate  # noqa: E402
+from tests import gpu_common as G  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    import paper_2512_06729_amd  # noqa: F401  (fails loudly if not built)
+
+
+@pytest.mark.parametrize("solver,cfg,dt,prec", [(0, 1, 1e-6, 0), (1, 1, 1e-6, 0),
+                                                (0, 2, 1e-6, 0), (1, 2, 1e-6, 0),
+                                                (1, 3, 1e-8, 0), (0, 1, 1e-3, 0),
+                                                (1, 1, 1e-3, 0), (1, 2, 1e-6, 1)])
+def test_bdf2_steps_match_oracle(solver, cfg, dt, prec):
+    import paper_2512_06729_amd as xod
+    print(f"bdf2 solver={solver} config {cfg} dt={dt} precision={prec}", flush=True)
+    net, col = synth.make_config(cfg)
+    prob, gnet, gcol = G.make_pair(net, col, precision=prec)
+    gcol.set_solver(solver)
+    rel = 1e-9 if prec == 0 else 1e-8
+    n1, d1 = integrate.be_step(prob, col.n0, dt)
+    xod.xod_step(gcol, dt)
+    G.assert_state_agrees(gcol.state(), n1, d1, rel=rel)
+    prev, n = col.n0, n1
+    for _ in range(2 if cfg == 3 else 3):
+        ref, delta = integrate.bdf2_step(prob, n, prev, dt)
+        xod.xod_step_bdf2(gcol, dt)
+        G.assert_state_agrees(gcol.state(), ref, delta, rel=rel)
+        prev, n = n, ref
+
+
+def test_bdf2_history_bookkeeping():
+    import paper_2512_06729_amd as xod
+    net, col = synth.make_config(1)
+    prob, gnet, gcol = G.make_pair(net, col)
+    dt = 1e-6
+
+    def refused():
+        with pytest.raises(xod.XodError) as e:
+            xod.xod_step_bdf2(gcol, dt)
+        assert e.value.status == xod.XOD_EINVAL
+
+    refused()                                # nothing before it
+    xod.xod_step(gcol, 2 * dt)
+    refused()                                # a step of another dt
+    n1 = gcol.state()
+    xod.xod_step_ros2(gcol, dt)              # any completed step of this dt
+    n2 = gcol.state()
+    ref, delta = integrate.bdf2_step(prob, n2, n1, dt)
+    xod.xod_step_bdf2(gcol, dt)
+    G.assert_state_agrees(gcol.state(), ref, delta, rel=1e-9)
+    gcol.set_state(gcol.state())
+    refused()                                # the state was replaced
