@@ -144,3 +144,24 @@ def test_closing_the_ends_restores_the_closed_column():
         assert e.value.status == xod.XOD_EINVAL
     # a rejected call changed nothing
     np.testing.assert_array_equal(gpu_rhs(gcol, kf, kr, col.n0), f0)
+
+
+@pytest.mark.parametrize("solver", [0, 1])
+def test_single_layer_column_with_both_ends_open(solver):
+    """N = 1: the one layer is both the bottom and the top, so it takes the
+    deposition, emission and escape terms together."""
+    import paper_2512_06729_amd as xod
+    net = synth.make_network("c2", seed=1002)
+    col = synth.with_boundary(net, synth.make_column("c2", net, seed=31, N=1), seed=5)
+    prob, gnet, gcol = G.make_pair(net, col)
+    gcol.set_solver(solver)
+    g = prob.grid
+    assert (g.v_top > 0).any() and (g.v_dep > 0).any() and (g.phi_surf > 0).any()
+    kf, kr = G.gpu_rates(gcol)
+    f = gpu_rhs(gcol, kf, kr, col.n0)
+    scale = _rhs_scale(prob, col.n0)
+    scale[0] += np.abs(g.phi_surf) / g.dz[0]
+    assert np.all(np.abs(f - prob.rhs(col.n0)) <= 1e-12 * scale + 1e-300)
+    ref, delta = integrate.be_step(prob, col.n0, 1e-4)
+    xod.xod_step(gcol, 1e-4)
+    G.assert_state_agrees(gcol.state(), ref, delta, rel=1e-9)
