@@ -272,7 +272,8 @@ xod_status xod_step_ros2(xod_column *col, double dt, xod_step_stats *st);
  * xod_step. */
 xod_status xod_step_bdf2(xod_column *col, double dt, xod_step_stats *st);
 
-/* Adaptive driver to steady state.
+/* Adaptive driver to steady state; each step is a backward-Euler step, or
+ * with method 1 a ROS2 step (xod_step_ros2), under the same control:
  *   reject (dt /= 2) if the step is not finite or a species whose mixing
  *   ratio exceeded y_sig turns negative; accept otherwise, clip negatives to
  *   zero and set dt *= 2 / 1.2 / 0.7 for a control change c < 0.5 / < 0.9 /
@@ -289,7 +290,7 @@ typedef struct {
   int32_t max_steps; /* [5000]  */
   int32_t max_consec_rejects; /* [30] */
   int32_t use_mix_rule;       /* 0/1 [1 if the struct is NULL] */
-  int32_t pad_;
+  int32_t method;             /* 0 backward Euler [0], 1 ROS2 (FP64 columns) */
 } xod_ss_opts;
 typedef struct {
   double t, dt, clipped;
@@ -457,9 +458,10 @@ xod_status xod_serve_set_solver(xod_server *srv, xod_solver solver);
 xod_status xod_serve_footprint(const xod_network *net, int32_t N,
                                xod_precision prec, size_t *bytes);
 /* Queue a steady-state solve (host arrays copied; opts as for
- * xod_integrate_to_steady_state, NULL = defaults).  Never blocks: a request
+ * xod_integrate_to_steady_state, NULL = defaults; requests are stepped with
+ * backward Euler, so opts->method must be 0).  Never blocks: a request
  * waits in the queue until a slot and memory are free.  XOD_EINVAL if the
- * request could never fit the budget. */
+ * request could never fit the budget or asks for another method. */
 xod_status xod_serve_submit(xod_server *srv, const xod_network *net,
                             const xod_profile *prof, const double *n0,
                             const xod_ss_opts *opts, uint64_t *req_id);

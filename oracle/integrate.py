@@ -148,8 +148,9 @@ class SteadyResult:
 
 def steady_state(prob, n0, tol_rel=1.0e-4, y_floor=1.0e-30, y_sig=1.0e-10,
                  t_end=1.0e12, dt0=1.0e-8, max_steps=5000,
-                 max_consec_rejects=30, use_mix_rule=True):
-    """Adaptive backward-Euler driver to steady state.
+                 max_consec_rejects=30, use_mix_rule=True, method="be"):
+    """Adaptive driver to steady state; each step is a backward-Euler step
+    (method "be") or a ROS2 step (method "ros2"), with the same control.
 
     * Reject a step (dt <- dt/2) if it is not finite or if a species whose
       mixing ratio exceeded y_sig turns negative; after more than
@@ -173,8 +174,9 @@ def steady_state(prob, n0, tol_rel=1.0e-4, y_floor=1.0e-30, y_sig=1.0e-10,
     clipped = 0.0
     hist = []
     converged = False
+    step = {"be": be_step, "ros2": ros2_step}[method]
     while steps < max_steps:
-        n_new, delta = be_step(prob, n, dt)
+        n_new, delta = step(prob, n, dt)
         sig = n > y_sig * ngas
         if not np.all(np.isfinite(n_new)) or np.any(sig & (n_new < 0.0)):
             rejects += 1

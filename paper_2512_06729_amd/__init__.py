@@ -83,7 +83,7 @@ class SSOpts(ctypes.Structure):
     _fields_ = [("tol_rel", c_double), ("y_floor", c_double), ("y_sig", c_double),
                 ("t_end", c_double), ("dt0", c_double), ("max_steps", c_int32),
                 ("max_consec_rejects", c_int32), ("use_mix_rule", c_int32),
-                ("pad_", c_int32)]
+                ("method", c_int32)]
 
 
 class SSResult(ctypes.Structure):
@@ -441,9 +441,10 @@ def xod_step_bdf2(col, dt):
 
 def xod_integrate_to_steady_state(col, tol_rel=0.0, y_floor=0.0, y_sig=0.0, t_end=0.0,
                                   dt0=0.0, max_steps=0, max_consec_rejects=0,
-                                  use_mix_rule=1, check=True):
+                                  use_mix_rule=1, check=True, method=0):
+    """method 0: backward-Euler steps, 1: ROS2 steps (FP64 columns)."""
     o = SSOpts(tol_rel, y_floor, y_sig, t_end, dt0, max_steps, max_consec_rejects,
-               use_mix_rule, 0)
+               use_mix_rule, method)
     r = SSResult()
     st = _f["xod_integrate_to_steady_state"](col.handle, ctypes.byref(o), ctypes.byref(r))
     if check and st not in (XOD_OK,):

@@ -973,11 +973,8 @@ extern "C" xod_status xod_step_frozen(xod_column *col, double dt, xod_step_stats
 //   M d1 = F(n),   M d2 = F(n + d1/g) - 2 d1/(g dt),   n_new = n + (3 d1 + d2)/(2g).
 // The stage state lives in ntmp (the update writes it only afterwards) and
 // d1 in dx (used by the mixed-precision refinement only).
-extern "C" xod_status xod_step_ros2(xod_column *col, double dt, xod_step_stats *st) {
-  XOD_CHECK(col, "xod_step_ros2: null column");
-  XOD_CHECK(!col->in_batch, "xod_step_ros2: column belongs to a batch");
-  XOD_CHECK(col->prec == XOD_FP64, "xod_step_ros2: FP64 columns only");
-  XOD_CHECK(std::isfinite(dt) && dt > 0, "xod_step_ros2: dt must be > 0");
+// x = the ROS2 increment (3 d1 + d2)/(2g) of the column's state (FP64).
+static xod_status enqueue_ros2(xod_column *col, double dt) {
   const double g = 1.0 + 1.0 / std::sqrt(2.0);
   int iters, fb;
   double res;
@@ -996,6 +993,15 @@ extern "C" xod_status xod_step_ros2(xod_column *col, double dt, xod_step_stats *
   else
     XOD_HIP(launch_solve_fp64(OneCol{col->args()}, 1, col->N, col->ld, col->stream));  // x = d2
   XOD_HIP(launch_lincomb(col->x, col->dx, 1.5 / g, col->x, 0.5 / g, NS, col->stream));
+  return XOD_OK;
+}
+
+extern "C" xod_status xod_step_ros2(xod_column *col, double dt, xod_step_stats *st) {
+  XOD_CHECK(col, "xod_step_ros2: null column");
+  XOD_CHECK(!col->in_batch, "xod_step_ros2: column belongs to a batch");
+  XOD_CHECK(col->prec == XOD_FP64, "xod_step_ros2: FP64 columns only");
+  XOD_CHECK(std::isfinite(dt) && dt > 0, "xod_step_ros2: dt must be > 0");
+  XOD_TRY(enqueue_ros2(col, dt));
   double s[kStatLen];
   col->prev_dt = 0.0;   // ntmp is about to receive the new state
   XOD_TRY(run_update(col, false, 1e-30, 1e-10, s));
@@ -1060,8 +1066,13 @@ extern "C" xod_status xod_integrate_to_steady_state(xod_column *col, const xod_s
   XOD_CHECK(col && res, "xod_integrate_to_steady_state: null argument");
   XOD_CHECK(!col->in_batch, "xod_integrate_to_steady_state: column belongs to a batch");
   double tol = 1e-4, yfl = 1e-30, ysig = 1e-10, tend = 1e12, dt0 = 1e-8;
-  int maxs = 5000, maxrej = 30, mixrule = 1;
+  int maxs = 5000, maxrej = 30, mixrule = 1, method = 0;
   if (o) {
+    XOD_CHECK(o->method == 0 || o->method == 1,
+              "xod_integrate_to_steady_state: method must be 0 (backward Euler) or 1 (ROS2)");
+    XOD_CHECK(o->method == 0 || col->prec == XOD_FP64,
+              "xod_integrate_to_steady_state: ROS2 needs an FP64 column");
+    method = o->method;
     if (o->tol_rel > 0) tol = o->tol_rel;
     if (o->y_floor > 0) yfl = o->y_floor;
     if (o->y_sig > 0) ysig = o->y_sig;
@@ -1080,7 +1091,10 @@ extern "C" xod_status xod_integrate_to_steady_state(xod_column *col, const xod_s
   while (steps < maxs) {
     int iters, fb;
     double rr;
-    XOD_TRY(enqueue_solve(col, dt, &iters, &fb, &rr));
+    if (method == 1)
+      XOD_TRY(enqueue_ros2(col, dt));
+    else
+      XOD_TRY(enqueue_solve(col, dt, &iters, &fb, &rr));
     double s[kStatLen];
     XOD_TRY(run_update(col, true, yfl, ysig, s));
     const bool singular = s[kNStat] >= 0;

@@ -145,6 +145,8 @@ extern "C" xod_status xod_serve_submit(xod_server *s, const xod_network *net,
                                        const xod_ss_opts *o, uint64_t *req_id) {
   SCHECK(s && net && p && n0 && req_id, "xod_serve_submit: null argument");
   SCHECK(p->N >= 1, "xod_serve_submit: N must be >= 1");
+  SCHECK(!o || o->method == 0, "xod_serve_submit: requests are stepped with backward Euler "
+                               "(method 0)");
   Req r;
   r.id = s->next_id++;
   r.net = net;

@@ -141,3 +141,16 @@ def test_bdf2_is_second_order_on_the_chemistry():
 
     e = [err(m) for m in (8, 16, 32)]
     assert 3.8 < e[0] / e[1] < 4.2 and 3.8 < e[1] / e[2] < 4.2
+
+
+def test_backward_euler_and_ros2_drivers_reach_the_same_steady_state():
+    """The steady state is the fixed point F(n) = 0 (of the clipped
+    iteration), whichever step the driver takes to reach it."""
+    net, col = synth.make_config(1)
+    prob = integrate.Problem(net, col)
+    kw = dict(tol_rel=1e-13, t_end=1e30, max_steps=4000)
+    a = integrate.steady_state(prob, col.n0, **kw)
+    b = integrate.steady_state(prob, col.n0, method="ros2", **kw)
+    assert a.converged and b.converged
+    keep = a.n > 1e-30 * prob.grid.ngas[:, None]
+    assert np.max(np.abs(a.n - b.n)[keep] / a.n[keep]) < 1e-7
