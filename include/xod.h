@@ -459,7 +459,8 @@ xod_status xod_serve_footprint(const xod_network *net, int32_t N,
                                xod_precision prec, size_t *bytes);
 /* Queue a steady-state solve (host arrays copied; opts as for
  * xod_integrate_to_steady_state, NULL = defaults; requests are stepped with
- * backward Euler, so opts->method must be 0).  Never blocks: a request
+ * backward Euler, so opts->method must be 0; the columns are closed: no
+ * boundary exchange, gray photolysis).  Never blocks: a request
  * waits in the queue until a slot and memory are free.  XOD_EINVAL if the
  * request could never fit the budget or asks for another method. */
 xod_status xod_serve_submit(xod_server *srv, const xod_network *net,

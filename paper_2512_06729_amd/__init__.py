@@ -522,6 +522,9 @@ class Server:
 
     def submit(self, network, col, tol_rel=0.0, y_floor=0.0, y_sig=0.0, t_end=0.0, dt0=0.0,
                max_steps=0, max_consec_rejects=0, use_mix_rule=1):
+        if any(getattr(col, k, None) is not None
+               for k in ("escape_diff_limited", "v_top", "v_dep", "phi_surf")):
+            raise ValueError("served requests are closed columns (no boundary exchange)")
         N = int(np.asarray(col.P_bar).shape[0])
         prof, keep = _profile_struct(col, N)
         n0 = np.ascontiguousarray(col.n0, np.float64)
