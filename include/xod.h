@@ -258,6 +258,18 @@ xod_status xod_step_frozen(xod_column *col, double dt, xod_step_stats *st);
  * (resid_inf, refine_iters 0); XOD_ENONFINITE leaves the state unchanged. */
 xod_status xod_step_ros2(xod_column *col, double dt, xod_step_stats *st);
 
+/* One backward-Euler step solved by modified Newton (the corrector of the
+ * DLSODES family Section 2.1 names): the linearised step Delta = M^-1 F(n),
+ * M = I/dt - J(n), then iters - 1 corrections reusing M's factorisation,
+ *   Delta += M^-1 (F(n + Delta) - Delta/dt),
+ * toward the solution of n1 - n - dt F(n1) = 0.  iters = 1 is xod_step.
+ * The corrections converge only while the stale M is close enough (small
+ * dt or near steady state): there is no convergence test, and a diverging
+ * iteration ends in XOD_ENONFINITE with the state unchanged.  FP64 columns,
+ * iters in 1..64 (XOD_EINVAL otherwise).  st as for xod_step, refine_iters
+ * = iters - 1.  Leaves the factorisation of dt held. */
+xod_status xod_step_newton(xod_column *col, double dt, int32_t iters, xod_step_stats *st);
+
 /* One step of the second-order backward differentiation formula BDF2 at
  * constant step (the BDF family of the DLSODES solver Section 2.1 names),
  * linearised about the current state n (one Newton iteration from n):

@@ -126,6 +126,8 @@ _f = {
     "xod_step_frozen": _sig("xod_step_frozen", c_void_p, c_double, ctypes.POINTER(StepStats)),
     "xod_step_ros2": _sig("xod_step_ros2", c_void_p, c_double, ctypes.POINTER(StepStats)),
     "xod_step_bdf2": _sig("xod_step_bdf2", c_void_p, c_double, ctypes.POINTER(StepStats)),
+    "xod_step_newton": _sig("xod_step_newton", c_void_p, c_double, c_int32,
+                            ctypes.POINTER(StepStats)),
     "xod_column_set_boundary": _sig("xod_column_set_boundary", c_void_p,
                                     ctypes.POINTER(Boundary)),
     "xod_integrate_to_steady_state": _sig("xod_integrate_to_steady_state", c_void_p,
@@ -429,6 +431,13 @@ def xod_step_ros2(col, dt):
     """One two-stage Rosenbrock (ROS2) step: one factorisation, two solves."""
     st = StepStats()
     _check(_f["xod_step_ros2"](col.handle, float(dt), ctypes.byref(st)))
+    return st.as_dict()
+
+
+def xod_step_newton(col, dt, iters):
+    """Backward Euler by modified Newton: iters - 1 corrections on one factorisation."""
+    st = StepStats()
+    _check(_f["xod_step_newton"](col.handle, float(dt), int(iters), ctypes.byref(st)))
     return st.as_dict()
 
 

@@ -1025,6 +1025,58 @@ extern "C" xod_status xod_step_ros2(xod_column *col, double dt, xod_step_stats *
   return XOD_OK;
 }
 
+// Backward Euler solved by modified Newton: the linearised step, then
+// iters - 1 corrections with the same factorisation,
+//   M delta = F(n + Delta) - Delta/dt,  Delta += delta,  M = I/dt - J(n).
+// Delta is kept in dx, the corrected state n + Delta goes to ntmp.
+extern "C" xod_status xod_step_newton(xod_column *col, double dt, int32_t iters,
+                                      xod_step_stats *st) {
+  XOD_CHECK(col, "xod_step_newton: null column");
+  XOD_CHECK(!col->in_batch, "xod_step_newton: column belongs to a batch");
+  XOD_CHECK(col->prec == XOD_FP64, "xod_step_newton: FP64 columns only");
+  XOD_CHECK(std::isfinite(dt) && dt > 0, "xod_step_newton: dt must be > 0");
+  XOD_CHECK(iters >= 1 && iters <= 64, "xod_step_newton: iters must be in 1..64");
+  int it0, fb;
+  double res;
+  XOD_TRY(enqueue_solve(col, dt, &it0, &fb, &res));          // x = Delta
+  const size_t NS = (size_t)col->N * col->S;
+  col->prev_dt = 0.0;   // corrected states go to ntmp
+  for (int it = 1; it < iters; ++it) {
+    XOD_HIP(hipMemcpyAsync(col->dx, col->x, NS * sizeof(double), hipMemcpyDeviceToDevice,
+                           col->stream));
+    XOD_HIP(launch_lincomb(col->ntmp, col->n, 1.0, col->dx, 1.0, NS, col->stream));
+    ColArgs a = col->args();
+    a.n = col->ntmp;
+    XOD_HIP(launch_rhs(OneCol{a}, 1, col->N, col->R, col->S, col->stream));
+    XOD_HIP(launch_lincomb(col->x, col->f, 1.0, col->dx, -1.0 / dt, NS, col->stream));
+    if (col->solver == XOD_SOLVER_CR)
+      XOD_TRY(col->cr64->solve(col));
+    else
+      XOD_HIP(launch_solve_fp64(OneCol{col->args()}, 1, col->N, col->ld, col->stream));
+    XOD_HIP(launch_lincomb(col->x, col->dx, 1.0, col->x, 1.0, NS, col->stream));
+  }
+  double s[kStatLen];
+  XOD_TRY(run_update(col, false, 1e-30, 1e-10, s));
+  XOD_TRY(check_flags(col, s + kNStat));
+  if (st) {
+    st->max_rel_change = s[0];
+    st->min_ratio = s[1];
+    st->resid_inf = 0.0;
+    st->refine_iters = iters - 1;
+    st->fp64_fallback = 0;
+    st->nonfinite = s[5] > 0 ? 1 : 0;
+  }
+  if (s[5] > 0) {
+    set_error("xod_step_newton: non-finite state after the step");
+    return XOD_ENONFINITE;
+  }
+  std::swap(col->n, col->ntmp);
+  col->t += dt;
+  col->dt = dt;
+  col->prev_dt = dt;
+  return XOD_OK;
+}
+
 // Linearly implicit constant-step BDF2: with h = 2 dt/3,
 //   (I/h - J(n)) Delta = F(n) + (n - n_prev) / (2 dt),   n <- n + Delta,
 // n_prev being the starting state of the previous step, which the state

@@ -75,6 +75,7 @@ def test_null_arguments_are_einval():
     assert xod._f["xod_step_frozen"](None, 1.0, None) == xod.XOD_EINVAL
     assert xod._f["xod_step_ros2"](None, 1.0, None) == xod.XOD_EINVAL
     assert xod._f["xod_step_bdf2"](None, 1.0, None) == xod.XOD_EINVAL
+    assert xod._f["xod_step_newton"](None, 1.0, 2, None) == xod.XOD_EINVAL
     assert xod._f["xod_column_set_boundary"](None, None) == xod.XOD_EINVAL
     assert xod._f["xod_column_destroy"](None) == xod.XOD_EINVAL
     assert xod._f["xod_set_option"](b"nope", 1) == xod.XOD_EINVAL

@@ -68,3 +68,21 @@ def test_bdf2_history_bookkeeping():
     G.assert_state_agrees(gcol.state(), ref, delta, rel=1e-9)
     gcol.set_state(gcol.state())
     refused()                                # the state was replaced
+
+
+@pytest.mark.parametrize("solver,cfg,dt,iters", [(0, 1, 1e-6, 2), (1, 1, 1e-5, 4),
+                                                 (0, 2, 1e-6, 3), (1, 2, 1e-6, 5),
+                                                 (1, 3, 1e-8, 3)])
+def test_modified_newton_step_matches_oracle(solver, cfg, dt, iters):
+    import paper_2512_06729_amd as xod
+    print(f"newton solver={solver} config {cfg} dt={dt} iters={iters}", flush=True)
+    net, col = synth.make_config(cfg)
+    prob, gnet, gcol = G.make_pair(net, col)
+    gcol.set_solver(solver)
+    ref, delta = integrate.be_step(prob, col.n0, dt, newton_iters=iters)
+    st = xod.xod_step_newton(gcol, dt, iters)
+    assert st["refine_iters"] == iters - 1
+    G.assert_state_agrees(gcol.state(), ref, delta, rel=1e-9)
+    with pytest.raises(xod.XodError) as e:
+        xod.xod_step_newton(gcol, dt, 0)
+    assert e.value.status == xod.XOD_EINVAL
