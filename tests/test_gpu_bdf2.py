@@ -86,3 +86,24 @@ def test_modified_newton_step_matches_oracle(solver, cfg, dt, iters):
     with pytest.raises(xod.XodError) as e:
         xod.xod_step_newton(gcol, dt, 0)
     assert e.value.status == xod.XOD_EINVAL
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 17])
+@pytest.mark.parametrize("solver", [0, 1])
+def test_second_order_steps_on_ragged_columns(N, solver):
+    """ROS2 and BDF2 on short and odd columns (cyclic reduction's ragged
+    levels and the single-block root), each step from the oracle's state."""
+    import paper_2512_06729_amd as xod
+    print(f"ragged second-order N={N} solver={solver}", flush=True)
+    net = synth.make_network("c1", seed=1001)
+    col = synth.make_column("c1", net, seed=400 + N, N=N)
+    prob, gnet, gcol = G.make_pair(net, col)
+    gcol.set_solver(solver)
+    dt = 1e-6
+    r1, d1, (t1, t2) = integrate.ros2_step(prob, col.n0, dt, stages=True)
+    xod.xod_step_ros2(gcol, dt)
+    scale = np.maximum(np.maximum(np.abs(t1), np.abs(t2)), np.abs(d1))
+    G.assert_state_agrees(gcol.state(), r1, scale, rel=1e-9)
+    r2, d2 = integrate.bdf2_step(prob, r1, col.n0, dt)
+    xod.xod_step_bdf2(gcol, dt)
+    G.assert_state_agrees(gcol.state(), r2, d2, rel=1e-9)
