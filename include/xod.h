@@ -241,9 +241,11 @@ xod_status xod_step(xod_column *col, double dt, xod_step_stats *stats);
  * state n_f it started from, at the current state n, then n <- n + Delta.
  * Rates and F are those of n (spectral photolysis too).  Costs the rates,
  * F, the solve and the update, no Jacobian and no factorisation.  FP64
- * columns; dt must equal the dt of that xod_step (XOD_EINVAL otherwise, or
- * when no factorisation is held: after creation, a solver switch or a
- * mixed-precision step).  st as for xod_step (resid_inf, refine_iters 0). */
+ * columns; dt must equal the dt of that factorisation (XOD_EINVAL
+ * otherwise, or when no factorisation is held: after creation, a solver
+ * switch, a boundary change or a mixed-precision step).  The factorisation
+ * may also come from xod_step_ros2 (of gamma dt), xod_step_bdf2 (of 2dt/3)
+ * or xod_step_newton.  st as for xod_step (resid_inf, refine_iters 0). */
 xod_status xod_step_frozen(xod_column *col, double dt, xod_step_stats *st);
 
 /* One step of the two-stage, second-order, L-stable Rosenbrock method ROS2

@@ -934,7 +934,7 @@ extern "C" xod_status xod_step_frozen(xod_column *col, double dt, xod_step_stats
   XOD_CHECK(!col->in_batch, "xod_step_frozen: column belongs to a batch");
   XOD_CHECK(col->prec == XOD_FP64, "xod_step_frozen: FP64 columns only");
   XOD_CHECK(col->fact_dt > 0 && dt == col->fact_dt,
-            "xod_step_frozen: dt must equal that of the factorisation of the last xod_step");
+            "xod_step_frozen: dt must equal that of the held factorisation");
   ColArgs a = col->args();
   OneCol one{a};
   XOD_TRY(enqueue_photolysis(col));
