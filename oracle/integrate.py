@@ -103,22 +103,26 @@ def ros2_step(prob, n, dt, stages=False):
     return n + delta, delta
 
 
-def bdf2_step(prob, n, n_prev, dt):
+def bdf2_step(prob, n, n_prev, dt, dt_prev=None):
     """One linearly implicit step of the second-order backward
     differentiation formula (BDF2, the lowest member above backward Euler of
-    the BDF family that DLSODES, named in Section 2.1, integrates with) at
-    constant step dt:
-        n_new - 4/3 n + 1/3 n_prev = 2/3 dt F(n_new),
+    the BDF family that DLSODES, named in Section 2.1, integrates with).
+    With the step ratio w = dt / dt_prev (dt_prev: the step that led from
+    n_prev to n; None = dt) the variable-step formula is
+        n_new - (1+w)^2/(1+2w) n + w^2/(1+2w) n_prev = (1+w)/(1+2w) dt F(n_new),
     with F(n_new) linearised about n (one Newton iteration from n).  With
-    h = 2 dt / 3 and Delta = n_new - n this is the backward-Euler system of
-    step h with the history term added to the right-hand side:
-        (I/h - J(n)) Delta = F(n) + (n - n_prev) / (2 dt).
+    h = (1+w)/(1+2w) dt and Delta = n_new - n this is the backward-Euler
+    system of step h with a history term on the right-hand side:
+        (I/h - J(n)) Delta = F(n) + w^2/(1+2w) (n - n_prev) / h.
+    At w = 1: h = 2 dt/3 and the history term (n - n_prev)/(2 dt).
     Returns (n_new, delta)."""
     if getattr(prob, "spectrum", None) is not None:
         prob.lag_photolysis(n)
-    h = 2.0 * dt / 3.0
+    w = 1.0 if dt_prev is None else dt / dt_prev
+    h = (1.0 + w) / (1.0 + 2.0 * w) * dt
     B, a, c = prob.step_matrix(n, h)
-    delta = btd(B, a, c, prob.rhs(n) + (n - n_prev) / (2.0 * dt))
+    hist = w * w / (1.0 + 2.0 * w) * (n - n_prev) / h
+    delta = btd(B, a, c, prob.rhs(n) + hist)
     return n + delta, delta
 
 

@@ -154,3 +154,40 @@ def test_backward_euler_and_ros2_drivers_reach_the_same_steady_state():
     assert a.converged and b.converged
     keep = a.n > 1e-30 * prob.grid.ngas[:, None]
     assert np.max(np.abs(a.n - b.n)[keep] / a.n[keep]) < 1e-7
+
+
+@pytest.mark.parametrize("w", [0.5, 1.0, 3.0])
+def test_variable_step_bdf2_on_a_linear_problem_is_the_recurrence(transport_only, w):
+    """(I - b dt L) n_new = (1+w)^2/(1+2w) n - w^2/(1+2w) n_prev, b = (1+w)/(1+2w)."""
+    prob, n0, L = transport_only
+    dt_prev = 1e5
+    dt = w * dt_prev
+    n_prev = n0 * (1.0 + 0.1 * np.random.default_rng(8).random(n0.shape))
+    eye = np.eye(L.shape[0])
+    b = (1 + w) / (1 + 2 * w)
+    want = np.linalg.solve(eye - b * dt * L, (1 + w) ** 2 / (1 + 2 * w) * n0.ravel()
+                           - w * w / (1 + 2 * w) * n_prev.ravel())
+    got, _ = integrate.bdf2_step(prob, n0, n_prev, dt, dt_prev)
+    assert np.abs(got.ravel() - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def test_variable_step_bdf2_is_second_order_on_the_chemistry():
+    """Steps alternating between h and 2h (ratios 2 and 1/2), halved together."""
+    net, col = synth.make_config(1)
+    prob = integrate.Problem(net, col)
+    N, S = col.n0.shape
+    T = 1e-6
+    ref = solve_ivp(lambda t, y: prob.rhs(y.reshape(N, S)).ravel(), (0.0, T),
+                    col.n0.ravel(), method="Radau", rtol=1e-12, atol=1e-16)
+    yT = ref.y[:, -1]
+
+    def err(m):
+        steps = [T / (1.5 * m) * (1.0 if i % 2 == 0 else 2.0) for i in range(m)]
+        prev = col.n0
+        n, _ = integrate.be_step(prob, prev, steps[0])
+        for i in range(1, m):
+            n, prev = integrate.bdf2_step(prob, n, prev, steps[i], steps[i - 1])[0], n
+        return np.abs(n.ravel() - yT).max() / np.abs(yT).max()
+
+    e = [err(m) for m in (8, 16, 32)]
+    assert 3.6 < e[0] / e[1] < 4.4 and 3.6 < e[1] / e[2] < 4.4
