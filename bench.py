@@ -513,7 +513,7 @@ def main():
             torch.cuda.synchronize()
             el_b = (time.perf_counter() - t0) / args.steps
             bdf2 = {"value": 1.0 / el_b, "unit": "steps/s", "ms_per_step": 1e3 * el_b,
-                    "what": "xod_step_bdf2: linearly implicit constant-step BDF2 (rates, F "
+                    "what": "xod_step_bdf2: linearly implicit BDF2 at constant step (rates, F "
                             "with the history term, Jacobian, factorisation, solve, update)"}
             progress(f"BDF2 steps: {1.0 / el_b:.2f} steps/s")
         except xod.XodError as e:

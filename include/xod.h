@@ -272,18 +272,22 @@ xod_status xod_step_ros2(xod_column *col, double dt, xod_step_stats *st);
  * = iters - 1.  Leaves the factorisation of dt held. */
 xod_status xod_step_newton(xod_column *col, double dt, int32_t iters, xod_step_stats *st);
 
-/* One step of the second-order backward differentiation formula BDF2 at
- * constant step (the BDF family of the DLSODES solver Section 2.1 names),
- * linearised about the current state n (one Newton iteration from n):
- *   n_new - 4/3 n + 1/3 n_prev = 2/3 dt F(n_new)  becomes, with h = 2dt/3,
- *   (I/h - J(n)) Delta = F(n) + (n - n_prev)/(2 dt),  n <- n + Delta.
- * n_prev is the state the previous step started from; that step must be a
- * completed xod_step, xod_step_frozen, xod_step_ros2 or xod_step_bdf2 of
- * the same dt on this column (XOD_EINVAL otherwise: after creation,
+/* One step of the second-order backward differentiation formula BDF2 (the
+ * BDF family of the DLSODES solver Section 2.1 names) with variable step,
+ * linearised about the current state n (one Newton iteration from n).  With
+ * w = dt/dt_prev, dt_prev the previous step's size:
+ *   n_new - (1+w)^2/(1+2w) n + w^2/(1+2w) n_prev = (1+w)/(1+2w) dt F(n_new)
+ * becomes, with h = (1+w)/(1+2w) dt,
+ *   (I/h - J(n)) Delta = F(n) + w^2/(1+2w) (n - n_prev)/h,  n <- n + Delta
+ * (w = 1: h = 2dt/3, history term (n - n_prev)/(2 dt)).  n_prev is the
+ * state the previous step started from; that step must be a completed
+ * xod_step, xod_step_frozen, xod_step_ros2, xod_step_bdf2 or
+ * xod_step_newton on this column (XOD_EINVAL otherwise: after creation,
  * xod_column_set_state, a failed step, a batch step or the steady-state
- * driver).  FP64 and mixed columns (the mixed solve refines against the
- * same right-hand side).  Leaves the factorisation of h held.  st as for
- * xod_step. */
+ * driver).  Ratios w above 1 + sqrt 2 make the formula unstable over many
+ * steps; they are not refused.  FP64 and mixed columns (the mixed solve
+ * refines against the same right-hand side).  Leaves the factorisation of
+ * h held.  st as for xod_step. */
 xod_status xod_step_bdf2(xod_column *col, double dt, xod_step_stats *st);
 
 /* Adaptive driver to steady state; each step is a backward-Euler step, or

@@ -442,7 +442,7 @@ def xod_step_newton(col, dt, iters):
 
 
 def xod_step_bdf2(col, dt):
-    """One constant-step BDF2 step; the previous step must have had this dt."""
+    """One variable-step BDF2 step; its history is the previous step's start."""
     st = StepStats()
     _check(_f["xod_step_bdf2"](col.handle, float(dt), ctypes.byref(st)))
     return st.as_dict()

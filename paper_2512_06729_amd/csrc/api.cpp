@@ -1077,19 +1077,22 @@ extern "C" xod_status xod_step_newton(xod_column *col, double dt, int32_t iters,
   return XOD_OK;
 }
 
-// Linearly implicit constant-step BDF2: with h = 2 dt/3,
-//   (I/h - J(n)) Delta = F(n) + (n - n_prev) / (2 dt),   n <- n + Delta,
+// Linearly implicit variable-step BDF2: with w = dt/dt_prev and
+// h = (1+w)/(1+2w) dt,
+//   (I/h - J(n)) Delta = F(n) + w^2/(1+2w) (n - n_prev) / h,   n <- n + Delta,
 // n_prev being the starting state of the previous step, which the state
 // swap leaves in ntmp.
 extern "C" xod_status xod_step_bdf2(xod_column *col, double dt, xod_step_stats *st) {
   XOD_CHECK(col, "xod_step_bdf2: null column");
   XOD_CHECK(!col->in_batch, "xod_step_bdf2: column belongs to a batch");
   XOD_CHECK(std::isfinite(dt) && dt > 0, "xod_step_bdf2: dt must be > 0");
-  XOD_CHECK(col->prev_dt > 0 && dt == col->prev_dt,
-            "xod_step_bdf2: the previous step must be a completed step of the same dt");
+  XOD_CHECK(col->prev_dt > 0,
+            "xod_step_bdf2: the previous step must be a completed step on this column");
+  const double w = dt / col->prev_dt;
+  const double h = (1.0 + w) / (1.0 + 2.0 * w) * dt;
   int iters, fb;
   double res;
-  XOD_TRY(enqueue_solve(col, 2.0 * dt / 3.0, &iters, &fb, &res, col->ntmp, 0.5 / dt));
+  XOD_TRY(enqueue_solve(col, h, &iters, &fb, &res, col->ntmp, w * w / (1.0 + 2.0 * w) / h));
   double s[kStatLen];
   col->prev_dt = 0.0;   // ntmp is about to receive the new state
   XOD_TRY(run_update(col, false, 1e-30, 1e-10, s));

@@ -47,6 +47,10 @@ def test_bdf2_steps_match_oracle(solver, cfg, dt, prec):
 
 
 def test_bdf2_history_bookkeeping():
+    """Which calls leave a usable history, and the variable-step ratio: a
+    BDF2 step of dt after a step of 2 dt (w = 1/2) and after a ROS2 step of
+    the same dt (w = 1); each compared with the oracle from the GPU's own
+    states."""
     import paper_2512_06729_amd as xod
     net, col = synth.make_config(1)
     prob, gnet, gcol = G.make_pair(net, col)
@@ -59,15 +63,37 @@ def test_bdf2_history_bookkeeping():
 
     refused()                                # nothing before it
     xod.xod_step(gcol, 2 * dt)
-    refused()                                # a step of another dt
     n1 = gcol.state()
-    xod.xod_step_ros2(gcol, dt)              # any completed step of this dt
+    ref, delta = integrate.bdf2_step(prob, n1, col.n0, dt, 2 * dt)
+    xod.xod_step_bdf2(gcol, dt)
+    G.assert_state_agrees(gcol.state(), ref, delta, rel=1e-9)
     n2 = gcol.state()
-    ref, delta = integrate.bdf2_step(prob, n2, n1, dt)
+    xod.xod_step_ros2(gcol, dt)              # any completed step
+    n3 = gcol.state()
+    ref, delta = integrate.bdf2_step(prob, n3, n2, dt)
     xod.xod_step_bdf2(gcol, dt)
     G.assert_state_agrees(gcol.state(), ref, delta, rel=1e-9)
     gcol.set_state(gcol.state())
     refused()                                # the state was replaced
+
+
+@pytest.mark.parametrize("solver", [0, 1])
+def test_variable_step_bdf2_matches_oracle(solver):
+    """Step ratios 2, 1/2 and 3 on the 90-species column."""
+    import paper_2512_06729_amd as xod
+    net, col = synth.make_config(2)
+    prob, gnet, gcol = G.make_pair(net, col)
+    gcol.set_solver(solver)
+    dts = [1e-7, 2e-7, 1e-7, 3e-7]
+    n1, d1 = integrate.be_step(prob, col.n0, dts[0])
+    xod.xod_step(gcol, dts[0])
+    G.assert_state_agrees(gcol.state(), n1, d1, rel=1e-9)
+    prev, n = col.n0, n1
+    for i in range(1, len(dts)):
+        ref, delta = integrate.bdf2_step(prob, n, prev, dts[i], dts[i - 1])
+        xod.xod_step_bdf2(gcol, dts[i])
+        G.assert_state_agrees(gcol.state(), ref, delta, rel=1e-9)
+        prev, n = n, ref
 
 
 @pytest.mark.parametrize("solver,cfg,dt,iters", [(0, 1, 1e-6, 2), (1, 1, 1e-5, 4),
