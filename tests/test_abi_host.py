@@ -41,6 +41,18 @@ def test_header_is_plain_c(tmp_path):
     assert r.returncode == 0, r.stderr
 
 
+def test_binding_covers_every_header_symbol():
+    """Each entry point of include/xod.h has a typed binding (the status
+    calls in the signature table; the workspace-size query, which returns a
+    size, directly), and nothing is bound that the header does not declare."""
+    import paper_2512_06729_amd as xod
+    declared = set(xod.header_symbols())
+    bound = set(xod._f)
+    assert declared - bound == {"xod_photolysis_workspace"}
+    assert bound <= declared
+    assert xod.photolysis_workspace(1, 1, 1, 1) > 0
+
+
 def _desc(xod, S=3, reac=None):
     keep = dict(comp=np.ones((1, S), np.int32), mass=np.full(S, 10.0),
                 nasa=np.zeros((S, 2, 7)), rtype=np.zeros(1, np.int32),
