@@ -72,36 +72,107 @@ def cr_gemm_products(N):
     return n
 
 
-def cpu_baseline(net, col, seconds=15.0):
-    """The oracle's backward-Euler step on the same column, timed on the host
-    cores for a bounded number of steps (about `seconds` of work)."""
-    import numpy as np
+def oracle_steps(seconds, max_steps, keep=0):
+    """Backward-Euler steps of the oracle on the 594 x 150 column from its
+    initial state at dt = 1e-6, for about `seconds` or `max_steps` steps;
+    returns (steps, elapsed s, set-up s, the first `keep` states)."""
     from oracle import integrate
+    import synth
+    net, col = synth.make_config(3)
     t0 = time.perf_counter()
     prob = integrate.Problem(net, col)
     setup = time.perf_counter() - t0
     n = col.n0.copy()
+    states = []
     steps = 0
     t0 = time.perf_counter()
     while True:
         n, _ = integrate.be_step(prob, n, 1e-6)
         steps += 1
+        if len(states) < keep:
+            states.append(n)
         el = time.perf_counter() - t0
-        if el > seconds or steps >= 20:
+        if (el > seconds and len(states) >= keep) or steps >= max_steps:
             break
+    return steps, el, setup, states
+
+
+def oracle_worker(seconds, max_steps):
+    """Entry of the one-thread oracle timing (a child process whose BLAS and
+    OpenMP thread counts were set to 1 before NumPy loaded)."""
+    steps, el, setup, _ = oracle_steps(seconds, max_steps)
+    print(json.dumps({"steps": steps, "elapsed_s": el, "setup_s": setup}), flush=True)
+
+
+def cpu_baseline(seconds=12.0, keep=3):
+    """The oracle's backward-Euler step on the same column, timed on the host
+    cores for a bounded number of steps: once with the default BLAS threads
+    (all cores) and once in a child process limited to one thread.  The
+    first `keep` states of the all-core run are returned for the per-species
+    error of the GPU steps."""
+    import subprocess
+    steps, el, setup, states = oracle_steps(seconds, 20, keep)
     try:
         cores = len(os.sched_getaffinity(0))
     except Exception:
         cores = os.cpu_count()
-    return {"value": steps / el, "unit": "steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{steps} oracle BE steps (dt=1e-6) of the 594x150 column, "
-                      f"{el:.1f} s (+{setup:.1f} s grid/rate set-up untimed); "
-                      "NumPy/SciPy with their default BLAS threads"}
+    out = {"value": steps / el, "unit": "steps/s", "cores": cores, "kind": "oracle",
+           "sample": f"{steps} oracle BE steps (dt=1e-6) of the 594x150 column from its "
+                     f"initial state, {el:.1f} s (+{setup:.1f} s grid/rate set-up untimed); "
+                     f"NumPy/SciPy with their default BLAS threads on {cores} cores"}
+    env = dict(os.environ)
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS",
+              "BLIS_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
+        env[v] = "1"
+    try:
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-worker",
+                            str(seconds / 2), "2"], env=env, cwd=ROOT, capture_output=True,
+                           text=True, timeout=300)
+        w = json.loads(r.stdout.strip().splitlines()[-1])
+        out["one_thread"] = {"value": w["steps"] / w["elapsed_s"], "unit": "steps/s",
+                             "cores": 1, "sample": f"{w['steps']} oracle BE steps, "
+                             f"{w['elapsed_s']:.1f} s, one BLAS/OpenMP thread"}
+    except Exception as e:      # reported, not fatal: the all-core figure stands
+        out["one_thread"] = {"error": repr(e)[:200]}
+    return out, states
+
+
+def per_species(n, ref, ngas):
+    """Largest relative error over layers of each species' densities with
+    mixing ratio above 1e-30, summarised: max, median, worst species and the
+    number of species per error decade."""
+    import numpy as np
+    keep = np.abs(ref) > 1e-30 * ngas[:, None]
+    rel = np.where(keep, np.abs(n - ref) / np.where(keep, np.abs(ref), 1.0), 0.0)
+    e = rel.max(axis=0)
+    hist = {}
+    for lo in (0, 1e-16, 1e-14, 1e-12, 1e-10, 1e-8, 1e-6, 1e-4):
+        hi = lo * 100 if lo else 1e-16
+        hist[f"<{hi:g}" if not lo else f"{lo:g}..{hi:g}"] = int(((e >= lo) & (e < hi)).sum())
+    hist[">=1e-2"] = int((e >= 1e-2).sum())
+    return {"max": float(e.max()), "median": float(np.median(e)),
+            "worst_species": int(np.argmax(e)), "species_per_decade": hist}
+
+
+def time_each(torch, reset, call, reps):
+    """Wall time of `reps` calls, each bracketed by device synchronisations
+    and each from the state reset() establishes (untimed).  Returns (total
+    seconds, list of the calls' results)."""
+    total, out = 0.0, []
+    for _ in range(reps):
+        reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out.append(call())
+        torch.cuda.synchronize()
+        total += time.perf_counter() - t0
+    return total, out
 
 
 def bench_mixed(xod, torch, gnet, col, args, solver):
     """The same steps with FP32 Schur complements / products and FP64
-    refinement; error of the first step against the FP64 GPU step."""
+    refinement, each from the initial state; refinements per step and the
+    error of the first step against the FP64 GPU step."""
     import numpy as np
     stream = torch.cuda.current_stream().cuda_stream
     gm = xod.Column(gnet, col, precision=xod.XOD_MIXED, stream=stream, solver=solver)
@@ -111,22 +182,92 @@ def bench_mixed(xod, torch, gnet, col, args, solver):
     a, b = gm.state(), g64.state()
     keep = np.abs(b) > 1e-30 * np.asarray(g64.grid()["ngas"])[:, None]
     err = float(np.max(np.abs(a - b)[keep] / np.abs(b)[keep]))
-    for _ in range(max(0, args.warmup - 1)):
-        xod.xod_step(gm, args.dt)
-    torch.cuda.synchronize()
-    iters = fb = 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s = xod.xod_step(gm, args.dt)
-        iters += s["refine_iters"]
-        fb += s["fp64_fallback"]
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    reset = lambda: gm.set_state(col.n0)   # noqa: E731
+    time_each(torch, reset, lambda: xod.xod_step(gm, args.dt), args.warmup)
+    el, sts = time_each(torch, reset, lambda: xod.xod_step(gm, args.dt), args.steps)
+    iters = sum(s["refine_iters"] for s in sts)
+    fb = sum(s["fp64_fallback"] for s in sts)
     gm.close()
     g64.close()
     return {"value": args.steps / el, "unit": "steps/s", "ms_per_step": 1e3 * el / args.steps,
             "refine_iters_per_step": iters / args.steps, "fp64_fallbacks": fb,
-            "first_step_max_rel_err_vs_fp64": err, "first_step_refine_iters": st["refine_iters"]}
+            "first_step_max_rel_err_vs_fp64": err, "first_step_refine_iters": st["refine_iters"],
+            "what": "each step from the initial state at the bench dt"}
+
+
+def trajectory(xod, gnet, col, precision, solver, dt, steps, stream):
+    """States after 1..steps backward-Euler steps from the initial state."""
+    g = xod.Column(gnet, col, precision=precision, stream=stream, solver=solver)
+    out = []
+    for _ in range(steps):
+        xod.xod_step(g, dt)
+        out.append(g.state())
+    g.close()
+    return out
+
+
+def bench_config1(xod, torch, stream):
+    """Latency-bound workload: the 12-species x 20-layer column through the
+    200-step fixed schedule dt_j = 1e-8 1.2^j, back to back (every step is
+    synchronous: it reads its statistics)."""
+    import synth
+    from paper_2512_06729_amd import XOD_SOLVER_CR, XOD_SOLVER_THOMAS
+    net, col = synth.make_config(1)
+    gnet = xod.Network(net)
+    sched = [1e-8 * 1.2 ** j for j in range(200)]
+    out = {"workload": "S=12, R=30, N=20: 200 fixed-schedule backward-Euler steps"}
+    for name, solver in (("cr", XOD_SOLVER_CR), ("thomas", XOD_SOLVER_THOMAS)):
+        g = xod.Column(gnet, col, stream=stream, solver=solver)
+        xod.xod_step(g, 1e-8)
+        g.set_state(col.n0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for dt in sched:
+            xod.xod_step(g, dt)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"us_per_step": 1e6 * el / len(sched), "steps_per_s": len(sched) / el}
+        g.close()
+    gnet.close()
+    return out
+
+
+def bench_config2(xod, torch, stream):
+    """The 90-species x 120-layer column (1200 reactions) integrated to steady
+    state (max |dn/n| < 1e-4 with dt past the mixing time) by the library's
+    adaptive driver: wall time, steps and rejections, for both
+    factorisations."""
+    import synth
+    from paper_2512_06729_amd import XOD_SOLVER_CR, XOD_SOLVER_THOMAS
+    net, col = synth.make_config(2)
+    gnet = xod.Network(net)
+    out = {"workload": "S=90, R=1200, N=120: adaptive backward Euler to steady state, "
+                       "tol_rel 1e-4"}
+    for name, solver in (("cr", XOD_SOLVER_CR), ("thomas", XOD_SOLVER_THOMAS)):
+        g = xod.Column(gnet, col, stream=stream, solver=solver)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = xod.xod_integrate_to_steady_state(g, tol_rel=1e-4, check=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"wall_s": el, "steps": r["steps"], "rejects": r["rejects"],
+                     "t_end_s": r["t"], "converged": r["converged"],
+                     "ms_per_step": 1e3 * el / max(1, r["steps"] + r["rejects"])}
+        g.close()
+    gnet.close()
+    return out
+
+
+def hbm_roofline(kern, name, algo_bytes, kernels):
+    """Achieved HBM rate of a memory-bound kernel group from its event-timed
+    launches and its algorithmic bytes per launch."""
+    k = kern.get(name)
+    if not k or not k["avg_us"]:
+        return None
+    ach = algo_bytes / (k["avg_us"] * 1e-6) / 1e9
+    return {"bound": "hbm", "kernels": kernels, "achieved": ach, "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "algorithmic_bytes": algo_bytes,
+            "avg_launch_us": k["avg_us"]}
 
 
 def bench_batch(xod, torch, args, precision):
@@ -311,15 +452,6 @@ def panel_traffic():
     return vals.get("bytes") if vals.get("sha") == sha else None
 
 
-def timed_steps(xod, torch, gcol, dt, steps):
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        xod.xod_step(gcol, dt)
-    torch.cuda.synchronize()
-    return time.perf_counter() - t0
-
-
 KERNELS = ("panel", "update", "gemm", "prologue", "solve", "jacobian", "rates", "rhs")
 T_START = time.perf_counter()
 
@@ -341,6 +473,10 @@ def main():
     ap.add_argument("--skip-mixed", action="store_true")
     ap.add_argument("--skip-thomas", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
+    ap.add_argument("--skip-small", action="store_true",
+                    help="skip the 12-species latency and 90-species steady-state legs")
+    ap.add_argument("--skip-integrators", action="store_true",
+                    help="skip the frozen, ROS2, BDF2 and Newton legs")
     ap.add_argument("--batch-cols", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--skip-serve", action="store_true")
@@ -353,7 +489,12 @@ def main():
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="copy 256 MiB device to device three times first (the plain copy "
                          "that scales FETCH_SIZE / WRITE_SIZE counters to bytes)")
+    ap.add_argument("--oracle-worker", nargs=2, type=float, metavar=("SECONDS", "STEPS"),
+                    help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_worker:
+        oracle_worker(args.oracle_worker[0], int(args.oracle_worker[1]))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): columns are "
               "independent, so more GPUs would only shard columns; no multi-GPU run "
@@ -379,21 +520,22 @@ def main():
     gnet = xod.Network(net)
     solver = xod.XOD_SOLVER_CR if args.solver == "cr" else xod.XOD_SOLVER_THOMAS
     gcol = xod.Column(gnet, col, precision=xod.XOD_FP64, stream=stream, solver=solver)
-
-    col_dz = gcol.grid()["dz"]            # layer thicknesses of the library's column grid
+    grid = gcol.grid()
+    col_dz, ngas = grid["dz"], np.asarray(grid["ngas"])
     progress("config-3 column on the device")
-    for _ in range(args.warmup):
-        xod.xod_step(gcol, args.dt)
-    torch.cuda.synchronize()
 
-    # timed region: the steps alone
-    el = timed_steps(xod, torch, gcol, args.dt, args.steps)
-    # kernel breakdown: the same number of steps again with HIP events around
-    # every launch (profile_every thins the per-layer block-Thomas events)
+    # Every timed step starts from the column's initial state (reset untimed),
+    # so each leg times the same physical step whatever ran before it.
+    reset = lambda: gcol.set_state(col.n0)   # noqa: E731
+    be = lambda: xod.xod_step(gcol, args.dt)   # noqa: E731
+    time_each(torch, reset, be, args.warmup)
+    el, _ = time_each(torch, reset, be, args.steps)
+    # kernel breakdown: the same steps again with HIP events around every
+    # launch (profile_every thins the per-layer block-Thomas events)
     xod.profile_reset()
     xod.set_option("profile_every", args.profile_every)
     xod.set_option("profile", 1)
-    el_prof = timed_steps(xod, torch, gcol, args.dt, args.steps)
+    el_prof, _ = time_each(torch, reset, be, args.steps)
     xod.set_option("profile", 0)
 
     kern = {}
@@ -402,7 +544,7 @@ def main():
         kern[name] = {"total_ms": ms, "launches": cnt,
                       "avg_us": 1e3 * ms / cnt if cnt else None}
 
-    S, N = net.S, col.N
+    S, N, R = net.S, col.N, net.R
     # algorithmic flops per step of the kernels that carry the factorisation
     npanel = -(-S // 32)
     gj_flops = 2.0 * S ** 3                          # one Gauss-Jordan inversion
@@ -415,9 +557,8 @@ def main():
     flops = {"gemm": gemm_flops, "update": upd_flops, "panel": N * panel_flops}
     dominant = max(("panel", "update", "gemm"), key=lambda k: kern[k]["total_ms"])
     dk = kern[dominant]
-    steps_prof = args.steps   # events cover every timed step
     frac_prof = 1.0 if args.solver == "cr" else 1.0 / args.profile_every
-    per_launch_flops = flops[dominant] * steps_prof * frac_prof / max(dk["launches"], 1)
+    per_launch_flops = flops[dominant] * args.steps * frac_prof / max(dk["launches"], 1)
     achieved = per_launch_flops / (dk["avg_us"] * 1e-6) / 1e12 if dk["avg_us"] else None
     if dominant == "panel":
         rl = {"bound": "alu", "kernel": "k_panel (Gauss-Jordan panel, FP64 VALU, one "
@@ -431,6 +572,7 @@ def main():
     rl.update({"achieved": achieved, "unit": "TFLOP/s",
                "frac": achieved / rl["peak"] if achieved else None, "traffic": traffic,
                "flops_per_launch": per_launch_flops, "avg_launch_us": dk["avg_us"]})
+
     def gemm_roofline(g, kernel):
         if not g["avg_us"]:
             return None
@@ -451,7 +593,7 @@ def main():
         xod.set_option("gemm_lib", 1 - lib)
         xod.profile_reset()
         xod.set_option("profile", 1)
-        el_alt = timed_steps(xod, torch, gcol, args.dt, args.steps)
+        el_alt, _ = time_each(torch, reset, be, args.steps)
         xod.set_option("profile", 0)
         xod.set_option("gemm_lib", lib)
         ms, cnt = xod.profile_read("gemm")
@@ -461,63 +603,47 @@ def main():
             gemm_alt["ms_per_step_with_kernel_events"] = 1e3 * el_alt / args.steps
         progress("other block-product path profiled for comparison")
 
-    # factor reuse: a step that solves with the factors the step before it
-    # left.  Repeated frozen steps diverge on this network at this dt (the
-    # oracle does the same), so each one follows a full step; its time is the
-    # pair's less a full step's.
-    frozen = None
-    if args.solver == "cr":
-        try:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(args.steps):
-                xod.xod_step(gcol, args.dt)
-                xod.xod_step_frozen(gcol, args.dt)
-            torch.cuda.synchronize()
-            el_pair = (time.perf_counter() - t0) / args.steps
-            el_fr = el_pair - el / args.steps
-            frozen = {"value": 1.0 / el_fr, "unit": "steps/s", "ms_per_step": 1e3 * el_fr,
-                      "ms_per_full_plus_frozen_pair": 1e3 * el_pair,
-                      "what": "xod_step_frozen after each xod_step: rates, F, solve with that "
-                              "step's factors, update (no Jacobian, no factorisation)"}
-            progress(f"frozen-matrix steps: {1.0 / el_fr:.1f} steps/s")
-        except xod.XodError as e:
-            frozen = {"error": str(e)}
+    # HBM-bound kernel groups: algorithmic bytes per launch (reads of the rate
+    # coefficients and the state, writes of the outputs; FP64)
+    hbm = {
+        "rates": hbm_roofline(kern, "rates", 16.0 * N * R, "k_rates: writes k_f, k_r"),
+        "rhs": hbm_roofline(kern, "rhs", 16.0 * N * R + 16.0 * N * S,
+                            "k_wrate + k_rhs: reads k_f, k_r, n; writes F"),
+        "jacobian": hbm_roofline(kern, "jacobian", 16.0 * N * R + 8.0 * N * S + 8.0 * N * S * S,
+                                 "k_dwd + k_jac: reads k_f, k_r, n; writes the S x S blocks "
+                                 "(the stored blocks are ld x ld, ld = 608: 4.8 % more)"),
+    }
 
-    # Rosenbrock ROS2: one factorisation, two solves per step
-    ros2 = None
-    if args.solver == "cr":
-        try:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(args.steps):
-                xod.xod_step_ros2(gcol, args.dt)
-            torch.cuda.synchronize()
-            el_r = (time.perf_counter() - t0) / args.steps
-            ros2 = {"value": 1.0 / el_r, "unit": "steps/s", "ms_per_step": 1e3 * el_r,
-                    "what": "xod_step_ros2: two-stage Rosenbrock step (rates, two F, "
-                            "Jacobian, one factorisation, two solves, update)"}
-            progress(f"ROS2 steps: {1.0 / el_r:.2f} steps/s")
-        except xod.XodError as e:
-            ros2 = {"error": str(e)}
-
-    # constant-step BDF2 (history: the previous step's starting state)
-    bdf2 = None
-    if args.solver == "cr":
-        try:
+    integ = {}
+    if args.solver == "cr" and not args.skip_integrators:
+        # factor reuse: a backward-Euler step solving with the factors the full
+        # step before it left (both from the initial state; the full step is
+        # untimed)
+        def after_full():
+            reset()
             xod.xod_step(gcol, args.dt)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(args.steps):
-                xod.xod_step_bdf2(gcol, args.dt)
-            torch.cuda.synchronize()
-            el_b = (time.perf_counter() - t0) / args.steps
-            bdf2 = {"value": 1.0 / el_b, "unit": "steps/s", "ms_per_step": 1e3 * el_b,
-                    "what": "xod_step_bdf2: linearly implicit BDF2 at constant step (rates, F "
-                            "with the history term, Jacobian, factorisation, solve, update)"}
-            progress(f"BDF2 steps: {1.0 / el_b:.2f} steps/s")
-        except xod.XodError as e:
-            bdf2 = {"error": str(e)}
+        for name, call, pre, what in (
+                ("frozen_matrix_steps", lambda: xod.xod_step_frozen(gcol, args.dt), after_full,
+                 "xod_step_frozen after an untimed xod_step from the initial state: rates, F, "
+                 "solve with that step's factors, update (no Jacobian, no factorisation)"),
+                ("ros2_steps", lambda: xod.xod_step_ros2(gcol, args.dt), reset,
+                 "xod_step_ros2 from the initial state: two-stage Rosenbrock step (rates, two "
+                 "F, Jacobian, one factorisation, two solves, update)"),
+                ("bdf2_steps", lambda: xod.xod_step_bdf2(gcol, args.dt), after_full,
+                 "xod_step_bdf2 after an untimed xod_step from the initial state (its "
+                 "history): rates, F with the history term, Jacobian, factorisation, solve, "
+                 "update"),
+                ("newton3_steps", lambda: xod.xod_step_newton(gcol, args.dt, 3), reset,
+                 "xod_step_newton with 3 iterations from the initial state: one Jacobian and "
+                 "factorisation, three solves and right-hand sides")):
+            try:
+                e, _ = time_each(torch, pre, call, max(2, args.steps // 2))
+                k = max(2, args.steps // 2)
+                integ[name] = {"value": k / e, "unit": "steps/s", "ms_per_step": 1e3 * e / k,
+                               "steps": k, "what": what}
+                progress(f"{name}: {k / e:.2f} steps/s")
+            except xod.XodError as ex:
+                integ[name] = {"error": str(ex)}
 
     steps_per_s = args.steps / el
     line = {
@@ -535,31 +661,37 @@ def main():
         "data": "synthetic (seeded 594-species / 7720-reaction network, 150-layer column)",
         "config": {"workload": "single column, S=594 species, R=7720 reactions, N=150 layers, "
                                "backward-Euler step (rates+RHS+Jacobian+block-tridiagonal "
-                               "factorisation+solve+update)",
-                   "S": S, "R": net.R, "N": N, "precision": "fp64", "dt": args.dt,
+                               "factorisation+solve+update), every timed step from the "
+                               "initial state",
+                   "S": S, "R": R, "N": N, "precision": "fp64", "dt": args.dt,
                    "solver": "block cyclic reduction" if args.solver == "cr" else "block Thomas"},
         "roofline": dict(rl),
         "roofline_schur_gemm": gemm_rl,
         "roofline_schur_gemm_other_path": gemm_alt,
-        "frozen_matrix_steps": frozen,
-        "ros2_steps": ros2,
-        "bdf2_steps": bdf2,
+        "roofline_hbm": hbm,
         "kernels": kern,
         "ms_per_step_with_kernel_events": 1e3 * el_prof / args.steps,
     }
+    line.update(integ)
     gcol.close()
     progress(f"FP64 steps: {steps_per_s:.2f} steps/s")
     if not args.skip_thomas and args.solver == "cr":
         gt = xod.Column(gnet, col, precision=xod.XOD_FP64, stream=stream)
-        xod.xod_step(gt, args.dt)
         k = max(2, args.steps // 5)
-        et = timed_steps(xod, torch, gt, args.dt, k)
+        et, _ = time_each(torch, lambda: gt.set_state(col.n0), lambda: xod.xod_step(gt, args.dt),
+                          k)
         line["thomas"] = {"value": k / et, "unit": "steps/s", "ms_per_step": 1e3 * et / k,
                           "steps": k}
         gt.close()
     if not args.skip_mixed:
         line["mixed"] = bench_mixed(xod, torch, gnet, col, args, solver)
         progress(f"mixed steps: {line['mixed']['value']:.2f} steps/s")
+    if not args.skip_small:
+        line["config1_latency"] = bench_config1(xod, torch, stream)
+        progress("config 1: %.1f us/step (cr)" % line["config1_latency"]["cr"]["us_per_step"])
+        line["config2_steady_state"] = bench_config2(xod, torch, stream)
+        progress("config 2 steady state: %.2f s (cr)" %
+                 line["config2_steady_state"]["cr"]["wall_s"])
     if not args.skip_serve:
         s64, n64 = bench_serve(xod, torch, args, xod.XOD_FP64, gnet, net)
         if args.serve_fp64_only:
@@ -587,8 +719,21 @@ def main():
         progress(f"batch mixed: {bmx['value']:.1f} column-steps/s")
         line["batch"] = {"fp64": b64, "mixed": bmx}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(net, col)
+        base, ref_states = cpu_baseline()
+        line["cpu_baseline"] = base
         progress("oracle timed")
+        # per-species error of three GPU steps from the initial state against
+        # the oracle's three steps (each trajectory on its own)
+        err = {}
+        k = len(ref_states)
+        for name, prec in (("fp64", xod.XOD_FP64), ("mixed", xod.XOD_MIXED)):
+            if name == "mixed" and args.skip_mixed:
+                continue
+            traj = trajectory(xod, gnet, col, prec, solver, 1e-6, k, stream)
+            err[name] = per_species(traj[-1], ref_states[-1], ngas)
+            err[name]["steps"] = k
+        line["per_species_error_vs_oracle"] = err
+        progress("per-species error vs the oracle done")
     print(json.dumps(line), flush=True)
 
 

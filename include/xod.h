@@ -244,8 +244,10 @@ xod_status xod_step(xod_column *col, double dt, xod_step_stats *stats);
  * columns; dt must equal the dt of that factorisation (XOD_EINVAL
  * otherwise, or when no factorisation is held: after creation, a solver
  * switch, a boundary change or a mixed-precision step).  The factorisation
- * may also come from xod_step_ros2 (of gamma dt), xod_step_bdf2 (of 2dt/3)
- * or xod_step_newton.  st as for xod_step (resid_inf, refine_iters 0). */
+ * may also come from xod_step_ros2 (of gamma dt), xod_step_bdf2 (of
+ * h = (1+w)/(1+2w) dt, w the step ratio; 2dt/3 at constant step) or
+ * xod_step_newton.  A column that joined a batch holds none.  st as for
+ * xod_step (resid_inf, refine_iters 0). */
 xod_status xod_step_frozen(xod_column *col, double dt, xod_step_stats *st);
 
 /* One step of the two-stage, second-order, L-stable Rosenbrock method ROS2

@@ -64,15 +64,3 @@ def btd_solve(fac, a, c, rhs):
 def btd(B, a, c, rhs):
     return btd_solve(btd_factor(B, a, c), a, c, rhs)
 
-
-def block_apply(B, a, c, x):
-    """y = M x for the block-tridiagonal matrix, block by block."""
-    N, S = x.shape
-    y = np.zeros_like(x)
-    for k in range(N):
-        y[k] = B[k] @ x[k]
-        if k >= 1:
-            y[k] += a[k] * x[k - 1]
-        if k <= N - 2:
-            y[k] += c[k] * x[k + 1]
-    return y

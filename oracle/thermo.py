@@ -23,20 +23,6 @@ def cp_over_r(a, T):
     return a1 + a2 * T + a3 * T ** 2 + a4 * T ** 3 + a5 * T ** 4
 
 
-def h_over_rt(a, T):
-    """Standard NASA-7 enthalpy H/RT (the integral of Cp consistent with G/RT)."""
-    a1, a2, a3, a4, a5, a6 = (float(x) for x in a[:6])
-    return (a1 + a2 * T / 2.0 + a3 * T ** 2 / 3.0 + a4 * T ** 3 / 4.0
-            + a5 * T ** 4 / 5.0 + a6 / T)
-
-
-def s_over_r(a, T):
-    """Standard NASA-7 entropy S/R (so that G/RT = H/RT - S/R)."""
-    a1, a2, a3, a4, a5, _, a7 = (float(x) for x in a)
-    return (a1 * np.log(T) + a2 * T + a3 * T ** 2 / 2.0 + a4 * T ** 3 / 3.0
-            + a5 * T ** 4 / 4.0 + a7)
-
-
 def species_g(nasa7, t_mid, T):
     """G/RT of every species at temperature T; the high range is used iff
     T >= t_mid (Appendix A gives 10-1000 K and 1000-3000 K ranges; the tie

@@ -284,7 +284,13 @@ extern "C" xod_status xod_batch_create(xod_column *const *cols, int32_t ncols, x
   b->cols.assign(cols, cols + ncols);
   b->stream = cols[0]->stream;
   XOD_TRY_B(b->runner.init(ncols));
-  for (auto *c : b->cols) c->in_batch = true;
+  // batch steps overwrite each column's blocks and pivots with block-Thomas
+  // factors of the batch's dt: no factorisation stays usable by
+  // xod_step_frozen, during the batch or after it
+  for (auto *c : b->cols) {
+    c->in_batch = true;
+    c->fact_dt = 0.0;
+  }
   *out = b.release();
   return XOD_OK;
 }

@@ -56,3 +56,78 @@ def test_batch_rejects_mixed_precisions():
     with pytest.raises(xod.XodError) as e:
         xod.Batch([a, b])
     assert e.value.status == xod.XOD_EINVAL
+
+
+def full_size_batch():
+    """Columns of the batched workload's three network sizes (594, 250 and
+    90 species; layer counts ragged, T offsets and Kzz scales per column as
+    in the batch recipe)."""
+    nets = {594: synth.make_network("c3", seed=1003),
+            250: synth.make_network("s250", seed=4250),
+            90: synth.make_network("c2", seed=1002)}
+    spec = [(594, 31, -120.0, 0.3), (250, 60, 250.0, 4.0), (594, 9, 80.0, 2.0),
+            (90, 45, -290.0, 0.15), (250, 17, 0.0, 1.0)]
+    out = []
+    for i, (S, N, dT, ks) in enumerate(spec):
+        out.append((nets[S], synth.make_column("c2", nets[S], seed=4100 + i, N=N, T_offset=dT,
+                                               Kzz_scale=ks)))
+    return out
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_batch_matches_oracle(precision):
+    """A batch holding 594- and 250-species columns (ld 608 and 256: the
+    wide-strip trailing update across columns, forked group streams) steps
+    every column as the oracle does: FP64 at the per-layer tolerance,
+    mixed precision within 1e-6 on every mixing ratio above 1e-30."""
+    import paper_2512_06729_amd as xod
+    print(f"full-size batch, precision {precision}", flush=True)
+    stream = torch.cuda.current_stream().cuda_stream
+    cols_in = full_size_batch()
+    gnets = {}
+    cols = []
+    for net, col in cols_in:
+        if id(net) not in gnets:
+            gnets[id(net)] = xod.Network(net)
+        cols.append(xod.Column(gnets[id(net)], col, precision=precision, stream=stream))
+    alone = [xod.Column(gnets[id(net)], col, precision=precision, stream=stream)
+             for net, col in cols_in]
+    batch = xod.Batch(cols)
+    dts = np.array([1e-6, 1e-5, 1e-7, 1e-6, 3e-6])
+    batch.step(dts)
+    for (net, col), c, a, dt in zip(cols_in, cols, alone, dts):
+        prob = integrate.Problem(net, col)
+        ref, delta = integrate.be_step(prob, col.n0, dt)
+        n = c.state()
+        if precision == 0:
+            G.assert_state_agrees(n, ref, delta)
+            xod.xod_step(a, dt)
+            np.testing.assert_array_equal(a.state(), n)   # batch = alone, bit for bit
+        else:
+            keep = np.abs(ref) > 1e-30 * prob.grid.ngas[:, None]
+            rel = np.abs(n - ref)[keep] / np.abs(ref)[keep]
+            print(f"  S={net.nasa7.shape[0]} N={col.N}: max rel err {rel.max():.2e}")
+            assert rel.max() <= 1e-6, rel.max()
+    batch.close()
+
+
+def test_no_factorisation_held_after_a_batch():
+    """Batch steps overwrite a column's blocks with the batch's factors, so
+    xod_step_frozen must refuse the column afterwards, even at the dt of its
+    own last step."""
+    import paper_2512_06729_amd as xod
+    stream = torch.cuda.current_stream().cuda_stream
+    net = synth.make_network("c1", seed=1001)
+    gnet = xod.Network(net)
+    a = xod.Column(gnet, synth.make_column("c1", net, seed=1, N=5), stream=stream)
+    b = xod.Column(gnet, synth.make_column("c1", net, seed=2, N=8), stream=stream)
+    a.set_solver(xod.XOD_SOLVER_CR)
+    xod.xod_step(a, 1e-6)
+    xod.xod_step_frozen(a, 1e-6)          # held: the step's own factorisation
+    batch = xod.Batch([a, b])
+    batch.step(np.array([2e-6, 2e-6]))
+    batch.close()
+    for dt in (1e-6, 2e-6):
+        with pytest.raises(xod.XodError) as e:
+            xod.xod_step_frozen(a, dt)
+        assert e.value.status == xod.XOD_EINVAL
