@@ -219,10 +219,13 @@ xod_status xod_btd_solve(xod_column *col, const double *B, const double *a,
  * solve (I/dt - J(n)) delta = F(n), n <- n + delta (no clipping).  In
  * XOD_MIXED each refinement solves for the FP64 residual (computed from the
  * reaction list and the transport coefficients) with the FP32 factors and
- * adds the correction d; it stops once max over layers of
- * max|d_k| / max|delta_k| <= 1e-10 (option "refine_tol_exp"), or when the
- * ratio stops halving and is <= 1e-9; otherwise, and after 10 refinements,
- * the step is refactored and solved in FP64.  Synchronous (reads the
+ * adds the correction d; it stops once every component whose new mixing
+ * ratio exceeds 1e-30 moved by at most rtol of its new density or by atol of
+ * its layer's largest increment, |d_i| <= rtol |n_i + delta_i| + atol
+ * max_k |delta_k| (rtol 1e-7, atol 1e-14: options "refine_tol_exp",
+ * "refine_atol_exp"), or, once the corrections stop halving or after 10
+ * refinements, if they are within ten times that; otherwise the step is
+ * refactored and solved in FP64.  Synchronous (reads the
  * statistics). */
 typedef struct {
   double max_rel_change;   /* max |delta| / |n_new| over n_new/n_gas > 1e-30 */
@@ -407,9 +410,12 @@ xod_status xod_photolysis_spectral(int32_t N, int32_t S, int32_t A, int32_t L, i
  *   "gemm_k": K step of the block products staged through LDS, 16 or 32
  *            (default 32); every element sums its K terms in the same order
  *            with either.
- *   "refine_tol_exp": e in 6..15: a mixed-precision solve has converged
- *            once the largest layer-wise correction ratio max|d|/max|x| is
- *            at most 10^-e (default 10).
+ *   "refine_tol_exp": e in 3..15: a mixed-precision solve has converged
+ *            once no component with mixing ratio above 1e-30 moves by more
+ *            than 10^-e of its new density (default 7), or by more than the
+ *            absolute floor below;
+ *   "refine_atol_exp": e in 8..17: that floor, 10^-e times the layer's
+ *            largest increment (default 14);
  *   "outer": Gauss-Jordan outer panel width, 32 (default), 64, 96 or 128:
  *            with a width above 32 the 32-column panels of an outer panel
  *            update only its own columns, then one rank-width update covers

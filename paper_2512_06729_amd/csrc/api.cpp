@@ -128,8 +128,13 @@ extern "C" xod_status xod_set_option(const char *name, int64_t value) {
     return XOD_OK;
   }
   if (std::strcmp(name, "refine_tol_exp") == 0) {
-    XOD_CHECK(value >= 6 && value <= 15, "xod_set_option: refine_tol_exp must be in 6..15");
+    XOD_CHECK(value >= 3 && value <= 15, "xod_set_option: refine_tol_exp must be in 3..15");
     options().refine_tol = std::pow(10.0, -(double)value);
+    return XOD_OK;
+  }
+  if (std::strcmp(name, "refine_atol_exp") == 0) {
+    XOD_CHECK(value >= 8 && value <= 17, "xod_set_option: refine_atol_exp must be in 8..17");
+    options().refine_atol = std::pow(10.0, -(double)value);
     return XOD_OK;
   }
   if (std::strcmp(name, "outer") == 0) {
@@ -185,6 +190,7 @@ extern "C" xod_status xod_get_option(const char *name, int64_t *value) {
       {"graph", o.graph},              {"profile", o.profile},
       {"profile_every", o.profile_every},
       {"refine_tol_exp", (int64_t)std::lround(-std::log10(o.refine_tol))},
+      {"refine_atol_exp", (int64_t)std::lround(-std::log10(o.refine_atol))},
   };
   for (const Entry &e : entries)
     if (std::strcmp(name, e.name) == 0) {
@@ -853,7 +859,7 @@ xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, do
   else
     XOD_HIP(launch_solve_mixed(one, 1, c->N, c->ld, c->stream));
   XOD_HIP(hipMemcpyAsync(c->dx, c->x, NSb, hipMemcpyDeviceToDevice, c->stream));
-  bool ok = false;
+  RefineNext verdict = kRefineFallback;
   double prev = 1e300, ratio = 1e300;
   for (int it = 1; it <= c->max_refine; ++it) {
     XOD_HIP(launch_residual(one, 1, c->N, c->S, c->R, c->stream));
@@ -867,17 +873,11 @@ xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, do
     XOD_HIP(hipStreamSynchronize(c->stream));
     ratio = c->stats_host[0];
     *iters = it;
-    if (ratio <= options().refine_tol) {
-      ok = true;
-      break;
-    }
-    if (ratio > 0.5 * prev) {          // stagnation: converged to the FP64 floor?
-      ok = ratio <= 1e-9;
-      break;
-    }
+    verdict = refine_next(ratio, prev, it, c->max_refine);
+    if (verdict != kRefineMore) break;
     prev = ratio;
   }
-  if (!ok && ratio <= 1e-9) ok = true;
+  const bool ok = verdict == kRefineDone;
   *resid = ratio;
   if (ok) {
     XOD_HIP(hipMemcpyAsync(c->x, c->dx, NSb, hipMemcpyDeviceToDevice, c->stream));

@@ -188,7 +188,7 @@ xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double
     const hipStream_t st = g.st;
     const ManyCols acc{d_args + g.base};
     double *ratio = d_ratio + g.roff;
-    bool ok = false;
+    RefineNext verdict = kRefineFallback;
     double prev = 1e300;
     g.ratio = 1e300;
     for (int it = 1; it <= 10; ++it) {
@@ -200,17 +200,11 @@ xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double
       XOD_HIP(hipStreamSynchronize(st));
       g.ratio = h_rmax[gi];
       g.iters = it;
-      if (g.ratio <= options().refine_tol) {
-        ok = true;
-        break;
-      }
-      if (g.ratio > 0.5 * prev) {
-        ok = g.ratio <= 1e-9;
-        break;
-      }
+      verdict = refine_next(g.ratio, prev, it, 10);
+      if (verdict != kRefineMore) break;
       prev = g.ratio;
     }
-    if (!ok && g.ratio <= 1e-9) ok = true;
+    const bool ok = verdict == kRefineDone;
     if (ok) {
       for (int j = 0; j < g.nc; ++j) {
         xod_column *c = cols[(*g.idx)[j]];

@@ -8,7 +8,7 @@
 //   k_resid    x = s * (F - M delta),  M delta = delta/dt - J_chem delta
 //              - (trl delta_{k-1} + trd delta_k + tru delta_{k+1})
 //   k_scale    x = s * F
-//   k_axpy     delta += x, per-layer max|x| / max|delta|
+//   k_axpy     delta += x, per-layer componentwise correction size
 #include "xod_internal.h"
 
 namespace xod {
@@ -73,9 +73,16 @@ __global__ void __launch_bounds__(256) k_scale(Acc acc) {
   c.x[o] = c.rs[(size_t)k * c.ld + y] * c.f[o];
 }
 
-// delta += x; ratio[k] = max|x_k| / max|delta_k| (0 if delta_k == 0).
+// delta += x, then the componentwise size of the correction x in layer k,
+//   ratio[k] = max_i |x_i| / (rtol |n_i + delta_i| + atol max_j |delta_j|)
+// over the components whose new density n_i + delta_i exceeds y_floor times
+// the layer's gas density (0 if there is none).  ratio <= 1 means every
+// such component moved by at most rtol of its new value, or by atol of the
+// layer's largest increment (the absolute floor below which an FP64 solve
+// fixes no component either).
 template <class Acc>
-__global__ void __launch_bounds__(256) k_axpy(Acc acc, double *ratio) {
+__global__ void __launch_bounds__(256) k_axpy(Acc acc, double *ratio, double rtol, double atol,
+                                              double y_floor) {
   const ColArgs &c = acc(blockIdx.y);
   const int k = blockIdx.x;
   double *delta = c.dx;
@@ -84,29 +91,40 @@ __global__ void __launch_bounds__(256) k_axpy(Acc acc, double *ratio) {
     if (threadIdx.x == 0) *rk = 0.0;
     return;
   }
-  __shared__ double s1[256], s2[256];
-  double m1 = 0.0, m2 = 0.0;
+  __shared__ double red[256];
+  double m = 0.0;
   for (int y = threadIdx.x; y < c.S; y += blockDim.x) {
     const size_t o = (size_t)k * c.S + y;
     const double d = delta[o] + c.x[o];
     delta[o] = d;
-    m1 = fmax(m1, fabs(c.x[o]));
-    m2 = fmax(m2, fabs(d));
+    m = fmax(m, fabs(d));
   }
-  s1[threadIdx.x] = m1;
-  s2[threadIdx.x] = m2;
+  red[threadIdx.x] = m;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + o]);
-      s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + o]);
-    }
+    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    const double r = s2[0] > 0.0 ? s1[0] / s2[0] : (s1[0] > 0.0 ? 1.0 : 0.0);
-    *rk = isfinite(r) ? r : 1e300;
+  const double floor_abs = atol * red[0];
+  const double sig = y_floor * c.ngas[k];
+  __syncthreads();
+  double q = 0.0;
+  for (int y = threadIdx.x; y < c.S; y += blockDim.x) {
+    const size_t o = (size_t)k * c.S + y;
+    const double nn = fabs(c.n[o] + delta[o]);
+    if (nn > sig) {
+      const double den = rtol * nn + floor_abs;
+      const double xi = fabs(c.x[o]);
+      q = fmax(q, den > 0.0 ? xi / den : (xi > 0.0 ? 1e300 : 0.0));
+    }
   }
+  red[threadIdx.x] = q;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *rk = isfinite(red[0]) ? red[0] : 1e300;
 }
 
 __global__ void k_maxreduce(const double *v, int n, double *out) {
@@ -141,7 +159,8 @@ hipError_t launch_scale(const Acc &acc, int ncols, int maxN, int maxS, hipStream
 template <class Acc>
 hipError_t launch_axpy_ratio(const Acc &acc, int ncols, int maxN, double *ratio, double *out,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_axpy<Acc>, dim3(maxN, ncols), dim3(256), 0, s, acc, ratio);
+  hipLaunchKernelGGL(k_axpy<Acc>, dim3(maxN, ncols), dim3(256), 0, s, acc, ratio,
+                     options().refine_tol, options().refine_atol, 1e-30);
   hipLaunchKernelGGL(k_maxreduce, dim3(1), dim3(256), 0, s, ratio, maxN * ncols, out);
   return hipGetLastError();
 }

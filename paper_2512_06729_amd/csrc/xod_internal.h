@@ -90,7 +90,8 @@ struct Options {
   int update32_min = 200; // ... for launches of at least this many (block, strip) pairs
   int outer = 32;         // Gauss-Jordan outer panel width (32: unblocked)
   int outer_nmat = 1;     // ... for launches of at least this many blocks
-  double refine_tol = 1e-10;   // mixed refinement: converged at this correction ratio
+  double refine_tol = 1e-7;    // mixed refinement: relative size of the last correction
+  double refine_atol = 1e-14;  // ... and its floor, relative to the layer's largest increment
   int gemm_large = 1;     // 128 x 128 product tiles for large batches
   int gemm_k = 32;        // K step of the block products staged in LDS (16 or 32)
   int panel_sync = 2;     // barriers per Gauss-Jordan column (1 or 2)
@@ -129,8 +130,21 @@ hipError_t launch_factor_mixed(const Acc &acc, int ncols, int maxN, int ld, hipS
 // Refinement (mixed precision), per column of the launch:
 //   residual  x = rs * (f - M dx)   (dw: the column's w buffer as scratch)
 //   scale     x = rs * f
-//   axpy      dx += x, ratio[col * maxN + k] = max|x_k| / max|dx_k|, and
-//             out[0] = the maximum over all columns and layers
+//   axpy      dx += x, ratio[col * maxN + k] = the componentwise size of x
+//             in layer k, max_i |x_i| / (rtol |n_i + dx_i| + atol max|dx_k|)
+//             over the components with mixing ratio above 1e-30 (rtol, atol
+//             from the options), and out[0] = the maximum over all columns
+//             and layers
+// A refinement has converged at a size <= 1; refine_next() decides.
+enum RefineNext { kRefineMore = 0, kRefineDone, kRefineFallback };
+inline RefineNext refine_next(double q, double q_prev, int it, int max_it) {
+  if (q <= 1.0) return kRefineDone;
+  // stalled (the corrections no longer shrink: the FP64 residual's rounding
+  // floor) or out of iterations: accept within ten times the tolerance,
+  // otherwise solve again in FP64
+  if (q > 0.5 * q_prev || it >= max_it) return q <= 10.0 ? kRefineDone : kRefineFallback;
+  return kRefineMore;
+}
 template <class Acc>
 hipError_t launch_residual(const Acc &acc, int ncols, int maxN, int maxS, int maxR,
                            hipStream_t s);

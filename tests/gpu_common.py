@@ -91,3 +91,35 @@ def assert_state_agrees(n, ref, delta, rel=1e-10, frac=1e-6):
            f"layer max |delta| {lm[k, 0]:.3e}")
     print(msg)
     assert worst <= 1.0, msg
+
+
+def block_kappa(prob, n, dt):
+    """Largest 1-norm condition number over the layers of the diagonal step
+    blocks B_k = I/dt - dF_k/dn_k at state n (the oracle's blocks), from
+    LAPACK's estimator on each block's LU factors."""
+    import scipy.linalg
+    B, a, c = prob.step_matrix(n, dt)
+    worst = 1.0
+    for k in range(B.shape[0]):
+        lu, _ = scipy.linalg.lu_factor(B[k])
+        rcond, info = scipy.linalg.lapack.dgecon(lu, np.abs(B[k]).sum(axis=0).max(), norm="1")
+        worst = max(worst, 1.0 / rcond if rcond > 0 else np.inf)
+    return float(worst)
+
+
+def assert_state_agrees_kappa(n, ref, delta, kappa, rel=1e-10, c=10.0):
+    """A stepped state held to the forward-error bound of a backward-stable
+    solve: per layer, |n - ref| <= rel |delta| + c kappa eps max_layer |delta|
+    (+ the rounding of n0 + delta).  The per-layer floor of
+    assert_state_agrees is this bound at kappa ~ 1; with the stiff blocks of
+    large steps the floor grows with the blocks' condition number kappa."""
+    lm = np.abs(delta).max(axis=-1, keepdims=True)
+    allowed = rel * np.abs(delta) + c * kappa * EPS * lm + 4 * EPS * np.abs(ref)
+    ratio = np.abs(n - ref) / (allowed + 1e-300)
+    k, y = np.unravel_index(int(np.argmax(ratio)), ratio.shape)
+    worst = float(ratio[k, y])
+    msg = (f"state disagreement {worst:.3e} x allowed (kappa {kappa:.2e}) at layer {k} "
+           f"species {y}: n {n[k, y]:.17e} ref {ref[k, y]:.17e} delta {delta[k, y]:.3e} "
+           f"layer max |delta| {lm[k, 0]:.3e}")
+    print(msg)
+    assert worst <= 1.0, msg

@@ -8,9 +8,11 @@ between steps), so the errors are those a user of three steps sees.  The
 per-species figure is the largest relative error over the layers of the
 species' densities with mixing ratio above 1e-30.
 
-Asserted: FP64 at the per-layer solve tolerance of every other parity test
-(increments to 1e-9 relative once above 1e-6 of the layer's largest), and
-mixed precision within 1e-6 relative on every mixing ratio above 1e-30.
+Asserted: each FP64 step, against the oracle's step from the same state,
+within the forward-error bound of a backward-stable solve (increments to
+1e-9 relative, plus ten times the diagonal blocks' condition number times
+the unit roundoff of the layer's largest increment), and mixed precision
+within 1e-6 relative on every mixing ratio above 1e-30.
 """
 
 import numpy as np
@@ -78,7 +80,8 @@ def test_config3_three_steps_per_species(reference, name, precision, solver):
             # the step from the GPU's own previous state, against the oracle's
             # step from the same state (the trajectory error above is the sum)
             ref_i, d_i = integrate.be_step(prob, prev, DT) if i else (states[0], deltas[0])
-            G.assert_state_agrees(n, ref_i, d_i, rel=1e-9)
+            G.assert_state_agrees_kappa(n, ref_i, d_i, G.block_kappa(prob, prev, DT),
+                                        rel=1e-9)
         else:
             assert err.max() <= 1e-6, err.max()
         prev = n
