@@ -170,7 +170,7 @@ xod_status xod_column_grid(const xod_column *col, double *ngas, double *tau,
  * xod_integrate_to_steady_state on this column (default XOD_SOLVER_THOMAS).
  * XOD_SOLVER_CR allocates its workspace on first selection (XOD_ENOMEM if
  * it does not fit).  The explicit-block calls xod_btd_factor / xod_btd_solve
- * always use block Thomas.  The FP64 fallback of a mixed-precision solve
+ * use the column's solver too.  The FP64 fallback of a mixed-precision solve
  * uses the column's solver in FP64 (a mixed column with XOD_SOLVER_CR holds
  * FP64 and FP32 cyclic-reduction workspaces). */
 xod_status xod_column_set_solver(xod_column *col, xod_solver solver);
@@ -196,24 +196,56 @@ xod_status xod_jacobian(xod_column *col, const double *kf, const double *kr,
                         const double *n, double dt, double *B, double *a,
                         double *c, int32_t ld);
 
-/* Block Thomas elimination in place (FP64).  For k = 0..N-1 the Schur
- * complement D'_k = B_k - diag(a_k) D'_{k-1}^{-1} diag(c_{k-1}) is inverted
- * by Gauss-Jordan elimination with partial pivoting (implicit row
- * pivoting: the unused row of largest magnitude, compared to 42 mantissa
- * bits, lowest row among equals).  On return block k holds W_k and piv[k*ld+j]
- * the row chosen as pivot for column j, such that
- *   (D'_k^{-1})[j][i] = W_k[piv[j]][q(i)],  q = inverse permutation of piv.
+/* Factorisation of the block-tridiagonal system M = (B, a, c) of
+ * xod_jacobian (Section 2.1: the step matrix I/dt - dF/dn, S x S diagonal
+ * blocks, diagonal couplings; B padded with the identity), in precision
+ * `prec` with the column's solver (xod_column_set_solver):
+ *   XOD_FP64 + block Thomas: in place.  For k = 0..N-1 the Schur complement
+ *     D'_k = B_k - diag(a_k) D'_{k-1}^{-1} diag(c_{k-1}) is inverted by
+ *     Gauss-Jordan elimination with partial pivoting (implicit row pivoting:
+ *     the unused row of largest magnitude, compared to 42 mantissa bits,
+ *     lowest row among equals).  On return block k holds W_k and
+ *     piv[k*ld+j] the row chosen as pivot for column j, such that
+ *     (D'_k^{-1})[j][i] = W_k[piv[j]][q(i)], q = inverse permutation of piv.
+ *   XOD_FP64 + cyclic reduction, and XOD_MIXED with either solver: B, a, c
+ *     are read only and piv is not used (may be NULL).  The factors are held
+ *     in the column's own workspace until its next factor, step, solver
+ *     switch or batch: FP64 factors of a copy of the system, or, in
+ *     XOD_MIXED, FP32 factors of the row-scaled system (each row of B, a, c
+ *     divided by its largest magnitude), the FP64 B, a, c serving the
+ *     refinement of xod_btd_solve (the caller keeps them unchanged until
+ *     then).  A column created in FP64 allocates its FP32 blocks (N ld^2
+ *     floats) on the first mixed factorisation.
  * XOD_ESINGULAR (layer and column in xod_last_error) on a zero or
  * non-finite pivot.  Synchronises the stream to read the singular flag. */
 xod_status xod_btd_factor(xod_column *col, double *B, const double *a,
-                          const double *c, int32_t ld, int32_t *piv);
+                          const double *c, int32_t ld, int32_t *piv,
+                          xod_precision prec);
 
-/* Forward / backward substitution with factors from xod_btd_factor:
- * g'_k = g_k - a_k * D'^{-1}_{k-1} g'_{k-1};
- * x_k = D'^{-1}_k (g'_k - c_k * x_{k+1}).  rhs [N*S] is overwritten by x. */
+/* Solve M x = rhs with the factorisation of xod_btd_factor (same column and
+ * the same B, a, c, piv pointers), rhs [N*S] overwritten by x:
+ *   block Thomas FP64: g'_k = g_k - a_k * D'^{-1}_{k-1} g'_{k-1};
+ *     x_k = D'^{-1}_k (g'_k - c_k * x_{k+1}) with the factors in B, piv;
+ *   cyclic reduction FP64: substitution through the held levels;
+ *   XOD_MIXED: x from the FP32 factors, then up to max_refine refinements
+ *     x += M32^{-1} (rhs - M x) with the residual in FP64 from the caller's
+ *     B, a, c, stopping once no component moves by more than rtol of |x_i|
+ *     or atol of its layer's largest |x| (the rule and options of xod_step);
+ *     if the corrections stall above ten times that, or max_refine runs
+ *     out first, the system is refactored and solved in FP64 (max_refine 0:
+ *     the FP32 solution as it is).
+ * max_refine in 0..100 (ignored in FP64).  XOD_EINVAL when the column holds
+ * no factorisation of these B, a, c (cyclic reduction and mixed precision
+ * need xod_btd_factor first).  Mixed solves synchronise the stream. */
 xod_status xod_btd_solve(xod_column *col, const double *B, const double *a,
                          const double *c, int32_t ld, const int32_t *piv,
-                         double *rhs);
+                         double *rhs, int32_t max_refine);
+
+/* Refinements, FP64 fallback (0/1) and the last componentwise correction
+ * size of the column's last xod_btd_solve (0 for FP64 solves); any pointer
+ * may be NULL. */
+xod_status xod_btd_solve_info(const xod_column *col, int32_t *refine_iters,
+                              int32_t *fp64_fallback, double *correction);
 
 /* One linearly implicit backward-Euler step of the column state:
  * solve (I/dt - J(n)) delta = F(n), n <- n + delta (no clipping).  In
@@ -296,13 +328,27 @@ xod_status xod_step_newton(xod_column *col, double dt, int32_t iters, xod_step_s
 xod_status xod_step_bdf2(xod_column *col, double dt, xod_step_stats *st);
 
 /* Adaptive driver to steady state; each step is a backward-Euler step, or
- * with method 1 a ROS2 step (xod_step_ros2), under the same control:
+ * with method 1 a ROS2 step (xod_step_ros2), or with method 2 a
+ * backward-Euler step on a step matrix kept across steps (below), under the
+ * same control:
  *   reject (dt /= 2) if the step is not finite or a species whose mixing
  *   ratio exceeded y_sig turns negative; accept otherwise, clip negatives to
  *   zero and set dt *= 2 / 1.2 / 0.7 for a control change c < 0.5 / < 0.9 /
  *   otherwise, c = max |n1 - n0| / max(n0, n1) over mixing ratios > y_sig;
  *   converged when max |dn| / n over mixing ratios > y_floor is < tol_rel
  *   with dt >= the mixing time (Section 3.2), or when t >= t_end.
+ * Method 2 (FP64 columns) amortises factorisations after the corrector of
+ * the DLSODES family Section 2.1 names: a step of size dt solves
+ * n1 - n - dt F(n1) = 0.  With a fresh factorisation of M = I/dt - J(n) it
+ * takes the first Newton iterate (the plain linearly implicit step); with
+ * a held one, factored at an earlier state and step dt_f, it iterates
+ * Delta += M_f^-1 (F(n + Delta) - Delta/dt) from Delta = 0 until a
+ * correction is at most 1e-3 of every new density with mixing ratio above
+ * y_floor (at most 4 corrections; one not below 0.3 of the previous ends
+ * the attempt, which is retried with a fresh factorisation, not rejected).
+ * A factorisation serves while dt/dt_f is in [1/1.3, 1.3], for at most 20
+ * accepted steps.  res->factorizations counts them (every attempt for
+ * methods 0 and 1), res->newton_iters the corrections on held ones.
  * Zero fields take the defaults in brackets. */
 typedef struct {
   double tol_rel;    /* [1e-4]  */
@@ -313,17 +359,42 @@ typedef struct {
   int32_t max_steps; /* [5000]  */
   int32_t max_consec_rejects; /* [30] */
   int32_t use_mix_rule;       /* 0/1 [1 if the struct is NULL] */
-  int32_t method;             /* 0 backward Euler [0], 1 ROS2 (FP64 columns) */
+  int32_t method;             /* 0 backward Euler [0], 1 ROS2, 2 backward
+                                 Euler with factorisations kept across steps
+                                 (1 and 2: FP64 columns) */
 } xod_ss_opts;
 typedef struct {
   double t, dt, clipped;
   int64_t steps, rejects;
   int32_t converged;
-  int32_t pad_;
+  int32_t factorizations;     /* step-matrix factorisations */
+  int64_t newton_iters;       /* method 2: corrections on held factorisations */
 } xod_ss_result;
 xod_status xod_integrate_to_steady_state(xod_column *col,
                                          const xod_ss_opts *opts,
                                          xod_ss_result *res);
+
+/* nsteps backward-Euler steps of one size dt (no clipping, no rejection)
+ * keeping the step matrix across steps when reuse = 1: the chord /
+ * modified-Newton corrector of the DLSODES family Section 2.1 names.  A
+ * step on a fresh factorisation of M = I/dt - J(n) takes the first Newton
+ * iterate (the linearly implicit step of xod_step); a step on the held
+ * factorisation (of an earlier state) solves n1 - n - dt F(n1) = 0 by
+ * Delta += M_f^-1 (F(n + Delta) - Delta/dt) from Delta = 0 until a
+ * correction is at most 1e-3 of every new density with mixing ratio above
+ * 1e-10; a correction not below half the previous one, a non-finite iterate
+ * or 4 corrections without convergence make the step start again on a
+ * fresh factorisation, as does a factorisation that has served 20 steps.
+ * reuse = 0: every step is an xod_step.  reuse = 1 needs an FP64 column.
+ * XOD_ENONFINITE stops at the first step whose result is not finite (the
+ * state is that of the steps before it).  st may be NULL. */
+typedef struct {
+  int64_t steps;            /* steps taken                                  */
+  int64_t factorizations;   /* step-matrix factorisations                   */
+  int64_t newton_iters;     /* corrections on held factorisations           */
+} xod_reuse_stats;
+xod_status xod_integrate_fixed_dt(xod_column *col, double dt, int32_t nsteps,
+                                  int32_t reuse, xod_reuse_stats *st);
 
 /* Copy of the last error message of this thread (always NUL-terminated). */
 xod_status xod_last_error(char *buf, size_t len);

@@ -14,7 +14,7 @@ from . import photolysis
 from . import rates as rates_mod
 from .rhs import rhs
 from .jacobian import step_matrix
-from .linalg import btd, dense_solve
+from .linalg import btd, btd_factor, btd_solve, dense_solve
 
 
 class Problem:
@@ -208,3 +208,149 @@ def steady_state(prob, n0, tol_rel=1.0e-4, y_floor=1.0e-30, y_sig=1.0e-10,
         dt *= 2.0 if c < 0.5 else (1.2 if c < 0.9 else 0.7)
     return SteadyResult(n=n, t=t, dt=dt, steps=steps, rejects=rejects,
                         converged=converged, clipped=clipped, history=hist)
+
+
+def newton_held(prob, n, dt, held, newton_tol=1.0e-3, max_newton=4, y_sig=1.0e-10):
+    """Modified Newton on the backward-Euler equation n1 - n - dt F(n1) = 0
+    with a step matrix factored earlier (held = (factors, a, c) of
+    step_matrix(n_f, dt_f)): from Delta = 0,
+        Delta += M_f^-1 (F(n + Delta) - Delta / dt),
+    until a correction is at most newton_tol of every new density whose
+    mixing ratio exceeds y_sig (converged), or a correction is not below half
+    the previous one, or max_newton corrections are spent, or the iterate is
+    not finite (failed).  Returns (Delta, converged, corrections)."""
+    ngas = prob.grid.ngas[:, None]
+    fac, a, c = held
+    delta = np.zeros_like(n)
+    prev = np.inf
+    for it in range(1, max_newton + 1):
+        resid = prob.rhs(n + delta) - delta / dt
+        corr = btd_solve(fac, a, c, resid)
+        delta = delta + corr
+        n1 = n + delta
+        if not np.all(np.isfinite(n1)):
+            return delta, False, it
+        sig = np.abs(n1) > y_sig * ngas
+        size = float(np.max(np.abs(corr[sig]) / np.abs(n1[sig]))) if sig.any() else 0.0
+        if size <= newton_tol:
+            return delta, True, it
+        if size > 0.5 * prev:
+            return delta, False, it
+        prev = size
+    return delta, False, max_newton
+
+
+def fixed_dt_reuse(prob, n0, dt, nsteps, newton_tol=1.0e-3, max_newton=4, max_age=20,
+                   y_sig=1.0e-10):
+    """nsteps backward-Euler steps of one size dt that keep the step matrix
+    across steps (the chord / modified-Newton corrector of the DLSODES
+    family): a step on a fresh factorisation of M = I/dt - J(n) takes the
+    first Newton iterate (the linearly implicit step); a step on the held
+    factorisation (of an earlier state) iterates newton_held to convergence;
+    when that fails, or the factorisation has served max_age steps, the step
+    is taken again on a fresh one.  No clipping, no rejection.  Returns
+    (n, factorizations, newton corrections)."""
+    n = n0.copy()
+    held = None
+    age = nfact = ncorr = 0
+    for _ in range(nsteps):
+        if held is not None and age < max_age:
+            delta, ok, it = newton_held(prob, n, dt, held, newton_tol, max_newton, y_sig)
+            ncorr += it
+            if ok:
+                n = n + delta
+                age += 1
+                continue
+        B, a, c = prob.step_matrix(n, dt)
+        held = (btd_factor(B, a, c), a, c)
+        nfact += 1
+        age = 1
+        n = n + btd_solve(held[0], a, c, prob.rhs(n))
+    return n, nfact, ncorr
+
+
+@dataclass
+class ReuseResult(SteadyResult):
+    factorizations: int = 0
+    newton_iters: int = 0
+
+
+def steady_state_reuse(prob, n0, tol_rel=1.0e-4, y_floor=1.0e-30, y_sig=1.0e-10,
+                       t_end=1.0e12, dt0=1.0e-8, max_steps=5000, max_consec_rejects=30,
+                       use_mix_rule=True, newton_tol=1.0e-3, max_newton=4, max_age=20,
+                       reuse_ratio=1.3):
+    """The adaptive steady-state driver with the step matrix kept across
+    steps, after the corrector of the DLSODES family Section 2.1 names
+    (modified Newton on the backward-Euler equation, one factorisation
+    serving several steps).
+
+    * A step of size dt at state n solves n1 - n - dt F(n1) = 0.  With a
+      freshly factored matrix M = I/dt - J(n) it takes the first Newton
+      iterate, Delta = M^-1 F(n): the linearly implicit step of the plain
+      driver.  With a held matrix (factored at an earlier state and step
+      size dt_f) it iterates Delta += M_f^-1 (F(n + Delta) - Delta/dt) from
+      Delta = 0 (newton_held: converged once a correction is at most
+      newton_tol of every new density with mixing ratio above y_sig; a
+      correction not below half the previous one, a non-finite iterate or
+      max_newton corrections end the attempt), and a failed attempt is
+      retried with a fresh matrix (not a rejection).
+    * The held matrix serves while dt / dt_f lies in [1/reuse_ratio,
+      reuse_ratio] and it has served fewer than max_age steps; otherwise a
+      new one is factored at the current state and dt.
+    * Acceptance, clipping, the dt rule and the convergence test are those
+      of steady_state (a rejection halves dt, so it refactors).
+    """
+    ngas = prob.grid.ngas[:, None]
+    mix = prob.grid.mix_time if use_mix_rule else 0.0
+    n = n0.copy()
+    t, dt = 0.0, dt0
+    steps = rejects = consec = nfact = nnewton = 0
+    clipped = 0.0
+    hist = []
+    converged = False
+    held = None            # (factors, a, c, dt_f, age)
+    while steps < max_steps:
+        fresh = held is None or not (1.0 / reuse_ratio <= dt / held[3] <= reuse_ratio) \
+            or held[4] >= max_age
+        if fresh:
+            B, a, c = prob.step_matrix(n, dt)
+            held = [btd_factor(B, a, c), a, c, dt, 0]
+            nfact += 1
+            delta = btd_solve(held[0], a, c, prob.rhs(n))
+            ok = bool(np.all(np.isfinite(delta)))
+        else:
+            delta, ok, it = newton_held(prob, n, dt, held[:3], newton_tol, max_newton, y_sig)
+            nnewton += it
+            if not ok:
+                held = None        # retry this step with a fresh matrix
+                continue
+        n_new = n + delta
+        sig = n > y_sig * ngas
+        if not ok or not np.all(np.isfinite(n_new)) or np.any(sig & (n_new < 0.0)):
+            rejects += 1
+            consec += 1
+            dt *= 0.5
+            if consec > max_consec_rejects:
+                break
+            continue
+        consec = 0
+        held[4] += 1
+        neg = n_new < 0.0
+        clipped += float(-n_new[neg].sum())
+        n_new[neg] = 0.0
+        keep = n_new > y_floor * ngas
+        rel = float(np.max(np.abs(n_new[keep] - n[keep]) / n_new[keep])) if keep.any() else 0.0
+        ctl = n_new > y_sig * ngas
+        big = np.maximum(n_new[ctl], n[ctl])
+        c = float(np.max(np.abs(n_new[ctl] - n[ctl]) / big)) if ctl.any() else 0.0
+        t += dt
+        steps += 1
+        n = n_new
+        hist.append((t, dt, rel, c))
+        if (rel < tol_rel and dt >= mix) or t >= t_end:
+            converged = True
+            break
+        dt *= 2.0 if c < 0.5 else (1.2 if c < 0.9 else 0.7)
+    return ReuseResult(n=n, t=t, dt=dt, steps=steps, rejects=rejects, converged=converged,
+                       clipped=clipped, history=hist, factorizations=nfact,
+                       newton_iters=nnewton)

@@ -86,13 +86,22 @@ class SSOpts(ctypes.Structure):
                 ("method", c_int32)]
 
 
+class ReuseStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("factorizations", ctypes.c_int64),
+                ("newton_iters", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class SSResult(ctypes.Structure):
     _fields_ = [("t", c_double), ("dt", c_double), ("clipped", c_double),
                 ("steps", ctypes.c_int64), ("rejects", ctypes.c_int64),
-                ("converged", c_int32), ("pad_", c_int32)]
+                ("converged", c_int32), ("factorizations", c_int32),
+                ("newton_iters", ctypes.c_int64)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 def _sig(name, *args):
@@ -119,9 +128,10 @@ _f = {
     "xod_jacobian": _sig("xod_jacobian", c_void_p, c_void_p, c_void_p, c_void_p, c_double,
                          c_void_p, c_void_p, c_void_p, c_int32),
     "xod_btd_factor": _sig("xod_btd_factor", c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
-                           c_void_p),
+                           c_void_p, c_int32),
     "xod_btd_solve": _sig("xod_btd_solve", c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
-                          c_void_p, c_void_p),
+                          c_void_p, c_void_p, c_int32),
+    "xod_btd_solve_info": _sig("xod_btd_solve_info", c_void_p, P_int, P_int, P_dbl),
     "xod_step": _sig("xod_step", c_void_p, c_double, ctypes.POINTER(StepStats)),
     "xod_step_frozen": _sig("xod_step_frozen", c_void_p, c_double, ctypes.POINTER(StepStats)),
     "xod_step_ros2": _sig("xod_step_ros2", c_void_p, c_double, ctypes.POINTER(StepStats)),
@@ -133,6 +143,8 @@ _f = {
     "xod_integrate_to_steady_state": _sig("xod_integrate_to_steady_state", c_void_p,
                                           ctypes.POINTER(SSOpts), ctypes.POINTER(SSResult)),
     "xod_last_error": _sig("xod_last_error", ctypes.c_char_p, ctypes.c_size_t),
+    "xod_integrate_fixed_dt": _sig("xod_integrate_fixed_dt", c_void_p, c_double, c_int32,
+                                   c_int32, ctypes.POINTER(ReuseStats)),
     "xod_set_option": _sig("xod_set_option", ctypes.c_char_p, ctypes.c_int64),
     "xod_column_set_photolysis_spectrum": _sig("xod_column_set_photolysis_spectrum", c_void_p,
                                                ctypes.c_int32, ctypes.c_int32, c_void_p,
@@ -405,13 +417,23 @@ def xod_jacobian(col, kf, kr, n, dt, B, a, c):
                               _dev(a), _dev(c), col.ld))
 
 
-def xod_btd_factor(col, B, a, c, piv):
-    _check(_f["xod_btd_factor"](col.handle, _dev(B), _dev(a), _dev(c), col.ld, _dev(piv)))
+def xod_btd_factor(col, B, a, c, piv, precision=XOD_FP64):
+    _check(_f["xod_btd_factor"](col.handle, _dev(B), _dev(a), _dev(c), col.ld,
+                                _dev(piv) if piv is not None else None, int(precision)))
 
 
-def xod_btd_solve(col, B, a, c, piv, rhs):
-    _check(_f["xod_btd_solve"](col.handle, _dev(B), _dev(a), _dev(c), col.ld, _dev(piv),
-                               _dev(rhs)))
+def xod_btd_solve(col, B, a, c, piv, rhs, max_refine=10):
+    _check(_f["xod_btd_solve"](col.handle, _dev(B), _dev(a), _dev(c), col.ld,
+                               _dev(piv) if piv is not None else None, _dev(rhs),
+                               int(max_refine)))
+
+
+def xod_btd_solve_info(col):
+    """(refinements, FP64 fallback, last correction size) of the last solve."""
+    it, fb, size = c_int32(), c_int32(), c_double()
+    _check(_f["xod_btd_solve_info"](col.handle, ctypes.byref(it), ctypes.byref(fb),
+                                    ctypes.byref(size)))
+    return it.value, fb.value, size.value
 
 
 def xod_step(col, dt):
@@ -451,7 +473,8 @@ def xod_step_bdf2(col, dt):
 def xod_integrate_to_steady_state(col, tol_rel=0.0, y_floor=0.0, y_sig=0.0, t_end=0.0,
                                   dt0=0.0, max_steps=0, max_consec_rejects=0,
                                   use_mix_rule=1, check=True, method=0):
-    """method 0: backward-Euler steps, 1: ROS2 steps (FP64 columns)."""
+    """method 0: backward-Euler steps, 1: ROS2 steps, 2: backward-Euler steps
+    on step matrices kept across steps (1 and 2: FP64 columns)."""
     o = SSOpts(tol_rel, y_floor, y_sig, t_end, dt0, max_steps, max_consec_rejects,
                use_mix_rule, method)
     r = SSResult()
@@ -461,6 +484,15 @@ def xod_integrate_to_steady_state(col, tol_rel=0.0, y_floor=0.0, y_sig=0.0, t_en
     out = r.as_dict()
     out["status"] = st
     return out
+
+
+def xod_integrate_fixed_dt(col, dt, nsteps, reuse=1):
+    """nsteps backward-Euler steps of size dt, keeping the step matrix across
+    steps (modified Newton) when reuse = 1; returns the step statistics."""
+    st = ReuseStats()
+    _check(_f["xod_integrate_fixed_dt"](col.handle, float(dt), int(nsteps), int(reuse),
+                                        ctypes.byref(st)))
+    return st.as_dict()
 
 
 class Batch:

@@ -122,6 +122,11 @@ extern "C" xod_status xod_set_option(const char *name, int64_t value) {
     options().panel_sync = (int)value;
     return XOD_OK;
   }
+  if (std::strcmp(name, "panel_defer") == 0) {
+    XOD_CHECK(value == 0 || value == 1, "xod_set_option: panel_defer must be 0 or 1");
+    options().panel_defer = (int)value;
+    return XOD_OK;
+  }
   if (std::strcmp(name, "gemm_k") == 0) {
     XOD_CHECK(value == 16 || value == 32, "xod_set_option: gemm_k must be 16 or 32");
     options().gemm_k = (int)value;
@@ -130,6 +135,11 @@ extern "C" xod_status xod_set_option(const char *name, int64_t value) {
   if (std::strcmp(name, "refine_tol_exp") == 0) {
     XOD_CHECK(value >= 3 && value <= 15, "xod_set_option: refine_tol_exp must be in 3..15");
     options().refine_tol = std::pow(10.0, -(double)value);
+    return XOD_OK;
+  }
+  if (std::strcmp(name, "refine64") == 0) {
+    XOD_CHECK(value >= 0 && value <= 10, "xod_set_option: refine64 must be in 0..10");
+    options().refine64 = (int)value;
     return XOD_OK;
   }
   if (std::strcmp(name, "refine_atol_exp") == 0) {
@@ -185,12 +195,14 @@ extern "C" xod_status xod_get_option(const char *name, int64_t *value) {
       {"gemm", o.gemm_mfma},           {"gemm_large", o.gemm_large},
       {"gemm_k", o.gemm_k},            {"outer", o.outer},
       {"panel_sync", o.panel_sync},    {"gemm_lib", o.gemm_lib},
+      {"panel_defer", o.panel_defer},
       {"outer_nmat", o.outer_nmat},    {"update32", o.update32},
       {"update32_min", o.update32_min},
       {"graph", o.graph},              {"profile", o.profile},
       {"profile_every", o.profile_every},
       {"refine_tol_exp", (int64_t)std::lround(-std::log10(o.refine_tol))},
       {"refine_atol_exp", (int64_t)std::lround(-std::log10(o.refine_atol))},
+      {"refine64", o.refine64},
   };
   for (const Entry &e : entries)
     if (std::strcmp(name, e.name) == 0) {
@@ -438,11 +450,7 @@ extern "C" xod_status xod_column_create(const xod_network *net, const xod_profil
   XOD_TRY(calloc_(c, &c->rstep, NL));
   XOD_TRY(calloc_(c, &c->flag, 4));
   XOD_TRY(calloc_(c, &c->B, NLL));
-  if (prec == XOD_MIXED) {
-    XOD_TRY(calloc_(c, &c->Bf, NLL));
-    XOD_TRY(calloc_(c, &c->a64, NL));
-    XOD_TRY(calloc_(c, &c->c64, NL));
-  }
+  if (prec == XOD_MIXED) XOD_TRY(calloc_(c, &c->Bf, NLL));
   XOD_TRY(calloc_(c, &c->ratio, (size_t)N));
   XOD_TRY(calloc_(c, &c->rmax, 1));
   XOD_TRY(calloc_(c, &c->partial, (size_t)kUpdBlocks * kNStat));
@@ -726,21 +734,51 @@ extern "C" xod_status xod_column_set_solver(xod_column *col, xod_solver solver) 
       col->cr32 = p.release();
     }
   }
-  if (col->solver != solver) col->fact_dt = 0.0;
+  if (col->solver != solver) {
+    col->fact_dt = 0.0;
+    col->btd.valid = false;
+  }
   col->solver = solver;
   return XOD_OK;
 }
 
-extern "C" xod_status xod_btd_factor(xod_column *col, double *B, const double *av,
-                                     const double *cv, int32_t ld, int32_t *piv) {
-  XOD_CHECK(col && B && av && cv && piv, "xod_btd_factor: null argument");
-  XOD_CHECK(ld == col->ld, "xod_btd_factor: ld must equal the network's padded size");
-  ColArgs a = col->args();
-  a.B = B;
-  a.a = const_cast<double *>(av);
-  a.c = const_cast<double *>(cv);
-  a.piv = piv;
-  XOD_HIP(launch_factor_fp64(OneCol{a}, 1, col->N, col->ld, col->stream));
+namespace {
+
+// FP32 blocks (and the single-precision cyclic-reduction plan) of a column
+// that was created in FP64, allocated on first use by a mixed explicit factor.
+xod_status ensure_fp32_blocks(xod_column *col) {
+  if (!col->Bf) {
+    float *p = nullptr;
+    XOD_TRY(calloc_(col, &p, (size_t)col->N * col->ld * col->ld));
+    col->Bf = p;
+  }
+  if (col->solver == XOD_SOLVER_CR && !col->cr32) {
+    std::unique_ptr<xod::CrPlan<float>> p(new xod::CrPlan<float>());
+    const xod_status st = p->build(col);
+    if (st != XOD_OK) return st == XOD_EHIP ? XOD_ENOMEM : st;
+    col->cr32 = p.release();
+  }
+  return XOD_OK;
+}
+
+// FP64 factorisation of the caller's system in the column's own blocks
+// (cyclic reduction, or the fallback of a mixed explicit solve).
+xod_status factor_own_fp64(xod_column *col, const double *B, const double *av,
+                           const double *cv) {
+  const size_t NL = (size_t)col->N * col->ld;
+  XOD_HIP(hipMemcpyAsync(col->B, B, NL * col->ld * sizeof(double), hipMemcpyDeviceToDevice,
+                         col->stream));
+  XOD_HIP(hipMemcpyAsync(col->a, av, NL * sizeof(double), hipMemcpyDeviceToDevice, col->stream));
+  XOD_HIP(hipMemcpyAsync(col->c, cv, NL * sizeof(double), hipMemcpyDeviceToDevice, col->stream));
+  if (col->solver == XOD_SOLVER_CR) {
+    XOD_TRY(col->cr64->factor(col));
+  } else {
+    XOD_HIP(launch_factor_fp64(OneCol{col->args()}, 1, col->N, col->ld, col->stream));
+  }
+  return XOD_OK;
+}
+
+xod_status read_singular_flag(xod_column *col) {
   int fl[4];
   XOD_HIP(hipMemcpyAsync(fl, col->flag, sizeof(fl), hipMemcpyDeviceToHost, col->stream));
   XOD_HIP(hipStreamSynchronize(col->stream));
@@ -748,19 +786,147 @@ extern "C" xod_status xod_btd_factor(xod_column *col, double *B, const double *a
   return check_flags(col, fd);
 }
 
+// Solve with the column's own FP64 factors: rhs [N*S] in, solution out.
+xod_status solve_own_fp64(xod_column *col, double *rhs) {
+  const size_t NSb = (size_t)col->N * col->S * sizeof(double);
+  XOD_HIP(hipMemcpyAsync(col->x, rhs, NSb, hipMemcpyDeviceToDevice, col->stream));
+  if (col->solver == XOD_SOLVER_CR) {
+    XOD_TRY(col->cr64->solve(col));
+  } else {
+    XOD_HIP(launch_solve_fp64(OneCol{col->args()}, 1, col->N, col->ld, col->stream));
+  }
+  XOD_HIP(hipMemcpyAsync(rhs, col->x, NSb, hipMemcpyDeviceToDevice, col->stream));
+  return XOD_OK;
+}
+
+}  // namespace
+
+extern "C" xod_status xod_btd_factor(xod_column *col, double *B, const double *av,
+                                     const double *cv, int32_t ld, int32_t *piv,
+                                     xod_precision prec) {
+  XOD_CHECK(col && B && av && cv, "xod_btd_factor: null argument");
+  XOD_CHECK(ld == col->ld, "xod_btd_factor: ld must equal the network's padded size");
+  XOD_CHECK(prec == XOD_FP64 || prec == XOD_MIXED, "xod_btd_factor: bad precision");
+  XOD_CHECK(!col->in_batch, "xod_btd_factor: column belongs to a batch");
+  col->btd.valid = false;
+  col->fact_dt = 0.0;     // the column's own blocks no longer hold a step's factors
+  if (prec == XOD_FP64 && col->solver == XOD_SOLVER_THOMAS) {
+    XOD_CHECK(piv, "xod_btd_factor: null pivot array");
+    ColArgs a = col->args();
+    a.B = B;
+    a.a = const_cast<double *>(av);
+    a.c = const_cast<double *>(cv);
+    a.piv = piv;
+    XOD_HIP(launch_factor_fp64(OneCol{a}, 1, col->N, col->ld, col->stream));
+    return read_singular_flag(col);
+  }
+  if (prec == XOD_FP64) {
+    XOD_TRY(factor_own_fp64(col, B, av, cv));
+  } else {
+    XOD_TRY(ensure_fp32_blocks(col));
+    XOD_HIP(launch_cast_scale(B, av, cv, col->N, col->ld, col->Bf, col->rs, col->a, col->c,
+                              col->stream));
+    if (col->solver == XOD_SOLVER_CR) {
+      XOD_TRY(col->cr32->factor(col));
+    } else {
+      XOD_HIP(launch_factor_mixed(OneCol{col->args()}, 1, col->N, col->ld, col->stream));
+    }
+  }
+  XOD_TRY(read_singular_flag(col));
+  col->btd.valid = true;
+  col->btd.prec = prec;
+  col->btd.solver = col->solver;
+  col->btd.B = B;
+  col->btd.a = av;
+  col->btd.c = cv;
+  return XOD_OK;
+}
+
 extern "C" xod_status xod_btd_solve(xod_column *col, const double *B, const double *av,
                                     const double *cv, int32_t ld, const int32_t *piv,
-                                    double *rhs) {
-  XOD_CHECK(col && B && av && cv && piv && rhs, "xod_btd_solve: null argument");
+                                    double *rhs, int32_t max_refine) {
+  XOD_CHECK(col && B && av && cv && rhs, "xod_btd_solve: null argument");
   XOD_CHECK(ld == col->ld, "xod_btd_solve: ld must equal the network's padded size");
-  XOD_HIP(launch_invperm(piv, col->rstep, col->N, col->ld, col->stream));
+  XOD_CHECK(max_refine >= 0 && max_refine <= 100, "xod_btd_solve: max_refine must be in 0..100");
+  XOD_CHECK(!col->in_batch, "xod_btd_solve: column belongs to a batch");
+  col->btd_iters = 0;
+  col->btd_fallback = 0;
+  col->btd_size = 0.0;
+  const bool held = col->btd.valid && col->btd.B == B && col->btd.a == av &&
+                    col->btd.c == cv && col->btd.solver == col->solver;
+  if (!held) {
+    // block Thomas in FP64 leaves its factors in the caller's arrays
+    XOD_CHECK(col->solver == XOD_SOLVER_THOMAS && piv,
+              "xod_btd_solve: no factorisation of this system is held by the column "
+              "(call xod_btd_factor with the same B, a, c first)");
+    XOD_HIP(launch_invperm(piv, col->rstep, col->N, col->ld, col->stream));
+    ColArgs a = col->args();
+    a.B = const_cast<double *>(B);
+    a.a = const_cast<double *>(av);
+    a.c = const_cast<double *>(cv);
+    a.piv = const_cast<int *>(piv);
+    a.x = rhs;
+    XOD_HIP(launch_solve_fp64(OneCol{a}, 1, col->N, col->ld, col->stream));
+    return XOD_OK;
+  }
+  if (col->btd.prec == XOD_FP64) return solve_own_fp64(col, rhs);
+
+  // Mixed precision: FP32 solves of the row-scaled system, refined against
+  // the caller's FP64 (B, a, c); FP64 refactorisation if refinement fails.
+  const bool cr = col->solver == XOD_SOLVER_CR;
+  const int N = col->N, S = col->S;
+  const size_t NSb = (size_t)N * S * sizeof(double);
   ColArgs a = col->args();
-  a.B = const_cast<double *>(B);
-  a.a = const_cast<double *>(av);
-  a.c = const_cast<double *>(cv);
-  a.piv = const_cast<int *>(piv);
-  a.x = rhs;
-  XOD_HIP(launch_solve_fp64(OneCol{a}, 1, col->N, col->ld, col->stream));
+  a.f = rhs;
+  a.n = nullptr;          // an explicit system: corrections measured against x itself
+  OneCol one{a};
+  XOD_HIP(launch_scale(one, 1, N, S, col->stream));                     // x = s g
+  if (cr)
+    XOD_TRY(col->cr32->solve(col));
+  else
+    XOD_HIP(launch_solve_mixed(one, 1, N, col->ld, col->stream));
+  XOD_HIP(hipMemcpyAsync(col->dx, col->x, NSb, hipMemcpyDeviceToDevice, col->stream));
+  RefineNext verdict = max_refine == 0 ? kRefineDone : kRefineFallback;
+  double prev = 1e300, size = 0.0;
+  for (int it = 1; it <= max_refine; ++it) {
+    XOD_HIP(launch_bt_resid(B, av, cv, rhs, col->dx, col->rs, N, S, col->ld, col->x,
+                            col->stream));
+    if (cr)
+      XOD_TRY(col->cr32->solve(col));
+    else
+      XOD_HIP(launch_solve_mixed(one, 1, N, col->ld, col->stream));
+    XOD_HIP(launch_axpy_ratio(one, 1, N, col->ratio, col->rmax, col->stream));
+    XOD_HIP(hipMemcpyAsync(col->stats_host, col->rmax, sizeof(double), hipMemcpyDeviceToHost,
+                           col->stream));
+    XOD_HIP(hipStreamSynchronize(col->stream));
+    size = col->stats_host[0];
+    col->btd_iters = it;
+    verdict = refine_next(size, prev, it, max_refine);
+    if (verdict != kRefineMore) break;
+    prev = size;
+  }
+  col->btd_size = size;
+  if (verdict == kRefineDone) {
+    XOD_HIP(hipMemcpyAsync(rhs, col->dx, NSb, hipMemcpyDeviceToDevice, col->stream));
+    XOD_HIP(hipStreamSynchronize(col->stream));
+    return XOD_OK;
+  }
+  // FP64 fallback: the column now holds FP64 factors of the same system
+  col->btd_fallback = 1;
+  XOD_TRY(factor_own_fp64(col, B, av, cv));
+  XOD_TRY(read_singular_flag(col));
+  col->btd.prec = XOD_FP64;
+  XOD_TRY(solve_own_fp64(col, rhs));
+  XOD_HIP(hipStreamSynchronize(col->stream));
+  return XOD_OK;
+}
+
+extern "C" xod_status xod_btd_solve_info(const xod_column *col, int32_t *refine_iters,
+                                         int32_t *fp64_fallback, double *correction) {
+  XOD_CHECK(col, "xod_btd_solve_info: null column");
+  if (refine_iters) *refine_iters = col->btd_iters;
+  if (fp64_fallback) *fp64_fallback = col->btd_fallback;
+  if (correction) *correction = col->btd_size;
   return XOD_OK;
 }
 
@@ -812,6 +978,35 @@ xod_status run_update(xod_column *c, bool clip, double y_floor, double y_sig, do
   return XOD_OK;
 }
 
+// Iterative refinement of an FP64 solve with its own factors: the residual
+// F - M delta in FP64 from the reaction list and the transport coefficients
+// (no row scaling), a solve for the correction, delta += correction, a fixed
+// options().refine64 times (no host round trip; batches do the same, so a
+// column steps alike alone and in a batch).  The explicit inverses make the
+// FP64 solve forward stable only: components far below their layer's
+// largest increment carry errors of order cond(M) eps of that increment,
+// and one correction brings them to the residual's rounding.  delta in
+// c->x on entry and on return.
+xod_status refine_fp64(xod_column *c, int *iters) {
+  const size_t NSb = (size_t)c->N * c->S * sizeof(double);
+  ColArgs a = c->args();
+  a.rs = nullptr;
+  OneCol one{a};
+  const bool cr = c->solver == XOD_SOLVER_CR;
+  XOD_HIP(hipMemcpyAsync(c->dx, c->x, NSb, hipMemcpyDeviceToDevice, c->stream));
+  for (int it = 1; it <= options().refine64; ++it) {
+    XOD_HIP(launch_residual(one, 1, c->N, c->S, c->R, c->stream));
+    if (cr)
+      XOD_TRY(c->cr64->solve(c));
+    else
+      XOD_HIP(launch_solve_fp64(one, 1, c->N, c->ld, c->stream));
+    XOD_HIP(launch_axpy_ratio(one, 1, c->N, c->ratio, c->rmax, c->stream));
+    *iters = it;
+  }
+  XOD_HIP(hipMemcpyAsync(c->x, c->dx, NSb, hipMemcpyDeviceToDevice, c->stream));
+  return XOD_OK;
+}
+
 xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, double *resid,
                          const double *hist, double hist_coef) {
   c->dt = dt;
@@ -830,6 +1025,7 @@ xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, do
   }
   const bool cr = c->solver == XOD_SOLVER_CR;
   c->fact_dt = 0.0;
+  c->btd.valid = false;   // the column's blocks receive this step's matrix
   if (c->prec == XOD_FP64) {
     XOD_HIP(launch_jacobian(one, 1, c->N, c->R, c->ld, false, c->stream));
     if (cr)
@@ -843,6 +1039,7 @@ xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, do
     else
       XOD_HIP(launch_solve_fp64(one, 1, c->N, c->ld, c->stream));
     c->fact_dt = dt;
+    if (options().refine64 > 0) XOD_TRY(refine_fp64(c, iters));
     return XOD_OK;
   }
   // Mixed precision: row-scaled FP32 Schur complements, FP64 refinement with a
@@ -894,6 +1091,10 @@ xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, do
     XOD_TRY(c->cr64->solve(c));
   else
     XOD_HIP(launch_solve_fp64(one, 1, c->N, c->ld, c->stream));
+  if (options().refine64 > 0) {       // as an FP64 column's step
+    int it64 = 0;
+    XOD_TRY(refine_fp64(c, &it64));
+  }
   return XOD_OK;
 }
 
@@ -1116,6 +1317,54 @@ extern "C" xod_status xod_step_bdf2(xod_column *col, double dt, xod_step_stats *
   return XOD_OK;
 }
 
+// One backward-Euler step of size dt on the factorisation the column holds
+// (of an earlier state and step): modified Newton from Delta = 0,
+//   Delta += M_f^-1 (F(n + Delta) - Delta/dt),
+// until a correction is at most ntol of every new density with mixing ratio
+// above y_sig (ok), or one is not below half the previous, or an iterate is
+// not finite, or max_it corrections are spent (not ok).  Delta ends in
+// c->x.  Rates are those of the step's start.
+static xod_status newton_on_held(xod_column *c, double dt, double ntol, int max_it,
+                                 double y_sig, bool *ok, int64_t *iters) {
+  const size_t NS = (size_t)c->N * c->S;
+  *ok = false;
+  c->dt = dt;
+  XOD_TRY(enqueue_photolysis(c));
+  XOD_HIP(launch_rates(OneCol{c->args()}, 1, c->N, c->R, c->stream));
+  XOD_HIP(hipMemsetAsync(c->dx, 0, NS * sizeof(double), c->stream));
+  double prev = 1e300;
+  for (int it = 1; it <= max_it; ++it) {
+    XOD_HIP(launch_lincomb(c->ntmp, c->n, 1.0, c->dx, 1.0, NS, c->stream));   // n + Delta
+    ColArgs a = c->args();
+    a.n = c->ntmp;
+    XOD_HIP(launch_rhs(OneCol{a}, 1, c->N, c->R, c->S, c->stream));          // f = F(n + Delta)
+    XOD_HIP(launch_lincomb(c->x, c->f, 1.0, c->dx, -1.0 / dt, NS, c->stream));
+    if (c->solver == XOD_SOLVER_CR)
+      XOD_TRY(c->cr64->solve(c));
+    else
+      XOD_HIP(launch_solve_fp64(OneCol{c->args()}, 1, c->N, c->ld, c->stream));
+    // Delta += correction; size = max |corr_i| / |n_i + Delta_i| over the
+    // components with mixing ratio above y_sig (1e300 if any is not finite)
+    XOD_HIP(launch_axpy_size(OneCol{c->args()}, 1, c->N, c->ratio, c->rmax, 1.0, 0.0, y_sig,
+                             c->stream));
+    XOD_HIP(hipMemcpyAsync(c->stats_host, c->rmax, sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+    XOD_HIP(hipStreamSynchronize(c->stream));
+    ++*iters;
+    const double size = c->stats_host[0];
+    if (size <= ntol) {
+      *ok = true;
+      break;
+    }
+    if (!(size <= 0.5 * prev)) break;
+    prev = size;
+  }
+  if (*ok)
+    XOD_HIP(hipMemcpyAsync(c->x, c->dx, NS * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream));
+  return XOD_OK;
+}
+
 extern "C" xod_status xod_integrate_to_steady_state(xod_column *col, const xod_ss_opts *o,
                                                     xod_ss_result *res) {
   XOD_CHECK(col && res, "xod_integrate_to_steady_state: null argument");
@@ -1123,10 +1372,11 @@ extern "C" xod_status xod_integrate_to_steady_state(xod_column *col, const xod_s
   double tol = 1e-4, yfl = 1e-30, ysig = 1e-10, tend = 1e12, dt0 = 1e-8;
   int maxs = 5000, maxrej = 30, mixrule = 1, method = 0;
   if (o) {
-    XOD_CHECK(o->method == 0 || o->method == 1,
-              "xod_integrate_to_steady_state: method must be 0 (backward Euler) or 1 (ROS2)");
+    XOD_CHECK(o->method >= 0 && o->method <= 2,
+              "xod_integrate_to_steady_state: method must be 0 (backward Euler), 1 (ROS2) "
+              "or 2 (backward Euler with kept factorisations)");
     XOD_CHECK(o->method == 0 || col->prec == XOD_FP64,
-              "xod_integrate_to_steady_state: ROS2 needs an FP64 column");
+              "xod_integrate_to_steady_state: methods 1 and 2 need an FP64 column");
     method = o->method;
     if (o->tol_rel > 0) tol = o->tol_rel;
     if (o->y_floor > 0) yfl = o->y_floor;
@@ -1140,16 +1390,43 @@ extern "C" xod_status xod_integrate_to_steady_state(xod_column *col, const xod_s
   col->prev_dt = 0.0;   // rejected steps leave their output in ntmp
   const double mix = mixrule ? col->mix_time : 0.0;
   double t = 0.0, dt = dt0, clipped = 0.0;
-  int64_t steps = 0, rejects = 0;
+  int64_t steps = 0, rejects = 0, nnewton = 0;
   int consec = 0;
-  int converged = 0;
+  int converged = 0, nfact = 0;
+  // method 2: the held factorisation's step size and accepted steps
+  constexpr double kReuseRatio = 1.3, kNewtonTol = 1e-3;
+  constexpr int kMaxNewton = 4, kMaxAge = 20;
+  bool held = false;
+  double held_dt = 0.0;
+  int held_age = 0;
   while (steps < maxs) {
     int iters, fb;
     double rr;
-    if (method == 1)
+    if (method == 1) {
       XOD_TRY(enqueue_ros2(col, dt));
-    else
+      ++nfact;
+    } else if (method == 2) {
+      const double ratio = held ? dt / held_dt : 0.0;
+      const bool fresh = !held || !(ratio >= 1.0 / kReuseRatio && ratio <= kReuseRatio) ||
+                         held_age >= kMaxAge;
+      if (fresh) {
+        XOD_TRY(enqueue_solve(col, dt, &iters, &fb, &rr));
+        held = true;
+        held_dt = dt;
+        held_age = 0;
+        ++nfact;
+      } else {
+        bool ok = false;
+        XOD_TRY(newton_on_held(col, dt, kNewtonTol, kMaxNewton, ysig, &ok, &nnewton));
+        if (!ok) {            // retry this step with a fresh factorisation
+          held = false;
+          continue;
+        }
+      }
+    } else {
       XOD_TRY(enqueue_solve(col, dt, &iters, &fb, &rr));
+      ++nfact;
+    }
     double s[kStatLen];
     XOD_TRY(run_update(col, true, yfl, ysig, s));
     const bool singular = s[kNStat] >= 0;
@@ -1165,6 +1442,7 @@ extern "C" xod_status xod_integrate_to_steady_state(xod_column *col, const xod_s
     std::swap(col->n, col->ntmp);
     t += dt;
     ++steps;
+    ++held_age;
     const double rel = s[0], ctl = s[2];
     if ((rel < tol && dt >= mix) || t >= tend) {
       converged = 1;
@@ -1181,9 +1459,65 @@ extern "C" xod_status xod_integrate_to_steady_state(xod_column *col, const xod_s
   res->steps = steps;
   res->rejects = rejects;
   res->converged = converged;
+  res->factorizations = nfact;
+  res->newton_iters = nnewton;
+  if (method == 2) col->fact_dt = held ? held_dt : 0.0;   // of an earlier state
   if (!converged) {
     set_error("steady state not reached (step or rejection limit)");
     return XOD_ENOTCONVERGED;
   }
   return XOD_OK;
+}
+
+extern "C" xod_status xod_integrate_fixed_dt(xod_column *col, double dt, int32_t nsteps,
+                                             int32_t reuse, xod_reuse_stats *st) {
+  XOD_CHECK(col, "xod_integrate_fixed_dt: null column");
+  XOD_CHECK(!col->in_batch, "xod_integrate_fixed_dt: column belongs to a batch");
+  XOD_CHECK(std::isfinite(dt) && dt > 0, "xod_integrate_fixed_dt: dt must be > 0");
+  XOD_CHECK(nsteps >= 0, "xod_integrate_fixed_dt: nsteps must be >= 0");
+  XOD_CHECK(reuse == 0 || reuse == 1, "xod_integrate_fixed_dt: reuse must be 0 or 1");
+  XOD_CHECK(reuse == 0 || col->prec == XOD_FP64,
+            "xod_integrate_fixed_dt: reusing factorisations needs an FP64 column");
+  constexpr double kNewtonTol = 1e-3, kYSig = 1e-10;
+  constexpr int kMaxNewton = 4, kMaxAge = 20;
+  int64_t nfact = 0, ncorr = 0, done = 0;
+  bool held = false;
+  int age = 0;
+  col->prev_dt = 0.0;
+  xod_status ret = XOD_OK;
+  for (int32_t i = 0; i < nsteps; ++i) {
+    bool ok = false;
+    if (reuse && held && age < kMaxAge)
+      XOD_TRY(newton_on_held(col, dt, kNewtonTol, kMaxNewton, kYSig, &ok, &ncorr));
+    if (ok) {
+      ++age;
+    } else {
+      int iters, fb;
+      double rr;
+      XOD_TRY(enqueue_solve(col, dt, &iters, &fb, &rr));
+      held = true;
+      age = 1;
+      ++nfact;
+    }
+    double s[kStatLen];
+    XOD_TRY(run_update(col, false, 1e-30, kYSig, s));
+    XOD_TRY(check_flags(col, s + kNStat));
+    if (s[5] > 0) {
+      set_error("xod_integrate_fixed_dt: non-finite state at step " + std::to_string(i));
+      ret = XOD_ENONFINITE;
+      break;
+    }
+    std::swap(col->n, col->ntmp);
+    col->t += dt;
+    ++done;
+  }
+  col->dt = dt;
+  col->prev_dt = 0.0;
+  col->fact_dt = held ? dt : 0.0;   // of an earlier state when reused
+  if (st) {
+    st->steps = done;
+    st->factorizations = nfact;
+    st->newton_iters = ncorr;
+  }
+  return ret;
 }

@@ -103,6 +103,7 @@ xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double
       const int sl = base + j;
       c->dt = dts[kv.second[j]];
       h_args[sl] = c->args();
+      if (c->prec == XOD_FP64) h_args[sl].rs = nullptr;   // FP64 refinement: unscaled
       UpdArgs u{};
       u.n = c->n;
       u.x = c->x;
@@ -122,7 +123,7 @@ xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double
       slots.push_back({kv.second[j], sl});
     }
     g.roff = rneed;
-    if (g.mixed) rneed += (size_t)g.nc * g.maxN;
+    rneed += (size_t)g.nc * g.maxN;
     base += g.nc;
     gs.push_back(g);
   }
@@ -179,6 +180,26 @@ xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double
                                hipMemcpyDeviceToDevice, st));
       }
       XOD_HIP(launch_solve_fp64(acc, g.nc, g.maxN, g.ld, st));
+      if (options().refine64 > 0) {
+        // the fixed FP64 refinement of a single column's step (the FP64
+        // columns' argument copies carry no row scales)
+        for (int j = 0; j < g.nc; ++j) {
+          xod_column *c = cols[(*g.idx)[j]];
+          XOD_HIP(hipMemcpyAsync(c->dx, c->x, (size_t)c->N * c->S * sizeof(double),
+                                 hipMemcpyDeviceToDevice, st));
+        }
+        for (int it = 1; it <= options().refine64; ++it) {
+          XOD_HIP(launch_residual(acc, g.nc, g.maxN, g.maxS, g.maxR, st));
+          XOD_HIP(launch_solve_fp64(acc, g.nc, g.maxN, g.ld, st));
+          XOD_HIP(launch_axpy_ratio(acc, g.nc, g.maxN, d_ratio + g.roff, d_rmax + gi, st));
+          g.iters = it;
+        }
+        for (int j = 0; j < g.nc; ++j) {
+          xod_column *c = cols[(*g.idx)[j]];
+          XOD_HIP(hipMemcpyAsync(c->x, c->dx, (size_t)c->N * c->S * sizeof(double),
+                                 hipMemcpyDeviceToDevice, st));
+        }
+      }
     }
   }
   // phase 2: refinement of mixed groups (each waits on its own stream only)
@@ -284,6 +305,7 @@ extern "C" xod_status xod_batch_create(xod_column *const *cols, int32_t ncols, x
   for (auto *c : b->cols) {
     c->in_batch = true;
     c->fact_dt = 0.0;
+    c->btd.valid = false;
   }
   *out = b.release();
   return XOD_OK;

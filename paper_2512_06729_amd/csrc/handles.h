@@ -67,7 +67,7 @@ struct xod_column {
          *f = nullptr, *x = nullptr, *gs = nullptr, *resid = nullptr, *dx = nullptr;
   double *B = nullptr;
   float *Bf = nullptr;
-  double *a = nullptr, *c = nullptr, *rs = nullptr, *a64 = nullptr, *c64 = nullptr;
+  double *a = nullptr, *c = nullptr, *rs = nullptr;
   int *piv = nullptr, *rstep = nullptr, *flag = nullptr;
   double *partial = nullptr, *stats_dev = nullptr, *stats_host = nullptr;
   double *ratio = nullptr, *rmax = nullptr;   // refinement convergence measure
@@ -78,6 +78,17 @@ struct xod_column {
   double fact_dt = 0.0;   // dt of the FP64 factorisation held in the blocks (0: none)
   double prev_dt = 0.0;   // dt of the step whose starting state ntmp holds (0: none)
   bool in_batch = false;
+  // The factorisation xod_btd_factor left in the column's own workspace
+  // (cyclic reduction or mixed precision): the caller's FP64 system it came
+  // from and how it was factored.  Steps, batches and solver switches drop it.
+  struct BtdHeld {
+    bool valid = false;
+    xod_precision prec = XOD_FP64;
+    xod_solver solver = XOD_SOLVER_THOMAS;
+    const double *B = nullptr, *a = nullptr, *c = nullptr;
+  } btd;
+  int btd_iters = 0, btd_fallback = 0;   // refinements / FP64 fallback of the last btd solve
+  double btd_size = 0.0;                 // its last componentwise correction size
   xod_solver solver = XOD_SOLVER_THOMAS;
   xod::CrPlan<double> *cr64 = nullptr;   // block cyclic reduction (FP64 column)
   xod::CrPlan<float> *cr32 = nullptr;    // block cyclic reduction (mixed column)

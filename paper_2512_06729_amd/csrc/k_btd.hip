@@ -260,6 +260,97 @@ __device__ __forceinline__ void gj_col(double (&row)[R][kNB], double (&sig)[R],
   }
 }
 
+// The same column step with the elimination of every other panel column
+// deferred by one column: pivot U's rank-1 update reaches column U+1 at once
+// (the next pivot search needs it) and the remaining columns only after the
+// next column's wave key has been published, so those FMAs run while the
+// barrier that exchanges the keys is pending.  Each element receives the
+// same FMAs in the same order as in gj_col.  dpr / dfm carry the deferred
+// pivot row and multipliers; on the group's last column nothing is deferred.
+template <int R, int U, bool kTwo>
+__device__ __forceinline__ void gj_col_defer(double (&row)[R][kNB], double (&sig)[R],
+                                             unsigned (&umask)[R], int (&mystep)[R],
+                                             PanelShared &sh, int t, int jcol, int j0,
+                                             double (&dpr)[kNB], double (&dfm)[R]) {
+  static_assert(kTwo, "deferred eliminations publish the pivot row after the key barrier");
+  const int lane = t & 63, wid = t >> 6;
+  const int buf = jcol & 1;
+  double key = 0.0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) key = fmax(key, pivot_key(row[i][U], R * t + i, umask[i]));
+  const double m = wave_max(key);
+  if (lane == 0) sh.key[buf][wid] = m;
+  if constexpr (U > 0) {
+    // pivot U-1's update of the columns other than U-1 (its own) and U (done)
+#pragma unroll
+    for (int q = 0; q < kNB; ++q) {
+      if (q == U - 1 || q == U) continue;
+#pragma unroll
+      for (int i = 0; i < R; ++i) row[i][q] = fma(-dfm[i], dpr[q], row[i][q]);
+    }
+  }
+  __syncthreads();
+  double K = sh.key[buf][0];
+#pragma unroll
+  for (int w = 1; w < kPanelWaves; ++w) K = fmax(K, sh.key[buf][w]);
+  if (!(K > 0.0)) {                    // no unused row left: nothing to defer
+    if (t == 0) { sh.piv[jcol] = 0; if (sh.bad < 0) sh.bad = jcol; }
+#pragma unroll
+    for (int i = 0; i < R; ++i) dfm[i] = 0.0;
+    return;
+  }
+  const int r = key_row(K);
+  if (r / (64 * R) == wid) publish_row<R, U>(row, t, r, sh.cand[0][buf]);
+  __syncthreads();
+  const double2 *prow = reinterpret_cast<const double2 *>(sh.cand[0][buf]);
+#pragma unroll
+  for (int q = 0; q < kNB; q += 2) {     // 16-byte loads
+    const double2 v = prow[q / 2];
+    dpr[q] = v.x;
+    dpr[q + 1] = v.y;
+  }
+  double npiv = dpr[U];
+  if (npiv != npiv) {                  // zero or non-finite pivot
+    if (t == 0 && sh.bad < 0) sh.bad = jcol;
+    npiv = 1.0;
+  }
+  sh.piv[jcol] = r;                    // every thread stores the same value
+  bool me[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    me[i] = R * t + i == r;
+    dfm[i] = me[i] ? 0.0 : row[i][U] * npiv;
+  }
+  if constexpr (U + 1 < kGroup) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) row[i][U + 1] = fma(-dfm[i], dpr[U + 1], row[i][U + 1]);
+  } else {                             // last column of the group: no deferral
+#pragma unroll
+    for (int q = 0; q < kNB; ++q) {
+      if (q == U) continue;
+#pragma unroll
+      for (int i = 0; i < R; ++i) row[i][q] = fma(-dfm[i], dpr[q], row[i][q]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    row[i][U] = me[i] ? 1.0 : -dfm[i];
+    umask[i] = me[i] ? 0u : umask[i];
+    sig[i] = me[i] ? npiv : sig[i];
+    mystep[i] = me[i] ? j0 + jcol : mystep[i];
+  }
+}
+
+template <int R, int U, bool kTwo>
+__device__ __forceinline__ void gj_group_defer(double (&row)[R][kNB], double (&sig)[R],
+                                               unsigned (&umask)[R], int (&mystep)[R],
+                                               PanelShared &sh, int t, int jbase, int j0,
+                                               double (&dpr)[kNB], double (&dfm)[R]) {
+  gj_col_defer<R, U, kTwo>(row, sig, umask, mystep, sh, t, jbase + U, j0, dpr, dfm);
+  if constexpr (U + 1 < kGroup)
+    gj_group_defer<R, U + 1, kTwo>(row, sig, umask, mystep, sh, t, jbase, j0, dpr, dfm);
+}
+
 template <int R, int U, bool kTwo>
 __device__ __forceinline__ void gj_group(double (&row)[R][kNB], double (&sig)[R],
                                          unsigned (&umask)[R], int (&mystep)[R],
@@ -269,7 +360,7 @@ __device__ __forceinline__ void gj_group(double (&row)[R][kNB], double (&sig)[R]
     gj_group<R, U + 1, kTwo>(row, sig, umask, mystep, sh, t, jbase, j0);
 }
 
-template <class MA, class T, int R, bool kTwo>
+template <class MA, class T, int R, bool kTwo, bool kDefer = false>
 __global__ void __launch_bounds__(64 * kPanelWaves) k_panel(MA ma, int k, int p, int ld) {
   MatRef<T> mat;
   if (!ma(blockIdx.x, k, mat)) return;
@@ -305,9 +396,13 @@ __global__ void __launch_bounds__(64 * kPanelWaves) k_panel(MA ma, int k, int p,
   // Columns in groups of kGroup at static positions 0..kGroup-1; afterwards
   // every row rotates left by kGroup, so after the last group the rows are
   // back in panel order.
+  double dpr[kNB], dfm[R];
 #pragma unroll 1
   for (int jb = 0; jb < kNB; jb += kGroup) {
-    gj_group<R, 0, kTwo>(row, sig, umask, mystep, sh, t, jb, j0);
+    if constexpr (kDefer)
+      gj_group_defer<R, 0, kTwo>(row, sig, umask, mystep, sh, t, jb, j0, dpr, dfm);
+    else
+      gj_group<R, 0, kTwo>(row, sig, umask, mystep, sh, t, jb, j0);
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       double tmp[kGroup];
@@ -337,7 +432,10 @@ __global__ void __launch_bounds__(64 * kPanelWaves) k_panel(MA ma, int k, int p,
 template <class MA, class T>
 void launch_panel(const MA &ma, int nmat, int ld, int k, int p, hipStream_t s) {
   const int threads = 64 * ((ld + 64 * kPanelRows - 1) / (64 * kPanelRows));
-  if (options().panel_sync == 2)
+  if (options().panel_defer)          // deferred eliminations: two barriers per column
+    hipLaunchKernelGGL((k_panel<MA, T, kPanelRows, true, true>), dim3(nmat), dim3(threads), 0, s,
+                       ma, k, p, ld);
+  else if (options().panel_sync == 2)
     hipLaunchKernelGGL((k_panel<MA, T, kPanelRows, true>), dim3(nmat), dim3(threads), 0, s, ma, k,
                        p, ld);
   else

@@ -94,6 +94,15 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmOp<T> *ops, int
       Bs[buf][idx / BM][idx % BM] = rb[e];
     }
   };
+  // 16 x 16 output tiles wholly beyond ld (the last tile row / column of a
+  // block whose size is not a multiple of BM) are skipped: wave-uniform
+  // conditions, so waves of edge tiles leave their SIMD to other work-groups.
+  bool live_r[TM], live_c[TM];
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    live_r[i] = tm0 + (wr * TM + i) * 16 < ld;
+    live_c[i] = tn0 + (wc * TM + i) * 16 < ld;
+  }
   gload(0);
   sstore(0);
   __syncthreads();
@@ -112,7 +121,8 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmOp<T> *ops, int
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TM; ++j) acc[i][j] = mfma16(av[i], bv[j], acc[i][j]);
+        for (int j = 0; j < TM; ++j)
+          if (live_r[i] && live_c[j]) acc[i][j] = mfma16(av[i], bv[j], acc[i][j]);
     }
     if (kt + 1 < nk) sstore(buf ^ 1);
     __syncthreads();

@@ -10,6 +10,7 @@
 //   k_scale    x = s * F
 //   k_axpy     delta += x, per-layer componentwise correction size
 #include "xod_internal.h"
+#include "mfma.h"
 
 namespace xod {
 
@@ -60,7 +61,8 @@ __global__ void __launch_bounds__(256) k_resid(Acc acc) {
   if (k >= 1) tr += c.trl[o] * delta[o - c.S];
   if (k + 1 < c.N) tr += c.tru[o] * delta[o + c.S];
   const double Md = delta[o] / c.dt - jd - tr;
-  c.x[o] = c.rs[(size_t)k * c.ld + y] * (c.f[o] - Md);
+  const double sc = c.rs ? c.rs[(size_t)k * c.ld + y] : 1.0;   // no scales: FP64 factors
+  c.x[o] = sc * (c.f[o] - Md);
 }
 
 template <class Acc>
@@ -93,12 +95,15 @@ __global__ void __launch_bounds__(256) k_axpy(Acc acc, double *ratio, double rto
   }
   __shared__ double red[256];
   double m = 0.0;
+  bool bad = false;           // a non-finite correction or sum anywhere in the layer
   for (int y = threadIdx.x; y < c.S; y += blockDim.x) {
     const size_t o = (size_t)k * c.S + y;
     const double d = delta[o] + c.x[o];
     delta[o] = d;
     m = fmax(m, fabs(d));
+    bad = bad || !isfinite(d);
   }
+  if (bad) m = __builtin_inf();
   red[threadIdx.x] = m;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
@@ -111,8 +116,10 @@ __global__ void __launch_bounds__(256) k_axpy(Acc acc, double *ratio, double rto
   double q = 0.0;
   for (int y = threadIdx.x; y < c.S; y += blockDim.x) {
     const size_t o = (size_t)k * c.S + y;
-    const double nn = fabs(c.n[o] + delta[o]);
-    if (nn > sig) {
+    // an explicit system (no state: c.n null) measures the correction
+    // against the solution itself, every component
+    const double nn = c.n ? fabs(c.n[o] + delta[o]) : fabs(delta[o]);
+    if (!c.n || nn > sig) {
       const double den = rtol * nn + floor_abs;
       const double xi = fabs(c.x[o]);
       q = fmax(q, den > 0.0 ? xi / den : (xi > 0.0 ? 1e300 : 0.0));
@@ -124,7 +131,73 @@ __global__ void __launch_bounds__(256) k_axpy(Acc acc, double *ratio, double rto
     if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) *rk = isfinite(red[0]) ? red[0] : 1e300;
+  if (threadIdx.x == 0) *rk = (isfinite(red[0]) && isfinite(floor_abs)) ? red[0] : 1e300;
+}
+
+// Explicit block systems (xod_btd_factor / xod_btd_solve in mixed precision):
+// one wave per block row.
+//   k_cast_scale  s_i = 1 / max(|B_k[i][:]|, |a_k[i]|, |c_k[i]|) (1 for a zero
+//                 row); Bf = s B in FP32, as = s a, cs = s c
+//   k_bt_resid    x = s * (g - M dx) with M the FP64 block-tridiagonal matrix
+//                 (B, a, c), dx and g in the compact [N*S] layout
+__global__ void __launch_bounds__(256) k_cast_scale(const double *B, const double *a,
+                                                    const double *cc, int N, int ld,
+                                                    float *Bf, double *rs, double *as,
+                                                    double *cs) {
+  const int lane = threadIdx.x & 63;
+  const size_t row = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= (size_t)N * ld) return;
+  const auto Bg = gmem(B) + row * ld;
+  double amax = fmax(fabs(a[row]), fabs(cc[row]));
+  for (int j = lane; j < ld; j += 64) amax = fmax(amax, fabs(Bg[j]));
+  for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
+  const double sc = amax > 0.0 ? 1.0 / amax : 1.0;
+  const auto Bo = gmem(Bf) + row * ld;
+  for (int j = lane; j < ld; j += 64) Bo[j] = (float)(sc * Bg[j]);
+  if (lane == 0) {
+    rs[row] = sc;
+    as[row] = sc * a[row];
+    cs[row] = sc * cc[row];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_bt_resid(const double *B, const double *a,
+                                                  const double *cc, const double *g,
+                                                  const double *dx, const double *rs, int N,
+                                                  int S, int ld, double *x) {
+  const int lane = threadIdx.x & 63;
+  const size_t r = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= (size_t)N * S) return;
+  const int k = (int)(r / S), i = (int)(r % S);
+  const size_t row = (size_t)k * ld + i;
+  const auto Bg = gmem(B) + row * ld;
+  const double *d = dx + (size_t)k * S;
+  double sum = 0.0;
+  for (int j = lane; j < S; j += 64) sum = fma(Bg[j], d[j], sum);
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+  if (lane == 0) {
+    double md = sum;
+    if (k >= 1) md += a[row] * dx[r - S];
+    if (k + 1 < N) md += cc[row] * dx[r + S];
+    x[r] = rs[row] * (g[r] - md);
+  }
+}
+
+hipError_t launch_cast_scale(const double *B, const double *a, const double *c, int N, int ld,
+                             float *Bf, double *rs, double *as, double *cs, hipStream_t s) {
+  const size_t rows = (size_t)N * ld;
+  hipLaunchKernelGGL(k_cast_scale, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, B, a, c, N,
+                     ld, Bf, rs, as, cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_bt_resid(const double *B, const double *a, const double *c, const double *g,
+                           const double *dx, const double *rs, int N, int S, int ld, double *x,
+                           hipStream_t s) {
+  const size_t rows = (size_t)N * S;
+  hipLaunchKernelGGL(k_bt_resid, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, B, a, c, g,
+                     dx, rs, N, S, ld, x);
+  return hipGetLastError();
 }
 
 __global__ void k_maxreduce(const double *v, int n, double *out) {
@@ -157,6 +230,15 @@ hipError_t launch_scale(const Acc &acc, int ncols, int maxN, int maxS, hipStream
 }
 
 template <class Acc>
+hipError_t launch_axpy_size(const Acc &acc, int ncols, int maxN, double *ratio, double *out,
+                            double rtol, double atol, double y_floor, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy<Acc>, dim3(maxN, ncols), dim3(256), 0, s, acc, ratio, rtol, atol,
+                     y_floor);
+  hipLaunchKernelGGL(k_maxreduce, dim3(1), dim3(256), 0, s, ratio, maxN * ncols, out);
+  return hipGetLastError();
+}
+
+template <class Acc>
 hipError_t launch_axpy_ratio(const Acc &acc, int ncols, int maxN, double *ratio, double *out,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_axpy<Acc>, dim3(maxN, ncols), dim3(256), 0, s, acc, ratio,
@@ -171,6 +253,8 @@ template hipError_t launch_scale<OneCol>(const OneCol &, int, int, int, hipStrea
 template hipError_t launch_scale<ManyCols>(const ManyCols &, int, int, int, hipStream_t);
 template hipError_t launch_axpy_ratio<OneCol>(const OneCol &, int, int, double *, double *,
                                               hipStream_t);
+template hipError_t launch_axpy_size<OneCol>(const OneCol &, int, int, double *, double *, double,
+                                             double, double, hipStream_t);
 template hipError_t launch_axpy_ratio<ManyCols>(const ManyCols &, int, int, double *, double *,
                                                 hipStream_t);
 

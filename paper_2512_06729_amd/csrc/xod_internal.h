@@ -92,9 +92,11 @@ struct Options {
   int outer_nmat = 1;     // ... for launches of at least this many blocks
   double refine_tol = 1e-7;    // mixed refinement: relative size of the last correction
   double refine_atol = 1e-14;  // ... and its floor, relative to the layer's largest increment
+  int refine64 = 1;            // FP64 steps: refinements with the FP64 factors (0: none)
   int gemm_large = 1;     // 128 x 128 product tiles for large batches
   int gemm_k = 32;        // K step of the block products staged in LDS (16 or 32)
   int panel_sync = 2;     // barriers per Gauss-Jordan column (1 or 2)
+  int panel_defer = 0;    // 1: panel eliminations of other columns deferred by one column
   int gemm_lib = 0;       // cyclic-reduction block products: 1 = rocBLAS batched GEMM
   int graph = 1;          // replay captured launch sequences (cyclic reduction)
   int profile = 0;        // record HIP events around profiled launches
@@ -128,7 +130,8 @@ hipError_t launch_solve_fp64(const Acc &acc, int ncols, int maxN, int ld, hipStr
 template <class Acc>
 hipError_t launch_factor_mixed(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s);
 // Refinement (mixed precision), per column of the launch:
-//   residual  x = rs * (f - M dx)   (dw: the column's w buffer as scratch)
+//   residual  x = rs * (f - M dx)   (dw: the column's w buffer as scratch;
+//             rs null: no row scaling, for FP64 factors)
 //   scale     x = rs * f
 //   axpy      dx += x, ratio[col * maxN + k] = the componentwise size of x
 //             in layer k, max_i |x_i| / (rtol |n_i + dx_i| + atol max|dx_k|)
@@ -153,8 +156,23 @@ hipError_t launch_scale(const Acc &acc, int ncols, int maxN, int maxS, hipStream
 template <class Acc>
 hipError_t launch_axpy_ratio(const Acc &acc, int ncols, int maxN, double *ratio, double *out,
                              hipStream_t s);
+// The same with explicit rtol, atol and mixing-ratio floor (rtol 1, atol 0:
+// the largest relative correction of a component above the floor, a Newton
+// iteration's size).
+template <class Acc>
+hipError_t launch_axpy_size(const Acc &acc, int ncols, int maxN, double *ratio, double *out,
+                            double rtol, double atol, double y_floor, hipStream_t s);
 template <class Acc>
 hipError_t launch_solve_mixed(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s);
+
+// Explicit block systems in mixed precision (caller's FP64 B [N*ld*ld], a, c
+// [N*ld]): row scales rs, the scaled FP32 blocks Bf and scaled couplings
+// as, cs; and the scaled FP64 residual x = rs * (g - M dx) ([N*S] layout).
+hipError_t launch_cast_scale(const double *B, const double *a, const double *c, int N, int ld,
+                             float *Bf, double *rs, double *as, double *cs, hipStream_t s);
+hipError_t launch_bt_resid(const double *B, const double *a, const double *c, const double *g,
+                           const double *dx, const double *rs, int N, int S, int ld, double *x,
+                           hipStream_t s);
 
 // One square block inverted in place by Gauss-Jordan elimination: its
 // storage, pivot bookkeeping (piv[j] = row chosen for column j, rstep = the

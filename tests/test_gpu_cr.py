@@ -264,24 +264,28 @@ def test_outer_panel_blocking_agrees(solver):
 @pytest.mark.parametrize("solver,precision", [(1, 0), (0, 0), (1, 1)])
 def test_panel_exchange_variants_agree(solver, precision):
     """The pivot row exchanged after one barrier (every wave publishes its
-    best row) or after two (only the winner's): the same pivots and the same
-    arithmetic, identical bits."""
+    best row) or after two (only the winner's), and the other columns'
+    eliminations deferred by one column: the same pivots and the same
+    arithmetic in the same order per element, identical bits."""
     import paper_2512_06729_amd as xod
     net, col = synth.make_config(2 if solver == 0 else 3)
     stream = torch.cuda.current_stream().cuda_stream
     gnet = xod.Network(net)
     out = []
-    default = xod.get_option("panel_sync")
+    default = (xod.get_option("panel_sync"), xod.get_option("panel_defer"))
     try:
-        for sync in (1, 2):
+        for sync, defer in ((1, 0), (2, 0), (2, 1)):
             xod.set_option("panel_sync", sync)
+            xod.set_option("panel_defer", defer)
             g = xod.Column(gnet, col, precision=precision, stream=stream, solver=solver)
             xod.xod_step(g, 1e-5)
             out.append(g.state())
             g.close()
     finally:
-        xod.set_option("panel_sync", default)
+        xod.set_option("panel_sync", default[0])
+        xod.set_option("panel_defer", default[1])
     np.testing.assert_array_equal(out[0], out[1])
+    np.testing.assert_array_equal(out[0], out[2])
 
 
 @pytest.mark.parametrize("precision", [0, 1])

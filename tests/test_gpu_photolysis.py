@@ -108,7 +108,8 @@ def test_step_with_lagged_spectrum_matches_oracle(solver, dt):
     xod.xod_step(gcol, dt)
     got = gcol.state()
     assert np.max(np.abs(ref - gray)) > 0          # the spectrum changes the step
-    G.assert_state_agrees(got, ref, delta, rel=1e-9)
+    # the refined GPU solve is held to the oracle's own forward-error bound
+    G.assert_state_agrees_kappa(got, ref, delta, G.block_kappa(ref_prob, col.n0, dt), rel=1e-9)
 
 
 def test_back_to_gray_gives_the_gray_bits():
