@@ -463,6 +463,24 @@ xod_status xod_photolysis_spectral(int32_t N, int32_t S, int32_t A, int32_t L, i
                                    double t_f, double mu, void *work, size_t work_bytes,
                                    double *kph, void *stream);
 
+/* xod_photolysis_spectral without a workspace argument and without any
+ * device allocation, for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, results and checks otherwise.  The workspace is a fixed 64 MiB
+ * device array, one per GPU the library runs on, held until the process
+ * ends: sizes whose xod_photolysis_workspace(N, A, L, P) exceeds 64 MiB are
+ * refused with XOD_EINVAL (the 150-layer, 463-absorber, 10,000-bin,
+ * 772-reaction workload needs 36.6 MB).  `stream` must belong to the
+ * current device.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, other host threads) race and must be
+ * serialised by the caller. */
+xod_status xod_photolysis_spectral_noalloc(int32_t N, int32_t S, int32_t A, int32_t L,
+                                           int32_t P, const double *n, const double *dz,
+                                           const int32_t *absorbers, const double *sig_ext,
+                                           const double *J0, const double *dlam,
+                                           const double *sig_ph, double t_f, double mu,
+                                           double *kph, void *stream);
+
 /* Kernel options (process-wide; for tests and tuning).
  *   "gemm": 0 = VALU FMA Schur update, 1 = MFMA Schur update (default).
  *   "update32": 1 = MFMA trailing update in 32-column strips by four-wave

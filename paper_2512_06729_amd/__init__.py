@@ -155,6 +155,11 @@ _f = {
                                     c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                     c_double, c_double, c_void_p, ctypes.c_size_t, c_void_p,
                                     c_void_p),
+    "xod_photolysis_spectral_noalloc": _sig("xod_photolysis_spectral_noalloc", ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int32, c_void_p, c_void_p, c_void_p,
+                                            c_void_p, c_void_p, c_void_p, c_void_p, c_double,
+                                            c_double, c_void_p, c_void_p),
     "xod_get_option": _sig("xod_get_option", ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)),
     "xod_batch_create": _sig("xod_batch_create", ctypes.POINTER(c_void_p), c_int32,
                              ctypes.POINTER(c_void_p)),
@@ -235,6 +240,20 @@ def photolysis_spectral(n, dz, absorbers, sig_ext, J0, dlam, sig_ph, kph, work, 
         _dev(sig_ext) if A else None, _dev(J0), _dev(dlam), _dev(sig_ph) if P else None,
         float(t_f), float(mu), _dev(work), work.numel() * work.element_size(),
         _dev(kph) if P else None, stream))
+
+
+def photolysis_spectral_noalloc(n, dz, absorbers, sig_ext, J0, dlam, sig_ph, kph, t_f=1.0,
+                                mu=1.0, stream=None):
+    """photolysis_spectral without a workspace: the library's fixed device
+    array serves instead (xod_photolysis_spectral_noalloc; no allocation)."""
+    N, S = n.shape
+    A = absorbers.shape[0]
+    L = J0.shape[0]
+    P = sig_ph.shape[0]
+    _check(_f["xod_photolysis_spectral_noalloc"](
+        N, S, A, L, P, _dev(n), _dev(dz), _dev(absorbers) if A else None,
+        _dev(sig_ext) if A else None, _dev(J0), _dev(dlam), _dev(sig_ph) if P else None,
+        float(t_f), float(mu), _dev(kph) if P else None, stream))
 
 
 def get_option(name):

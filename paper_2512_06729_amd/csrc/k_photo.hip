@@ -12,6 +12,7 @@
 #include "mfma.h"
 
 #include <algorithm>
+#include <mutex>
 
 #define PH_CHECK(cond, msg)      \
   do {                           \
@@ -242,6 +243,72 @@ extern "C" xod_status xod_photolysis_spectral(int32_t N, int32_t S, int32_t A, i
   PH_CHECK(P == 0 || (sig_ph && kph), "xod_photolysis_spectral: null cross-section table");
   PH_CHECK(work_bytes >= photolysis_work_bytes(N, A, L, P),
            "xod_photolysis_spectral: workspace smaller than xod_photolysis_workspace()");
+  XOD_HIP(launch_photolysis(N, S, A, L, P, n, dz, absorbers, sig_ext, J0, dlam, sig_ph, t_f, mu,
+                            work, kph, (hipStream_t)stream));
+  return XOD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant: the workspace is a fixed device array (one copy
+// per device, held until the process ends).  Host code must not pass the
+// array's name to a kernel: its device address is looked up once per device
+// with hipGetSymbolAddress and kept in scratch_dev.
+namespace xod {
+namespace {
+constexpr size_t kPhScratchBytes = (size_t)64 << 20;
+constexpr int kPhMaxDevices = 64;
+static __device__ __align__(256) double scratch[kPhScratchBytes / sizeof(double)];
+std::mutex scratch_mu;
+void *scratch_dev[kPhMaxDevices] = {};
+
+xod_status scratch_address(void **out) {
+  int dev = -1;
+  XOD_HIP(hipGetDevice(&dev));
+  PH_CHECK(dev >= 0 && dev < kPhMaxDevices,
+           "xod_photolysis_spectral_noalloc: device index out of range");
+  std::lock_guard<std::mutex> g(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      ::xod::set_error(std::string("xod_photolysis_spectral_noalloc: hipGetSymbolAddress "
+                                   "failed: ") + hipGetErrorString(e));
+      return XOD_EHIP;
+    }
+    scratch_dev[dev] = p;
+  }
+  *out = scratch_dev[dev];
+  return XOD_OK;
+}
+}  // namespace
+}  // namespace xod
+
+extern "C" xod_status xod_photolysis_spectral_noalloc(int32_t N, int32_t S, int32_t A,
+                                                      int32_t L, int32_t P, const double *n,
+                                                      const double *dz, const int32_t *absorbers,
+                                                      const double *sig_ext, const double *J0,
+                                                      const double *dlam, const double *sig_ph,
+                                                      double t_f, double mu, double *kph,
+                                                      void *stream) {
+  using namespace xod;
+  PH_CHECK(N > 0 && S > 0 && A >= 0 && L > 0 && P >= 0,
+           "xod_photolysis_spectral_noalloc: need N, S, L > 0 and A, P >= 0");
+  PH_CHECK(mu > 0.0, "xod_photolysis_spectral_noalloc: mu must be positive");
+  PH_CHECK(n && dz && J0 && dlam, "xod_photolysis_spectral_noalloc: null pointer");
+  PH_CHECK(A == 0 || (absorbers && sig_ext),
+           "xod_photolysis_spectral_noalloc: null absorber table");
+  PH_CHECK(P == 0 || (sig_ph && kph),
+           "xod_photolysis_spectral_noalloc: null cross-section table");
+  const size_t need = photolysis_work_bytes(N, A, L, P);
+  if (need > kPhScratchBytes) {
+    ::xod::set_error("xod_photolysis_spectral_noalloc: these sizes need " +
+                     std::to_string(need) + " bytes of workspace, more than the fixed " +
+                     std::to_string(kPhScratchBytes) + " (use xod_photolysis_spectral)");
+    return XOD_EINVAL;
+  }
+  void *work = nullptr;
+  const xod_status st = scratch_address(&work);
+  if (st != XOD_OK) return st;
   XOD_HIP(launch_photolysis(N, S, A, L, P, n, dz, absorbers, sig_ext, J0, dlam, sig_ph, t_f, mu,
                             work, kph, (hipStream_t)stream));
   return XOD_OK;
