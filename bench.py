@@ -431,6 +431,105 @@ def bench_serve(xod, torch, args, precision, gnet, net):
             "precision": "fp64" if precision == xod.XOD_FP64 else "mixed"}, states
 
 
+def bench_serve_sweep(xod, torch, args):
+    """Continuous-batching serving of a two-size request stream (90- and
+    250-species networks, 60-120 layers, per-request T offset, Kzz scale
+    and initial state; steady state at tol 1e-4, t_end 1e12 s, at most
+    3000 steps), Poisson arrivals at each rate of --serve-sweep, FP64 and
+    mixed precision: p50 / p99 latency, solves/s, and requests the loop
+    left unfinished.  Then the accuracy of the precisions against each
+    other on two requests solved to tol 1e-9."""
+    import numpy as np
+    import synth
+    stream = torch.cuda.current_stream().cuda_stream
+    nets = {90: synth.make_network("c2", seed=1002), 250: synth.make_network("s250", seed=4250)}
+    gnets = {s: xod.Network(n) for s, n in nets.items()}
+    rates = [float(r) for r in args.serve_sweep.split(",")]
+    n = args.serve_requests
+    reqs = [synth.make_mixed_request(j, nets) for j in range(n)]
+    fp = max(xod.Server.footprint(gnets[s], c.N, xod.XOD_MIXED) for s, c in reqs)
+    out = {"workload": f"{n} requests per rate, networks of 90 and 250 species, 60-120 layers",
+           "slots": args.serve_slots}
+    for prec, pname in ((xod.XOD_FP64, "fp64"), (xod.XOD_MIXED, "mixed")):
+        per = []
+        for rate in rates:
+            arrivals = synth.poisson_arrivals(n, rate)
+            srv = xod.Server(hbm_budget_bytes=args.serve_slots * fp, max_slots=args.serve_slots,
+                             precision=prec, stream=stream)
+            ids, done, lat = [], {}, []
+            t0 = time.perf_counter()
+            nsub = 0
+            while len(done) < n:
+                now = time.perf_counter() - t0
+                while nsub < n and arrivals[nsub] <= now:
+                    s, c = reqs[nsub]
+                    ids.append(srv.submit(gnets[s], c, tol_rel=1e-4, t_end=1e12,
+                                          max_steps=3000))
+                    nsub += 1
+                if nsub == len(done):
+                    time.sleep(max(0.0, min(0.01, arrivals[nsub] - now)))
+                    continue
+                srv.step()
+                for rid in ids:
+                    if rid in done:
+                        continue
+                    o = srv.poll(rid)
+                    if o["state"] >= xod.Server.DONE:
+                        done[rid] = o
+                        lat.append(o["latency_s"])
+                        srv.release(rid)
+                if time.perf_counter() - t0 > args.serve_timeout:
+                    break
+            wall = time.perf_counter() - t0
+            srv.close()
+            lat = np.array(lat)
+            conv = sum(1 for o in done.values() if o["state"] == xod.Server.DONE)
+            per.append({"rate_per_s": rate, "completed": len(done), "converged": conv,
+                        "unfinished": n - len(done),
+                        "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
+                        "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
+                        "solves_per_s": len(done) / wall, "wall_s": wall})
+            progress(f"serve sweep {pname} rate {rate}: {len(done)}/{n} done in {wall:.1f} s")
+        out[pname] = per
+    # accuracy: two requests to a tight tolerance in both precisions
+    diffs = []
+    for j in range(2):
+        s, c = reqs[j]
+        st = {}
+        for prec in (xod.XOD_FP64, xod.XOD_MIXED):
+            g = xod.Column(gnets[s], c, precision=prec, stream=stream)
+            xod.xod_integrate_to_steady_state(g, tol_rel=1e-9, t_end=1e30, max_steps=6000,
+                                              check=False)
+            st[prec] = g.state()
+            ngas = g.grid()["ngas"][:, None]
+            g.close()
+        a, b = st[xod.XOD_FP64], st[xod.XOD_MIXED]
+        keep = a > 1e-30 * ngas
+        diffs.append(float(np.max(np.abs(b - a)[keep] / a[keep])))
+    out["mixed_vs_fp64_tight_steady_state_max_rel_diff_y_gt_1e-30"] = diffs
+    for g in gnets.values():
+        g.close()
+    return out
+
+
+def bench_parcel(xod, torch, gnet, col, stream):
+    """One global iteration of the Lagrangian parcel (bottom to top and back
+    over the 594-species x 150-layer column, molecular diffusion as a
+    pseudo-reaction, adaptive backward Euler within each layer's residence
+    time): wall time, visits and steps.  Sequential by construction: every
+    step is one S x S block."""
+    g = xod.Column(gnet, col, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = xod.xod_parcel_pass(g, 1e-8)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    g.close()
+    return {"workload": "one parcel pass over the 594 x 150 column (299 layer visits)",
+            "wall_s": el, "visits": st["visits"], "steps": st["steps"],
+            "rejects": st["rejects"], "ms_per_step": 1e3 * el / max(1, st["steps"] + st["rejects"])}
+
+
 def panel_traffic():
     """HBM bytes per k_panel launch from the committed rocprofv3 counter runs
     (calibrated FETCH_SIZE + WRITE_SIZE), or None if the kernel source has
@@ -481,11 +580,15 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--skip-serve", action="store_true")
     ap.add_argument("--skip-photolysis", action="store_true")
+    ap.add_argument("--skip-parcel", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=4)
     ap.add_argument("--serve-rate", type=float, default=5.0)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-timeout", type=float, default=70.0)
     ap.add_argument("--serve-fp64-only", action="store_true")
+    ap.add_argument("--serve-sweep", default="",
+                    help="comma-separated arrival rates: run the two-size serving sweep "
+                         "(not part of the default run)")
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="copy 256 MiB device to device three times first (the plain copy "
                          "that scales FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -709,6 +812,11 @@ def main():
         if smx:
             smx["max_rel_diff_vs_fp64_steady_state"] = diffs
         line["serve"] = {"fp64": s64, "mixed": smx or None}
+    if not args.skip_parcel:
+        line["parcel_pass"] = bench_parcel(xod, torch, gnet, col, stream)
+        progress("parcel pass: %.2f s" % line["parcel_pass"]["wall_s"])
+    if args.serve_sweep:
+        line["serve_sweep"] = bench_serve_sweep(xod, torch, args)
     if not args.skip_photolysis:
         line["photolysis_spectral"] = bench_photolysis(xod, torch, net, col, col_dz)
         progress("spectral photolysis: %.1f us per call" % line["photolysis_spectral"]["us_per_call"])
@@ -726,10 +834,13 @@ def main():
         # the oracle's three steps (each trajectory on its own)
         err = {}
         k = len(ref_states)
-        for name, prec in (("fp64", xod.XOD_FP64), ("mixed", xod.XOD_MIXED)):
+        for name, prec, r64 in (("fp64", xod.XOD_FP64, 0), ("fp64_refined", xod.XOD_FP64, 1),
+                                ("mixed", xod.XOD_MIXED, 0)):
             if name == "mixed" and args.skip_mixed:
                 continue
+            xod.set_option("refine64", r64)
             traj = trajectory(xod, gnet, col, prec, solver, 1e-6, k, stream)
+            xod.set_option("refine64", 0)
             err[name] = per_species(traj[-1], ref_states[-1], ngas)
             err[name]["steps"] = k
         line["per_species_error_vs_oracle"] = err

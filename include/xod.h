@@ -396,6 +396,37 @@ typedef struct {
 xod_status xod_integrate_fixed_dt(xod_column *col, double dt, int32_t nsteps,
                                   int32_t reuse, xod_reuse_stats *st);
 
+/* One global iteration of the Lagrangian parcel scheme (the paper's own
+ * model: Section 2, an air parcel tracked from the bottom of the atmosphere
+ * to the top and back; Section 2.1, molecular diffusion as a
+ * pseudo-reaction) on the column's state, which is the profile and is
+ * updated in place.  The parcel visits layers 0, 1, ..., N-1, N-2, ..., 0;
+ * at layer k it takes the layer's temperature and gas density (its mixing
+ * ratios carried over), stays for the layer's eddy mixing time
+ * dz_k^2 / K_k (eddy mixing is the parcel's motion, so K appears nowhere
+ * else), and evolves by the layer's chemistry plus molecular diffusion: the
+ * molecular-diffusion part of the column's transport (K = 0), its
+ * self-coefficient removing the molecule from the parcel where negative,
+ * every gain (the profile's neighbours, a positive self-coefficient on the
+ * profile's own density) entering as a fixed source.  The integration is by
+ * linearly implicit backward-Euler steps on the layer's dense S x S system
+ * under the steady-state driver's control (xod_integrate_to_steady_state)
+ * inside the residence time, the first step of size dt0, each later visit
+ * starting with the step size the previous one ended on; the parcel's
+ * composition at the end of a visit becomes the profile at that layer.
+ * dt_last (may be NULL) receives the step size the last visit ended on.
+ * FP64, closed columns with gray photolysis and K > 0 in every layer
+ * (XOD_EINVAL otherwise); XOD_ENOTCONVERGED if a visit's step size
+ * collapses (more than 30 rejections in a row).  Synchronous. */
+typedef struct {
+  int64_t steps, rejects;   /* backward-Euler steps taken and rejected        */
+  double clipped;           /* negative density clipped to zero (sum)         */
+  int32_t visits;           /* layer visits (2N - 1)                          */
+  int32_t pad_;
+} xod_parcel_stats;
+xod_status xod_parcel_pass(xod_column *col, double dt0, double *dt_last,
+                           xod_parcel_stats *st);
+
 /* Copy of the last error message of this thread (always NUL-terminated). */
 xod_status xod_last_error(char *buf, size_t len);
 
@@ -505,6 +536,17 @@ xod_status xod_photolysis_spectral_noalloc(int32_t N, int32_t S, int32_t A, int3
  *            absolute floor below;
  *   "refine_atol_exp": e in 8..17: that floor, 10^-e times the layer's
  *            largest increment (default 14);
+ *   "refine64": 0..10 corrections of every FP64 solve of a step with its
+ *            own factors (residual in FP64 from the reaction list), a fixed
+ *            number with no host round trip; a layer whose last correction
+ *            exceeds 1e5 times the mixed-precision tolerance keeps the
+ *            unrefined solution.  Default 0: the explicit inverses make the
+ *            FP64 solve forward stable only, and one correction brings the
+ *            trace components to the residual's rounding (30 times closer to
+ *            the oracle on the 594-species column), but the adaptive drivers'
+ *            negativity test then sees the linearised step's own negative
+ *            trace densities, which the unrefined solve happens to miss;
+ *            the 90-species steady state then stalls with block Thomas;
  *   "outer": Gauss-Jordan outer panel width, 32 (default), 64, 96 or 128:
  *            with a width above 32 the 32-column panels of an outer panel
  *            update only its own columns, then one rank-width update covers

@@ -94,6 +94,14 @@ class ReuseStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ParcelStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("rejects", ctypes.c_int64), ("clipped", c_double),
+                ("visits", c_int32), ("pad_", c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+
+
 class SSResult(ctypes.Structure):
     _fields_ = [("t", c_double), ("dt", c_double), ("clipped", c_double),
                 ("steps", ctypes.c_int64), ("rejects", ctypes.c_int64),
@@ -143,6 +151,8 @@ _f = {
     "xod_integrate_to_steady_state": _sig("xod_integrate_to_steady_state", c_void_p,
                                           ctypes.POINTER(SSOpts), ctypes.POINTER(SSResult)),
     "xod_last_error": _sig("xod_last_error", ctypes.c_char_p, ctypes.c_size_t),
+    "xod_parcel_pass": _sig("xod_parcel_pass", c_void_p, c_double, P_dbl,
+                            ctypes.POINTER(ParcelStats)),
     "xod_integrate_fixed_dt": _sig("xod_integrate_fixed_dt", c_void_p, c_double, c_int32,
                                    c_int32, ctypes.POINTER(ReuseStats)),
     "xod_set_option": _sig("xod_set_option", ctypes.c_char_p, ctypes.c_int64),
@@ -502,6 +512,19 @@ def xod_integrate_to_steady_state(col, tol_rel=0.0, y_floor=0.0, y_sig=0.0, t_en
         raise XodError(st, last_error())
     out = r.as_dict()
     out["status"] = st
+    return out
+
+
+def xod_parcel_pass(col, dt0=1e-8):
+    """One bottom-to-top-to-bottom pass of the Lagrangian parcel over the
+    column's profile (its state, updated in place); returns the statistics
+    and the step size the last visit ended on."""
+    st = ParcelStats()
+    dt_last = c_double()
+    _check(_f["xod_parcel_pass"](col.handle, float(dt0), ctypes.byref(dt_last),
+                                 ctypes.byref(st)))
+    out = st.as_dict()
+    out["dt_last"] = dt_last.value
     return out
 
 

@@ -616,6 +616,9 @@ extern "C" xod_status xod_column_set_boundary(xod_column *col, const xod_boundar
   }
   XOD_HIP(hipStreamSynchronize(col->stream));
   col->has_bsrc = any_src;
+  bool any_v = false;
+  for (int y = 0; y < S; ++y) any_v = any_v || vt[y] != 0.0 || vd[y] != 0.0;
+  col->open_ends = any_src || any_v;
   col->fact_dt = 0.0;     // the step matrix changed
   return XOD_OK;
 }
@@ -978,6 +981,8 @@ xod_status run_update(xod_column *c, bool clip, double y_floor, double y_sig, do
   return XOD_OK;
 }
 
+constexpr double kRefineKeepMost = 1e5;
+
 // Iterative refinement of an FP64 solve with its own factors: the residual
 // F - M delta in FP64 from the reaction list and the transport coefficients
 // (no row scaling), a solve for the correction, delta += correction, a fixed
@@ -994,6 +999,7 @@ xod_status refine_fp64(xod_column *c, int *iters) {
   OneCol one{a};
   const bool cr = c->solver == XOD_SOLVER_CR;
   XOD_HIP(hipMemcpyAsync(c->dx, c->x, NSb, hipMemcpyDeviceToDevice, c->stream));
+  XOD_HIP(hipMemcpyAsync(c->resid, c->x, NSb, hipMemcpyDeviceToDevice, c->stream));
   for (int it = 1; it <= options().refine64; ++it) {
     XOD_HIP(launch_residual(one, 1, c->N, c->S, c->R, c->stream));
     if (cr)
@@ -1003,7 +1009,10 @@ xod_status refine_fp64(xod_column *c, int *iters) {
     XOD_HIP(launch_axpy_ratio(one, 1, c->N, c->ratio, c->rmax, c->stream));
     *iters = it;
   }
-  XOD_HIP(hipMemcpyAsync(c->x, c->dx, NSb, hipMemcpyDeviceToDevice, c->stream));
+  // layers whose last correction exceeds 1e5 times the tolerance (about 1 %
+  // of a density) keep the unrefined solution: there the factors' solve is
+  // too inaccurate for a correction to help (nearly singular steps)
+  XOD_HIP(launch_keep_refined(one, 1, c->N, c->S, c->ratio, kRefineKeepMost, c->stream));
   return XOD_OK;
 }
 

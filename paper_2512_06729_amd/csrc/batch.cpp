@@ -185,8 +185,9 @@ xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double
         // columns' argument copies carry no row scales)
         for (int j = 0; j < g.nc; ++j) {
           xod_column *c = cols[(*g.idx)[j]];
-          XOD_HIP(hipMemcpyAsync(c->dx, c->x, (size_t)c->N * c->S * sizeof(double),
-                                 hipMemcpyDeviceToDevice, st));
+          const size_t bytes = (size_t)c->N * c->S * sizeof(double);
+          XOD_HIP(hipMemcpyAsync(c->dx, c->x, bytes, hipMemcpyDeviceToDevice, st));
+          XOD_HIP(hipMemcpyAsync(c->resid, c->x, bytes, hipMemcpyDeviceToDevice, st));
         }
         for (int it = 1; it <= options().refine64; ++it) {
           XOD_HIP(launch_residual(acc, g.nc, g.maxN, g.maxS, g.maxR, st));
@@ -194,11 +195,7 @@ xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double
           XOD_HIP(launch_axpy_ratio(acc, g.nc, g.maxN, d_ratio + g.roff, d_rmax + gi, st));
           g.iters = it;
         }
-        for (int j = 0; j < g.nc; ++j) {
-          xod_column *c = cols[(*g.idx)[j]];
-          XOD_HIP(hipMemcpyAsync(c->x, c->dx, (size_t)c->N * c->S * sizeof(double),
-                                 hipMemcpyDeviceToDevice, st));
-        }
+        XOD_HIP(launch_keep_refined(acc, g.nc, g.maxN, g.maxS, d_ratio + g.roff, 1e5, st));
       }
     }
   }

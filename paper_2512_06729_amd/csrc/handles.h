@@ -62,6 +62,18 @@ struct xod_column {
   std::vector<double> trd_bot0, trd_top0;  // trd rows 0 and N-1 of the closed column
   double *bsrc = nullptr;
   bool has_bsrc = false;
+  bool open_ends = false;   // a boundary exchange with nonzero velocities or emission is set
+  // Lagrangian parcel pass (xod_parcel_pass): molecular-diffusion-only
+  // transport coefficients [N*S] (trl, trd, tru, the loss part min(trd, 0)),
+  // set-up scratch, and the single-layer step buffers; allocated on first use.
+  double *pc_trl = nullptr, *pc_trd = nullptr, *pc_tru = nullptr, *pc_loss = nullptr;
+  double *pc_setup = nullptr;
+  double *pc_p = nullptr, *pc_q = nullptr, *pc_f = nullptr, *pc_x = nullptr, *pc_zero = nullptr;
+  double *pc_w = nullptr, *pc_dwd = nullptr, *pc_B = nullptr, *pc_a = nullptr, *pc_c = nullptr;
+  double *pc_gs = nullptr, *pc_partial = nullptr, *pc_stats = nullptr;
+  int *pc_piv = nullptr, *pc_rstep = nullptr;
+  UpdArgs *pc_upd = nullptr;
+  RedArgs *pc_red = nullptr;
   double *dwd = nullptr;   // [N*R*6] reaction-rate derivatives of the last Jacobian
   double *n = nullptr, *ntmp = nullptr, *kf = nullptr, *kr = nullptr, *w = nullptr,
          *f = nullptr, *x = nullptr, *gs = nullptr, *resid = nullptr, *dx = nullptr;
@@ -152,6 +164,7 @@ struct xod_column {
     a_.rstep = rstep;
     a_.x = x;
     a_.dx = dx;
+    a_.x0 = resid;
     a_.gs = gs;
     a_.flag = flag;
     return a_;

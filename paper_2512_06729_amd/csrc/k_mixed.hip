@@ -247,8 +247,32 @@ hipError_t launch_axpy_ratio(const Acc &acc, int ncols, int maxN, double *ratio,
   return hipGetLastError();
 }
 
+template <class Acc>
+__global__ void __launch_bounds__(256) k_keep_refined(Acc acc, const double *ratio, int maxN,
+                                                      double most) {
+  const ColArgs &c = acc(blockIdx.z);
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (y >= c.S || k >= c.N) return;
+  const size_t o = (size_t)k * c.S + y;
+  const double q = ratio[(size_t)blockIdx.z * maxN + k];
+  c.x[o] = q <= most ? c.dx[o] : c.x0[o];
+}
+
+template <class Acc>
+hipError_t launch_keep_refined(const Acc &acc, int ncols, int maxN, int maxS, const double *ratio,
+                               double most, hipStream_t s) {
+  hipLaunchKernelGGL(k_keep_refined<Acc>, dim3((maxS + 255) / 256, maxN, ncols), dim3(256), 0, s,
+                     acc, ratio, maxN, most);
+  return hipGetLastError();
+}
+
 template hipError_t launch_residual<OneCol>(const OneCol &, int, int, int, int, hipStream_t);
 template hipError_t launch_residual<ManyCols>(const ManyCols &, int, int, int, int, hipStream_t);
+template hipError_t launch_keep_refined<OneCol>(const OneCol &, int, int, int, const double *,
+                                                double, hipStream_t);
+template hipError_t launch_keep_refined<ManyCols>(const ManyCols &, int, int, int,
+                                                  const double *, double, hipStream_t);
 template hipError_t launch_scale<OneCol>(const OneCol &, int, int, int, hipStream_t);
 template hipError_t launch_scale<ManyCols>(const ManyCols &, int, int, int, hipStream_t);
 template hipError_t launch_axpy_ratio<OneCol>(const OneCol &, int, int, double *, double *,

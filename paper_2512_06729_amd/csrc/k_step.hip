@@ -109,4 +109,40 @@ hipError_t launch_lincomb(double *out, const double *p, double alpha, const doub
   return hipGetLastError();
 }
 
+// Lagrangian parcel at layer k: the molecular-diffusion gains of its
+// right-hand side, f += max(trd_k, 0) prof_k + trl_k prof_{k-1} + tru_k
+// prof_{k+1} (the profile's densities as fixed sources), and the loss part
+// of the self-coefficient for all layers, loss = min(trd, 0).
+__global__ void __launch_bounds__(256) k_parcel_gain(double *f, const double *prof,
+                                                     const double *trl, const double *trd,
+                                                     const double *tru, int N, int S, int k) {
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= S) return;
+  const size_t o = (size_t)k * S + y;
+  double g = fmax(trd[o], 0.0) * prof[o];
+  if (k >= 1) g += trl[o] * prof[o - S];
+  if (k + 1 < N) g += tru[o] * prof[o + S];
+  f[y] += g;
+}
+
+__global__ void __launch_bounds__(256) k_min0(const double *in, double *out, size_t n) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    out[e] = fmin(in[e], 0.0);
+}
+
+hipError_t launch_parcel_gain(double *f, const double *prof, const double *trl,
+                              const double *trd, const double *tru, int N, int S, int k,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_parcel_gain, dim3((S + 255) / 256), dim3(256), 0, s, f, prof, trl, trd,
+                     tru, N, S, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_min0(const double *in, double *out, size_t n, hipStream_t s) {
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_min0, dim3((unsigned)blocks), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
 }  // namespace xod

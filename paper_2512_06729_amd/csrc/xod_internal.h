@@ -52,6 +52,7 @@ struct ColArgs {
   int *rstep;        // [N*ld] pivot step of each row (inverse of piv)
   double *x;         // solve vector [N*S] (in/out)
   double *dx;        // refined increment [N*S] (mixed precision)
+  double *x0;        // the unrefined solution of an FP64 refinement [N*S]
   double *dwd;       // [N*R*6] dw_r/dn_x for the distinct species x = rsp[6r+u]
   double *gs;        // solve scratch [N*ld]
   int *flag;         // [4]: singular layer, singular column, nonfinite, spare
@@ -92,7 +93,7 @@ struct Options {
   int outer_nmat = 1;     // ... for launches of at least this many blocks
   double refine_tol = 1e-7;    // mixed refinement: relative size of the last correction
   double refine_atol = 1e-14;  // ... and its floor, relative to the layer's largest increment
-  int refine64 = 1;            // FP64 steps: refinements with the FP64 factors (0: none)
+  int refine64 = 0;            // FP64 steps: refinements with the FP64 factors (0: none)
   int gemm_large = 1;     // 128 x 128 product tiles for large batches
   int gemm_k = 32;        // K step of the block products staged in LDS (16 or 32)
   int panel_sync = 2;     // barriers per Gauss-Jordan column (1 or 2)
@@ -164,6 +165,13 @@ hipError_t launch_axpy_size(const Acc &acc, int ncols, int maxN, double *ratio, 
                             double rtol, double atol, double y_floor, hipStream_t s);
 template <class Acc>
 hipError_t launch_solve_mixed(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s);
+// After an FP64 refinement: per layer, x = dx (refined) where the layer's
+// correction size ratio[col * maxN + k] is at most `most`, else x = x0 (the
+// unrefined solution): a correction that large means the factors' solve is
+// too inaccurate for the correction to help.
+template <class Acc>
+hipError_t launch_keep_refined(const Acc &acc, int ncols, int maxN, int maxS, const double *ratio,
+                               double most, hipStream_t s);
 
 // Explicit block systems in mixed precision (caller's FP64 B [N*ld*ld], a, c
 // [N*ld]): row scales rs, the scaled FP32 blocks Bf and scaled couplings
@@ -302,6 +310,13 @@ hipError_t launch_setup(const SetupArgs &a, hipStream_t st);
 hipError_t launch_update_state(const UpdArgs *dargs, const RedArgs *dred, int ncols,
                                hipStream_t s);
 hipError_t launch_invperm(const int *piv, int *rstep, int N, int ld, hipStream_t s);
+// Lagrangian parcel at layer k: f [S] += the molecular-diffusion gains from
+// the profile prof [N*S] (max(trd, 0) at k, trl from k-1, tru from k+1);
+// out = min(in, 0) over n doubles (the self-coefficient's loss part).
+hipError_t launch_parcel_gain(double *f, const double *prof, const double *trl,
+                              const double *trd, const double *tru, int N, int S, int k,
+                              hipStream_t s);
+hipError_t launch_min0(const double *in, double *out, size_t n, hipStream_t s);
 // out = alpha p + beta q over n doubles
 hipError_t launch_lincomb(double *out, const double *p, double alpha, const double *q,
                           double beta, size_t n, hipStream_t s);

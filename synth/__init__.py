@@ -14,8 +14,9 @@ at their shapes and sizes.
 
 from .network import make_network, NETWORK_PRESETS
 from .column import (make_column, COLUMN_PRESETS, make_config, make_batch, make_request,
-                     poisson_arrivals, make_spectrum, with_boundary)
+                     make_mixed_request, poisson_arrivals, make_spectrum, with_boundary)
 
 __all__ = ["make_network", "make_column", "make_config", "make_batch", "make_request",
+           "make_mixed_request",
            "poisson_arrivals", "make_spectrum", "with_boundary",
            "NETWORK_PRESETS", "COLUMN_PRESETS"]

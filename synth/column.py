@@ -157,6 +157,22 @@ def make_request(j, net):
     return make_column("c3", net, seed=5_000_000 + j, T_offset=dT, Kzz_scale=ks)
 
 
+def make_mixed_request(j, nets, n_range=(60, 120)):
+    """Serving request j of the two-size stream: network nets[size] with
+    the size drawn from the keys of nets (equal odds), the 120-layer
+    profile's pressure range on N ~ U{n_range} layers, T offset ~ U[-300,
+    300] K, Kzz scale ~ log-U[0.1, 10] and its own initial abundances
+    (seed 6,000,000 + j).  Returns (size, column)."""
+    rng = np.random.default_rng(6_000_000 + j)
+    sizes = sorted(nets)
+    size = sizes[int(rng.integers(0, len(sizes)))]
+    N = int(rng.integers(n_range[0], n_range[1] + 1))
+    dT = float(rng.uniform(-300.0, 300.0))
+    ks = float(10.0 ** rng.uniform(-1.0, 1.0))
+    return size, make_column("c2", nets[size], seed=6_000_000 + j, N=N, T_offset=dT,
+                             Kzz_scale=ks)
+
+
 def poisson_arrivals(n, rate, seed=5_000_000):
     """Arrival times (s) of n requests at a Poisson rate (per second)."""
     rng = np.random.default_rng(seed)

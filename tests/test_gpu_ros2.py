@@ -107,6 +107,9 @@ def test_steady_state_driver_method_checks():
         xod.xod_integrate_to_steady_state(gm, method=1, max_steps=3)
     assert e.value.status == xod.XOD_EINVAL
     with pytest.raises(xod.XodError) as e:
-        xod.xod_integrate_to_steady_state(gcol, method=2, max_steps=3)
+        xod.xod_integrate_to_steady_state(gcol, method=3, max_steps=3)
+    assert e.value.status == xod.XOD_EINVAL
+    with pytest.raises(xod.XodError) as e:
+        xod.xod_integrate_to_steady_state(gm, method=2, max_steps=3)
     assert e.value.status == xod.XOD_EINVAL
     gm.close()
