@@ -1,0 +1,89 @@
+"""The 90-species x 120-layer column (1200 reactions) at steady state on the
+GPU against the oracle's (tests/golden/config2_steady_state.npz, written by
+make_config2_steady_state.py from the oracle alone).
+
+* Fixed point: from the oracle's tol-1e-4 steady state, 40 backward-Euler
+  steps of ten times the mixing time (negatives clipped after each, as the
+  golden script does) bring both sides to the fixed point F(n) = 0 (the
+  oracle's last relative change: 1.5e-13).  The two fixed points are the
+  roots of the same F, evaluated in a different order, so they differ by
+  the conditioning of F's root times the rounding of the rate
+  coefficients: perturbing the oracle's k_f and k_r by 4e-16 relative
+  moves its fixed point by at most 2.1e-12 on mixing ratios above 1e-30;
+  the bound is 1e-10 there.
+* Driver: the GPU's adaptive driver from the initial state converges with
+  either factorisation at tol 1e-4.  The decisions of this controller are
+  sensitive to rounding on this column (the oracle takes 1743 steps and 858
+  rejections; 1e-13 changes elsewhere change them), so its end state is
+  compared with the fixed point, not step for step.  The oracle's own
+  tol-1e-4 end state lies within 1.5e-6 of the fixed point on mixing ratios
+  above 1e-30; the GPU's must lie within 1e-3 above 1e-20.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import synth  # noqa: E402
+from tests import gpu_common as G  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "config2_steady_state.npz")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    import paper_2512_06729_amd  # noqa: F401  (fails loudly if not built)
+
+
+def rel_errors(n, ref, ngas):
+    out = {}
+    for floor in (1e-30, 1e-20, 1e-10):
+        keep = ref > floor * ngas
+        out[floor] = float(np.max(np.abs(n - ref)[keep] / ref[keep]))
+    return out
+
+
+@pytest.mark.parametrize("solver", [0, 1])
+def test_fixed_point_matches_oracle(solver):
+    import paper_2512_06729_amd as xod
+    g = np.load(GOLDEN)
+    net, col = synth.make_config(2)
+    stream = torch.cuda.current_stream().cuda_stream
+    gnet = xod.Network(net)
+    gcol = xod.Column(gnet, col, stream=stream, solver=solver)
+    ngas = gcol.grid()["ngas"][:, None]
+    n = g["n_ss"]
+    dt = float(g["dt_fp"])
+    for _ in range(40):
+        gcol.set_state(n)
+        xod.xod_step(gcol, dt)
+        n = np.maximum(gcol.state(), 0.0)
+    err = rel_errors(n, g["n_fp"], ngas)
+    print(f"config-2 fixed point, solver {solver}: " +
+          ", ".join(f"y>{f:g}: {e:.2e}" for f, e in err.items()))
+    assert err[1e-30] <= 1e-10
+
+
+@pytest.mark.parametrize("solver", [0, 1])
+def test_driver_reaches_the_oracle_steady_state(solver):
+    import paper_2512_06729_amd as xod
+    g = np.load(GOLDEN)
+    net, col = synth.make_config(2)
+    stream = torch.cuda.current_stream().cuda_stream
+    gnet = xod.Network(net)
+    gcol = xod.Column(gnet, col, stream=stream, solver=solver)
+    res = xod.xod_integrate_to_steady_state(gcol, tol_rel=1e-4)
+    ngas = gcol.grid()["ngas"][:, None]
+    err = rel_errors(gcol.state(), g["n_fp"], ngas)
+    print(f"config-2 driver, solver {solver}: {res['steps']} steps, {res['rejects']} rejects "
+          f"(oracle {int(g['steps'])}, {int(g['rejects'])}); vs fixed point " +
+          ", ".join(f"y>{f:g}: {e:.2e}" for f, e in err.items()))
+    assert res["converged"] == 1
+    assert err[1e-20] <= 1e-3
