@@ -5,14 +5,21 @@ two 12-layer slices of the 90-species column (layers 40-51 and 108-119,
 molecular diffusion as a pseudo-reaction).
 
 Both sides take the same step-control decisions (the counts of steps and
-rejections must be equal), and the profiles agree to 1e-6 of each density
-above mixing ratio 1e-20.  These slices are chosen where the pass is well
-conditioned: perturbing every oracle solve by 1e-13 relative changes no
-decision there and the profile by at most 6e-9.  In the deepest layers of
-the 90-species column the same perturbation changes the decisions (the
-positivity-limited step control clips trace species) and the profile of
-some trace species by 30 %, so no two implementations can agree there
-beyond the invariants; the pins of the oracle cover those."""
+rejections must be equal).  The profiles are compared in bands of mixing
+ratio, because the library solves each visit's S x S systems with an
+explicit Gauss-Jordan inverse, whose rounding of a small component is
+relative to the largest terms of its row of the inverse, not to the
+component itself, and a pass takes 100-250 such solves.  The oracle with
+its LU solves replaced by explicit inverses (numpy's inv, then a product)
+moves its own profile by at most 5.8e-8 above mixing ratio 1e-10, 2.0e-6
+above 1e-15 and 7.6e-4 above 1e-20 on the layer 40-51 slice (c1: 3.9e-9,
+9.7e-7, 3.3e-5; layers 108-119: 1e-13 throughout), while a second LU solve
+of row-rescaled systems moves it by at most 2.3e-7 above 1e-20.  The bounds
+are 1e-6, 1e-5 and 1e-2 on those bands.  In the deepest layers of the
+90-species column even a 1e-13 perturbation of the solves changes the
+decisions (the positivity-limited step control clips trace species), so
+no two implementations can agree there beyond the invariants; the pins of
+the oracle cover those."""
 
 import numpy as np
 import pytest
@@ -61,8 +68,12 @@ def test_parcel_pass_matches_oracle(name, solver):
     assert st["visits"] == 2 * col.N - 1
     assert (st["steps"], st["rejects"]) == (steps, rejects)
     n = gcol.state()
-    keep = ref > 1e-20 * prob.grid.ngas[:, None]
-    np.testing.assert_allclose(n[keep], ref[keep], rtol=1e-6)
+    ngas = prob.grid.ngas[:, None]
+    for floor, rtol in ((1e-10, 1e-6), (1e-15, 1e-5), (1e-20, 1e-2)):
+        keep = ref > floor * ngas
+        err = float(np.max(np.abs(n - ref)[keep] / ref[keep]))
+        print(f"  y>{floor:g}: max rel {err:.2e} (bound {rtol:g})")
+        assert err <= rtol, (floor, err)
 
 
 def test_parcel_pass_refuses_what_it_does_not_model():
