@@ -258,6 +258,52 @@ def bench_config2(xod, torch, stream):
     return out
 
 
+def bench_reuse(xod, torch, stream, gnet3, col3):
+    """Factorisations kept across steps (the modified-Newton corrector of the
+    DLSODES family): the 90 x 120 column to steady state with method 2
+    against method 0 (cyclic reduction), and 20 fixed backward-Euler steps of
+    1e-6 s on the 594 x 150 column from its initial state with and without
+    reuse.  Reports wall time, steps and factorisations per step."""
+    import synth
+    from paper_2512_06729_amd import XOD_SOLVER_CR
+    net, col = synth.make_config(2)
+    gnet = xod.Network(net)
+    out = {"workload": "S=90, R=1200, N=120 to steady state (tol_rel 1e-4); S=594, R=7720, "
+                       "N=150, 20 steps of 1e-6 s"}
+    for method in (0, 2):
+        g = xod.Column(gnet, col, stream=stream, solver=XOD_SOLVER_CR)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = xod.xod_integrate_to_steady_state(g, tol_rel=1e-4, method=method, check=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[f"steady_state_method{method}"] = {
+            "wall_s": el, "steps": r["steps"], "rejects": r["rejects"],
+            "factorizations": r["factorizations"], "newton_iters": r["newton_iters"],
+            "factorizations_per_step": r["factorizations"] / max(1, r["steps"]),
+            "converged": r["converged"]}
+        g.close()
+    gnet.close()
+    gcol = xod.Column(gnet3, col3, stream=stream, solver=XOD_SOLVER_CR)
+    for reuse in (0, 1):
+        gcol.set_state(col3.n0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            st = xod.xod_integrate_fixed_dt(gcol, 1e-6, 20, reuse)
+        except xod.XodError as e:
+            out[f"fixed_dt_reuse{reuse}"] = {"error": str(e)}
+            continue
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[f"fixed_dt_reuse{reuse}"] = {
+            "steps_per_s": st["steps"] / el, "steps": st["steps"],
+            "factorizations": st["factorizations"], "newton_iters": st["newton_iters"],
+            "factorizations_per_step": st["factorizations"] / max(1, st["steps"])}
+    gcol.close()
+    return out
+
+
 def hbm_roofline(kern, name, algo_bytes, kernels):
     """Achieved HBM rate of a memory-bound kernel group from its event-timed
     launches and its algorithmic bytes per launch."""
@@ -581,6 +627,8 @@ def main():
     ap.add_argument("--skip-serve", action="store_true")
     ap.add_argument("--skip-photolysis", action="store_true")
     ap.add_argument("--skip-parcel", action="store_true")
+    ap.add_argument("--skip-reuse", action="store_true",
+                    help="skip the kept-factorisation legs (steady state method 2, fixed dt)")
     ap.add_argument("--serve-requests", type=int, default=4)
     ap.add_argument("--serve-rate", type=float, default=5.0)
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -795,6 +843,16 @@ def main():
         line["config2_steady_state"] = bench_config2(xod, torch, stream)
         progress("config 2 steady state: %.2f s (cr)" %
                  line["config2_steady_state"]["cr"]["wall_s"])
+    if not args.skip_reuse:
+        line["factor_reuse"] = bench_reuse(xod, torch, stream, gnet, col)
+        fr = line["factor_reuse"]
+        progress("factor reuse: steady state %.2f s with kept factorisations (%.2f per step), "
+                 "%.2f s without; fixed dt %s vs %s steps/s" % (
+                     fr["steady_state_method2"]["wall_s"],
+                     fr["steady_state_method2"]["factorizations_per_step"],
+                     fr["steady_state_method0"]["wall_s"],
+                     fr["fixed_dt_reuse1"].get("steps_per_s"),
+                     fr["fixed_dt_reuse0"].get("steps_per_s")))
     if not args.skip_serve:
         s64, n64 = bench_serve(xod, torch, args, xod.XOD_FP64, gnet, net)
         if args.serve_fp64_only:

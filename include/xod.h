@@ -332,8 +332,10 @@ xod_status xod_step_bdf2(xod_column *col, double dt, xod_step_stats *st);
  * backward-Euler step on a step matrix kept across steps (below), under the
  * same control:
  *   reject (dt /= 2) if the step is not finite or a species whose mixing
- *   ratio exceeded y_sig turns negative; accept otherwise, clip negatives to
- *   zero and set dt *= 2 / 1.2 / 0.7 for a control change c < 0.5 / < 0.9 /
+ *   ratio exceeded y_sig falls below mixing ratio -y_neg; accept otherwise,
+ *   clip negatives to zero (so a clipped overshoot adds at most y_neg of the
+ *   layer's gas to a species per step) and set dt *= 2 / 1.2 / 0.7 for a
+ *   control change c < 0.5 / < 0.9 /
  *   otherwise, c = max |n1 - n0| / max(n0, n1) over mixing ratios > y_sig;
  *   converged when max |dn| / n over mixing ratios > y_floor is < tol_rel
  *   with dt >= the mixing time (Section 3.2), or when t >= t_end.
@@ -362,6 +364,8 @@ typedef struct {
   int32_t method;             /* 0 backward Euler [0], 1 ROS2, 2 backward
                                  Euler with factorisations kept across steps
                                  (1 and 2: FP64 columns) */
+  double y_neg;      /* [1e-6]; a tiny value such as 1e-300 rejects any
+                        negative of a species above y_sig */
 } xod_ss_opts;
 typedef struct {
   double t, dt, clipped;

@@ -152,13 +152,16 @@ class SteadyResult:
 
 def steady_state(prob, n0, tol_rel=1.0e-4, y_floor=1.0e-30, y_sig=1.0e-10,
                  t_end=1.0e12, dt0=1.0e-8, max_steps=5000,
-                 max_consec_rejects=30, use_mix_rule=True, method="be"):
+                 max_consec_rejects=30, use_mix_rule=True, method="be", y_neg=1.0e-6):
     """Adaptive driver to steady state; each step is a backward-Euler step
     (method "be") or a ROS2 step (method "ros2"), with the same control.
 
     * Reject a step (dt <- dt/2) if it is not finite or if a species whose
-      mixing ratio exceeded y_sig turns negative; after more than
-      max_consec_rejects consecutive rejections give up (not converged).
+      mixing ratio exceeded y_sig turns more negative than -y_neg in mixing
+      ratio (y_neg = 0: any negative); after more than max_consec_rejects
+      consecutive rejections give up (not converged).  A smaller overshoot
+      is clipped like any other negative: it adds at most y_neg of the
+      layer's gas density to that species in that step.
     * On acceptance clip negative densities to zero (the clipped amount is
       recorded) and adapt dt from the largest relative change of the
       species above y_sig, c = max |n1 - n0| / max(n0, n1):
@@ -182,7 +185,7 @@ def steady_state(prob, n0, tol_rel=1.0e-4, y_floor=1.0e-30, y_sig=1.0e-10,
     while steps < max_steps:
         n_new, delta = step(prob, n, dt)
         sig = n > y_sig * ngas
-        if not np.all(np.isfinite(n_new)) or np.any(sig & (n_new < 0.0)):
+        if not np.all(np.isfinite(n_new)) or np.any(sig & (n_new < -y_neg * ngas)):
             rejects += 1
             consec += 1
             dt *= 0.5
@@ -278,7 +281,7 @@ class ReuseResult(SteadyResult):
 def steady_state_reuse(prob, n0, tol_rel=1.0e-4, y_floor=1.0e-30, y_sig=1.0e-10,
                        t_end=1.0e12, dt0=1.0e-8, max_steps=5000, max_consec_rejects=30,
                        use_mix_rule=True, newton_tol=1.0e-3, max_newton=4, max_age=20,
-                       reuse_ratio=1.3):
+                       reuse_ratio=1.3, y_neg=1.0e-6):
     """The adaptive steady-state driver with the step matrix kept across
     steps, after the corrector of the DLSODES family Section 2.1 names
     (modified Newton on the backward-Euler equation, one factorisation
@@ -326,7 +329,7 @@ def steady_state_reuse(prob, n0, tol_rel=1.0e-4, y_floor=1.0e-30, y_sig=1.0e-10,
                 continue
         n_new = n + delta
         sig = n > y_sig * ngas
-        if not ok or not np.all(np.isfinite(n_new)) or np.any(sig & (n_new < 0.0)):
+        if not ok or not np.all(np.isfinite(n_new)) or np.any(sig & (n_new < -y_neg * ngas)):
             rejects += 1
             consec += 1
             dt *= 0.5

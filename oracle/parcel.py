@@ -87,7 +87,8 @@ def layer_matrix(prob, k, p, dt, diff):
 def visit(prob, k, p, prof, diff, t_res, dt0, y_sig=1.0e-10, max_consec_rejects=30):
     """The parcel's composition after t_res at layer k, integrated by
     linearly implicit backward-Euler steps with the step control of the
-    column's steady-state driver (integrate.steady_state) inside the window:
+    column's steady-state driver (integrate.steady_state) with no overshoot
+    tolerance (y_neg = 0) inside the window:
     a step that is not finite or turns a species above mixing ratio y_sig
     negative is taken again at half the size; an accepted step clips
     negatives to zero and sets the next size by the control change c

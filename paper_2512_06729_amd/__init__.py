@@ -83,7 +83,7 @@ class SSOpts(ctypes.Structure):
     _fields_ = [("tol_rel", c_double), ("y_floor", c_double), ("y_sig", c_double),
                 ("t_end", c_double), ("dt0", c_double), ("max_steps", c_int32),
                 ("max_consec_rejects", c_int32), ("use_mix_rule", c_int32),
-                ("method", c_int32)]
+                ("method", c_int32), ("y_neg", c_double)]
 
 
 class ReuseStats(ctypes.Structure):
@@ -501,11 +501,11 @@ def xod_step_bdf2(col, dt):
 
 def xod_integrate_to_steady_state(col, tol_rel=0.0, y_floor=0.0, y_sig=0.0, t_end=0.0,
                                   dt0=0.0, max_steps=0, max_consec_rejects=0,
-                                  use_mix_rule=1, check=True, method=0):
+                                  use_mix_rule=1, check=True, method=0, y_neg=0.0):
     """method 0: backward-Euler steps, 1: ROS2 steps, 2: backward-Euler steps
     on step matrices kept across steps (1 and 2: FP64 columns)."""
     o = SSOpts(tol_rel, y_floor, y_sig, t_end, dt0, max_steps, max_consec_rejects,
-               use_mix_rule, method)
+               use_mix_rule, method, y_neg)
     r = SSResult()
     st = _f["xod_integrate_to_steady_state"](col.handle, ctypes.byref(o), ctypes.byref(r))
     if check and st not in (XOD_OK,):
@@ -604,7 +604,7 @@ class Server:
         return b.value
 
     def submit(self, network, col, tol_rel=0.0, y_floor=0.0, y_sig=0.0, t_end=0.0, dt0=0.0,
-               max_steps=0, max_consec_rejects=0, use_mix_rule=1):
+               max_steps=0, max_consec_rejects=0, use_mix_rule=1, y_neg=0.0):
         if any(getattr(col, k, None) is not None
                for k in ("escape_diff_limited", "v_top", "v_dep", "phi_surf")):
             raise ValueError("served requests are closed columns (no boundary exchange)")
@@ -612,7 +612,7 @@ class Server:
         prof, keep = _profile_struct(col, N)
         n0 = np.ascontiguousarray(col.n0, np.float64)
         o = SSOpts(tol_rel, y_floor, y_sig, t_end, dt0, max_steps, max_consec_rejects,
-                   use_mix_rule, 0)
+                   use_mix_rule, 0, y_neg)
         rid = ctypes.c_uint64()
         _check(_f["xod_serve_submit"](self.handle, network.handle, ctypes.byref(prof),
                                       _ptr(n0, c_double), ctypes.byref(o), ctypes.byref(rid)))

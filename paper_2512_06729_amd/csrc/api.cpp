@@ -950,7 +950,7 @@ size_t column_footprint(const xod_network *net, int N, xod_precision prec) {
   return b;
 }
 
-xod_status enqueue_update(xod_column *c, bool clip, double y_floor, double y_sig) {
+xod_status enqueue_update(xod_column *c, bool clip, double y_floor, double y_sig, double y_neg) {
   UpdArgs &u = *c->upd_host;
   u = UpdArgs{};
   u.n = c->n;
@@ -963,6 +963,7 @@ xod_status enqueue_update(xod_column *c, bool clip, double y_floor, double y_sig
   u.clip = clip ? 1 : 0;
   u.y_floor = y_floor;
   u.y_sig = y_sig;
+  u.y_neg = y_neg;
   *c->red_host = RedArgs{c->partial, c->flag, c->stats_dev};
   XOD_HIP(hipMemcpyAsync(c->upd_dev, c->upd_host, sizeof(UpdArgs), hipMemcpyHostToDevice,
                          c->stream));
@@ -974,8 +975,9 @@ xod_status enqueue_update(xod_column *c, bool clip, double y_floor, double y_sig
   return XOD_OK;
 }
 
-xod_status run_update(xod_column *c, bool clip, double y_floor, double y_sig, double *out) {
-  XOD_TRY(enqueue_update(c, clip, y_floor, y_sig));
+xod_status run_update(xod_column *c, bool clip, double y_floor, double y_sig, double *out,
+                      double y_neg) {
+  XOD_TRY(enqueue_update(c, clip, y_floor, y_sig, y_neg));
   XOD_HIP(hipStreamSynchronize(c->stream));
   std::memcpy(out, c->stats_host, kStatLen * sizeof(double));
   return XOD_OK;
@@ -1378,7 +1380,7 @@ extern "C" xod_status xod_integrate_to_steady_state(xod_column *col, const xod_s
                                                     xod_ss_result *res) {
   XOD_CHECK(col && res, "xod_integrate_to_steady_state: null argument");
   XOD_CHECK(!col->in_batch, "xod_integrate_to_steady_state: column belongs to a batch");
-  double tol = 1e-4, yfl = 1e-30, ysig = 1e-10, tend = 1e12, dt0 = 1e-8;
+  double tol = 1e-4, yfl = 1e-30, ysig = 1e-10, tend = 1e12, dt0 = 1e-8, yneg = 1e-6;
   int maxs = 5000, maxrej = 30, mixrule = 1, method = 0;
   if (o) {
     XOD_CHECK(o->method >= 0 && o->method <= 2,
@@ -1390,6 +1392,7 @@ extern "C" xod_status xod_integrate_to_steady_state(xod_column *col, const xod_s
     if (o->tol_rel > 0) tol = o->tol_rel;
     if (o->y_floor > 0) yfl = o->y_floor;
     if (o->y_sig > 0) ysig = o->y_sig;
+    if (o->y_neg > 0) yneg = o->y_neg;
     if (o->t_end > 0) tend = o->t_end;
     if (o->dt0 > 0) dt0 = o->dt0;
     if (o->max_steps > 0) maxs = o->max_steps;
@@ -1437,7 +1440,7 @@ extern "C" xod_status xod_integrate_to_steady_state(xod_column *col, const xod_s
       ++nfact;
     }
     double s[kStatLen];
-    XOD_TRY(run_update(col, true, yfl, ysig, s));
+    XOD_TRY(run_update(col, true, yfl, ysig, s, yneg));
     const bool singular = s[kNStat] >= 0;
     if (singular || s[5] > 0 || s[4] > 0) {
       ++rejects;

@@ -62,7 +62,8 @@ xod_status BatchRunner::init(int capacity) {
 // One FP64 BE step of every column (delta solved, n_new written to ntmp,
 // statistics into stats[i*kStatLen..]).  States are not committed here.
 xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double *dts,
-                             bool clip, double y_floor, double y_sig, hipStream_t s,
+                             bool clip, double y_floor, double y_sig, double y_neg,
+                             hipStream_t s,
                              std::vector<double> &stats) {
   const int n = (int)cols.size();
   if (n > cap) {
@@ -115,6 +116,7 @@ xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double
       u.clip = clip ? 1 : 0;
       u.y_floor = y_floor;
       u.y_sig = y_sig;
+      u.y_neg = y_neg;
       h_upd[sl] = u;
       h_red[sl] = RedArgs{u.partial, c->flag, d_stats + (size_t)sl * kStatLen};
       g.maxN = std::max(g.maxN, c->N);
@@ -320,7 +322,7 @@ extern "C" xod_status xod_batch_step(xod_batch *b, const double *dts, xod_step_s
   for (size_t i = 0; i < b->cols.size(); ++i)
     BCHECK(std::isfinite(dts[i]) && dts[i] > 0, "xod_batch_step: dt must be > 0");
   std::vector<double> stats;
-  XOD_TRY_B(b->runner.step(b->cols, dts, false, 1e-30, 1e-10, b->stream, stats));
+  XOD_TRY_B(b->runner.step(b->cols, dts, false, 1e-30, 1e-10, 0.0, b->stream, stats));
   xod_status ret = XOD_OK;
   for (size_t i = 0; i < b->cols.size(); ++i) {
     xod_column *c = b->cols[i];

@@ -34,7 +34,8 @@ struct BatchRunner {
   ~BatchRunner();
   xod_status init(int capacity);
   xod_status step(const std::vector<xod_column *> &cols, const double *dts, bool clip,
-                  double y_floor, double y_sig, hipStream_t s, std::vector<double> &stats);
+                  double y_floor, double y_sig, double y_neg, hipStream_t s,
+                  std::vector<double> &stats);
 };
 
 }  // namespace xod

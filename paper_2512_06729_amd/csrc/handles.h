@@ -180,10 +180,12 @@ namespace xod {
 xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, double *resid,
                          const double *hist = nullptr, double hist_coef = 0.0);
 // n_new = n + delta into col->ntmp plus statistics (host copy, kStatLen).
-xod_status run_update(xod_column *c, bool clip, double y_floor, double y_sig, double *out);
+xod_status run_update(xod_column *c, bool clip, double y_floor, double y_sig, double *out,
+                      double y_neg = 0.0);
 // The same, enqueued only: the statistics land in c->stats_host once the
 // column's stream has reached them.
-xod_status enqueue_update(xod_column *c, bool clip, double y_floor, double y_sig);
+xod_status enqueue_update(xod_column *c, bool clip, double y_floor, double y_sig,
+                          double y_neg = 0.0);
 // Device bytes of the cyclic-reduction workspace of a column.
 size_t cr_footprint(const xod_network *net, int N, xod_precision prec);
 // Device bytes a column of this network with N layers allocates.

@@ -19,7 +19,7 @@ __global__ void __launch_bounds__(256) k_update_state(const UpdArgs *args) {
     if (!isfinite(v)) nonfin = 1.0;
     if (u.clip) {
       if (v < 0.0) {
-        if (n0 > u.y_sig * ng) negsig = 1.0;
+        if (n0 > u.y_sig * ng && v < -u.y_neg * ng) negsig = 1.0;
         clipped += -v;
         v = 0.0;
       }

@@ -48,7 +48,7 @@ struct Req {
   double mbar = 2.3, g = 2000.0, sigma = 1e-22;
   int N = 0;
   // options
-  double tol = 1e-4, yfl = 1e-30, ysig = 1e-10, tend = 1e12, dt0 = 1e-8;
+  double tol = 1e-4, yfl = 1e-30, ysig = 1e-10, tend = 1e12, dt0 = 1e-8, yneg = 1e-6;
   int maxs = 5000, maxrej = 30, mixrule = 1;
   // controller state
   double t = 0.0, dt = 0.0, clipped = 0.0, mix = 0.0;
@@ -171,6 +171,7 @@ extern "C" xod_status xod_serve_submit(xod_server *s, const xod_network *net,
     if (o->tol_rel > 0) r.tol = o->tol_rel;
     if (o->y_floor > 0) r.yfl = o->y_floor;
     if (o->y_sig > 0) r.ysig = o->y_sig;
+    if (o->y_neg > 0) r.yneg = o->y_neg;
     if (o->t_end > 0) r.tend = o->t_end;
     if (o->dt0 > 0) r.dt0 = o->dt0;
     if (o->max_steps > 0) r.maxs = o->max_steps;
@@ -258,9 +259,11 @@ extern "C" xod_status xod_serve_step(xod_server *s, int32_t *n_active, int32_t *
       dts[i] = r.dt;
     }
     if (s->prec == XOD_FP64 && s->solver == XOD_SOLVER_THOMAS) {
-      // driver semantics: clipping, control statistics; y floors per request
+      // driver semantics: clipping, control statistics; one launch serves
+      // every active request, so the y thresholds are the first request's
       const Req &r0 = s->reqs.at(s->active[0]);
-      XOD_TRY_B(s->runner.step(cols, dts.data(), true, r0.yfl, r0.ysig, s->stream, stats));
+      XOD_TRY_B(s->runner.step(cols, dts.data(), true, r0.yfl, r0.ysig, r0.yneg, s->stream,
+                               stats));
     } else if (s->solver == XOD_SOLVER_CR) {
       // every request on its own stream, driven by its own host thread (the
       // mixed-precision refinement waits on its stream between iterations),
@@ -274,7 +277,7 @@ extern "C" xod_status xod_serve_step(xod_server *s, int32_t *n_active, int32_t *
           int it, fb;
           double res;
           xod_status st = enqueue_solve(r->col, r->dt, &it, &fb, &res);
-          if (st == XOD_OK) st = run_update(r->col, true, r->yfl, r->ysig, out);
+          if (st == XOD_OK) st = run_update(r->col, true, r->yfl, r->ysig, out, r->yneg);
           return std::make_pair(st, st == XOD_OK ? std::string() : last_error());
         }));
       }
@@ -298,7 +301,7 @@ extern "C" xod_status xod_serve_step(xod_server *s, int32_t *n_active, int32_t *
         int it, fb;
         double res;
         XOD_TRY_B(enqueue_solve(r.col, r.dt, &it, &fb, &res));
-        XOD_TRY_B(run_update(r.col, true, r.yfl, r.ysig, &stats[i * kStatLen]));
+        XOD_TRY_B(run_update(r.col, true, r.yfl, r.ysig, &stats[i * kStatLen], r.yneg));
       }
     }
   }

@@ -299,6 +299,7 @@ struct UpdArgs {
   int N, S;
   int clip;            // 1: driver semantics (clip negatives)
   double y_floor, y_sig;
+  double y_neg;        // significant negative: below -y_neg n_gas (0: any)
 };
 struct RedArgs {
   const double *partial;

@@ -5,7 +5,7 @@ make_config2_steady_state.py from the oracle alone).
 * Fixed point: from the oracle's tol-1e-4 steady state, 40 backward-Euler
   steps of ten times the mixing time (negatives clipped after each, as the
   golden script does) bring both sides to the fixed point F(n) = 0 (the
-  oracle's last relative change: 1.5e-13).  The two fixed points are the
+  oracle's last relative change: 5.6e-13).  The two fixed points are the
   roots of the same F, evaluated in a different order, so they differ by
   the conditioning of F's root times the rounding of the rate
   coefficients: perturbing the oracle's k_f and k_r by 4e-16 relative
@@ -13,15 +13,18 @@ make_config2_steady_state.py from the oracle alone).
   the bound is 1e-10 there.
 * Driver: the GPU's adaptive driver from the initial state converges with
   either factorisation at tol 1e-4.  The decisions of this controller are
-  sensitive to rounding on this column (the oracle takes 1743 steps and 858
+  sensitive to rounding on this column (the oracle takes 1437 steps and 473
   rejections; 1e-13 changes elsewhere change them), and with them the
   densities clipped at zero.  The steady state is that of the column's
   element inventory, which chemistry and closed transport conserve, but
-  which clipping raises and the linearised steps at dt ~ 1e10 s (nearly
-  singular step matrices) keep only to cond(M) eps: the oracle's own run
-  ends with 6e-4 less of one element than it started with, and a state
-  1e-2 off the fixed point at random (another inventory) relaxes to a
-  steady state 2.7e-2 away.  So the driver's end state is required to have
+  which clipping raises and the linearised steps keep only to the rounding
+  of F times dt in the conserved directions (the step matrix is nearly
+  singular there at large dt; single reaction rates reach 5.6e24
+  cm^-3 s^-1 in the deep layers of the initial state): the oracle's own
+  run ends with one element's inventory 4.8e-3 above its start (6e-4
+  below it under the stricter rejection rule of an earlier reading), and a
+  state 1e-2 off the fixed point at random (another inventory) relaxes to
+  a steady state 2.7e-2 away.  So the driver's end state is required to have
   converged and to lie within 0.1 of the oracle's fixed point above mixing
   ratio 1e-10 (measured 1.1e-2 and 1.6e-2); the fixed-point test above is
   the parity check of the steady state itself.
