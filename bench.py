@@ -215,8 +215,13 @@ def bench_config1(xod, torch, stream):
     net, col = synth.make_config(1)
     gnet = xod.Network(net)
     sched = [1e-8 * 1.2 ** j for j in range(200)]
-    out = {"workload": "S=12, R=30, N=20: 200 fixed-schedule backward-Euler steps"}
-    for name, solver in (("cr", XOD_SOLVER_CR), ("thomas", XOD_SOLVER_THOMAS)):
+    out = {"workload": "S=12, R=30, N=20: 200 fixed-schedule backward-Euler steps",
+           "thomas": "block Thomas in one persistent launch each for the factorisation and "
+                     "the solve (blocks up to 64); thomas_panels: the per-layer panel "
+                     "kernels of the large blocks"}
+    for name, solver, fused in (("cr", XOD_SOLVER_CR, 64), ("thomas", XOD_SOLVER_THOMAS, 64),
+                                ("thomas_panels", XOD_SOLVER_THOMAS, 0)):
+        xod.set_option("fused_max_ld", fused)
         g = xod.Column(gnet, col, stream=stream, solver=solver)
         xod.xod_step(g, 1e-8)
         g.set_state(col.n0)
@@ -228,6 +233,7 @@ def bench_config1(xod, torch, stream):
         el = time.perf_counter() - t0
         out[name] = {"us_per_step": 1e6 * el / len(sched), "steps_per_s": len(sched) / el}
         g.close()
+    xod.set_option("fused_max_ld", 64)
     gnet.close()
     return out
 
@@ -262,8 +268,8 @@ def bench_reuse(xod, torch, stream, gnet3, col3):
     """Factorisations kept across steps (the modified-Newton corrector of the
     DLSODES family): the 90 x 120 column to steady state with method 2
     against method 0 (cyclic reduction), and 20 fixed backward-Euler steps of
-    1e-6 s on the 594 x 150 column from its initial state with and without
-    reuse.  Reports wall time, steps and factorisations per step."""
+    1e-8 s and of 1e-6 s on the 594 x 150 column from its initial state with
+    and without reuse.  Reports wall time, steps and factorisations per step."""
     import synth
     from paper_2512_06729_amd import XOD_SOLVER_CR
     net, col = synth.make_config(2)
@@ -285,21 +291,23 @@ def bench_reuse(xod, torch, stream, gnet3, col3):
         g.close()
     gnet.close()
     gcol = xod.Column(gnet3, col3, stream=stream, solver=XOD_SOLVER_CR)
-    for reuse in (0, 1):
-        gcol.set_state(col3.n0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        try:
-            st = xod.xod_integrate_fixed_dt(gcol, 1e-6, 20, reuse)
-        except xod.XodError as e:
-            out[f"fixed_dt_reuse{reuse}"] = {"error": str(e)}
-            continue
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        out[f"fixed_dt_reuse{reuse}"] = {
-            "steps_per_s": st["steps"] / el, "steps": st["steps"],
-            "factorizations": st["factorizations"], "newton_iters": st["newton_iters"],
-            "factorizations_per_step": st["factorizations"] / max(1, st["steps"])}
+    for dt in (1e-8, 1e-6):
+        for reuse in (0, 1):
+            gcol.set_state(col3.n0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            key = f"fixed_dt_{dt:g}_reuse{reuse}"
+            try:
+                st = xod.xod_integrate_fixed_dt(gcol, dt, 20, reuse)
+            except xod.XodError as e:
+                out[key] = {"error": str(e)}
+                continue
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            out[key] = {
+                "steps_per_s": st["steps"] / el, "steps": st["steps"],
+                "factorizations": st["factorizations"], "newton_iters": st["newton_iters"],
+                "factorizations_per_step": st["factorizations"] / max(1, st["steps"])}
     gcol.close()
     return out
 
@@ -839,7 +847,10 @@ def main():
         progress(f"mixed steps: {line['mixed']['value']:.2f} steps/s")
     if not args.skip_small:
         line["config1_latency"] = bench_config1(xod, torch, stream)
-        progress("config 1: %.1f us/step (cr)" % line["config1_latency"]["cr"]["us_per_step"])
+        progress("config 1: %.1f us/step (cr), %.1f (thomas), %.1f (thomas, panel kernels)" % (
+            line["config1_latency"]["cr"]["us_per_step"],
+            line["config1_latency"]["thomas"]["us_per_step"],
+            line["config1_latency"]["thomas_panels"]["us_per_step"]))
         line["config2_steady_state"] = bench_config2(xod, torch, stream)
         progress("config 2 steady state: %.2f s (cr)" %
                  line["config2_steady_state"]["cr"]["wall_s"])
@@ -847,12 +858,13 @@ def main():
         line["factor_reuse"] = bench_reuse(xod, torch, stream, gnet, col)
         fr = line["factor_reuse"]
         progress("factor reuse: steady state %.2f s with kept factorisations (%.2f per step), "
-                 "%.2f s without; fixed dt %s vs %s steps/s" % (
+                 "%.2f s without; fixed dt 1e-8: %s vs %s steps/s (%s factorisations per step)" % (
                      fr["steady_state_method2"]["wall_s"],
                      fr["steady_state_method2"]["factorizations_per_step"],
                      fr["steady_state_method0"]["wall_s"],
-                     fr["fixed_dt_reuse1"].get("steps_per_s"),
-                     fr["fixed_dt_reuse0"].get("steps_per_s")))
+                     fr["fixed_dt_1e-08_reuse1"].get("steps_per_s"),
+                     fr["fixed_dt_1e-08_reuse0"].get("steps_per_s"),
+                     fr["fixed_dt_1e-08_reuse1"].get("factorizations_per_step")))
     if not args.skip_serve:
         s64, n64 = bench_serve(xod, torch, args, xod.XOD_FP64, gnet, net)
         if args.serve_fp64_only:

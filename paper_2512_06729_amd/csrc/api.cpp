@@ -137,6 +137,12 @@ extern "C" xod_status xod_set_option(const char *name, int64_t value) {
     options().refine_tol = std::pow(10.0, -(double)value);
     return XOD_OK;
   }
+  if (std::strcmp(name, "fused_max_ld") == 0) {
+    XOD_CHECK(value == 0 || value == 32 || value == 64 || value == 96 || value == 128,
+              "xod_set_option: fused_max_ld must be 0, 32, 64, 96 or 128");
+    options().fused_max_ld = (int)value;
+    return XOD_OK;
+  }
   if (std::strcmp(name, "refine64") == 0) {
     XOD_CHECK(value >= 0 && value <= 10, "xod_set_option: refine64 must be in 0..10");
     options().refine64 = (int)value;

@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 
 namespace xod {
 
@@ -739,9 +740,246 @@ void invert_blocks(const MA &ma, int nmat, int ld, int k, hipStream_t s, bool pr
   }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent block Thomas for small blocks (ld up to option fused_max_ld,
+// at most kFusedMaxLd): one work-group runs a column's whole layer chain in
+// one launch.  It pays where the per-layer launches dominate (ld 32, 64);
+// at ld 96 one work-group per column is slower than the panel kernels.
+//
+// Factorisation.  Thread t owns CW consecutive columns (a part) of row
+// t / TPR of the current block in registers.  Per layer k the Schur
+// complement
+//   D'_k = B_k - diag(a_k) E_{k-1} diag(c_{k-1})
+// is formed while B_k is read (E_{k-1} is the registers' previous content),
+// then inverted by Gauss-Jordan with implicit partial pivoting, the pivot
+// chosen by the panel kernels' key (largest magnitude among unused rows to
+// 42 mantissa bits, lowest row among equals).  Columns are eliminated in
+// rounds, slot r of every part in round r, and the register tiles rotate by
+// one slot per round, so the column being eliminated is always in slot 0
+// (static register indices; any column order gives the same inverse).  Per
+// column: the candidates' keys reduced per wave and a barrier, the pivot row
+// and the column published in LDS and a barrier, every row updated in
+// registers.  The result W goes through LDS to natural order,
+// E[column pivoted by row r][row pivoting column j] = W[r][j], is written
+// back over B_k, and stays in registers for the next layer.  Pivots are
+// stored as the identity, so every solve path reads E_k as it would any
+// factorisation.
+//
+// Solve.  One work-group per column: the forward chain
+//   y_k = E_k (rhs_k - a_k y_{k-1})          (y_k into gs)
+// then the backward chain
+//   x_{N-1} = y_{N-1},  x_k = y_k - E_k (c_k x_{k+1}),
+// each step a matrix-vector product of the thread's row segment and a
+// reduction over the TPR threads of the row.
+constexpr int kFusedMaxLd = 128;
+
+template <int LD>
+struct FusedShape {
+  static constexpr int TPR = LD <= 32 ? 8 : (LD <= 64 ? 4 : 2);   // threads per row
+  static constexpr int CW = LD / TPR;                             // columns per thread
+  static constexpr int THREADS = LD * TPR;                        // 256, 256, 192, 256
+};
+static_assert(FusedShape<96>::THREADS <= 256 && FusedShape<128>::THREADS <= 256, "shape");
+
+// Sum over the TPR consecutive lanes that share a row.
+template <int TPR>
+__device__ __forceinline__ double row_sum(double z) {
+#pragma unroll
+  for (int o = 1; o < TPR; o <<= 1) z += __shfl_xor(z, o, 64);
+  return z;
+}
+
+template <class Acc, int LD>
+__global__ void __launch_bounds__(256) k_btd_fused_factor(Acc acc) {
+  using F = FusedShape<LD>;
+  constexpr int CW = F::CW, TPR = F::TPR;
+  const ColArgs &c = acc(blockIdx.x);
+  const int N = c.N, S = c.S;
+  const int t = threadIdx.x, lane = t & 63;
+  const bool active = t < F::THREADS;
+  const int i = active ? t / TPR : 0, h = active ? t % TPR : 0, j0 = h * CW;
+  __shared__ double Es[LD][LD];
+  __shared__ double rowp[LD], colk[LD];   // rowp in (part, slot) order
+  __shared__ double wkey[4];
+  __shared__ int pvrow[LD];
+  if (t < 4) c.flag[t] = -1;
+  double A[CW];
+#pragma unroll
+  for (int q = 0; q < CW; ++q) A[q] = 0.0;
+  bool flagged = false;
+  for (int k = 0; k < N; ++k) {
+    double *Bk = c.B + (size_t)k * LD * LD;
+    if (active) {
+      const double ai = k > 0 ? c.a[(size_t)k * LD + i] : 0.0;
+      const double *cp = c.c + (size_t)(k > 0 ? k - 1 : 0) * LD;
+#pragma unroll
+      for (int q = 0; q < CW; ++q) {
+        const double b = Bk[(size_t)i * LD + j0 + q];
+        A[q] = k > 0 ? b - ai * A[q] * cp[j0 + q] : b;
+      }
+    }
+    if (t < LD) pvrow[t] = t;   // padding columns keep their own row
+    bool used = i >= S;         // padding rows are never pivots
+    int colof = i;              // the column this row pivots
+    int badcol = -1;
+    // Columns in rounds: round r takes column h * CW + r of every part h.
+    // The tile is rotated left by one slot after each round, so the round's
+    // column sits in slot 0 of its part and every register index is static.
+    for (int r = 0; r < CW; ++r) {
+      for (int hk = 0; hk < TPR; ++hk) {
+        const int kcol = hk * CW + r;
+        if (kcol >= S) continue;                 // uniform
+        const bool own = active && h == hk;      // holds column kcol (slot 0)
+        // pivot: the largest key among the unused rows' column entries
+        const double key = own ? pivot_key(A[0], i, used ? 0u : ~0u) : 0.0;
+        const double m = wave_max(key);
+        if (lane == 0) wkey[t >> 6] = m;
+        __syncthreads();
+        const double K = fmax(fmax(wkey[0], wkey[1]), fmax(wkey[2], wkey[3]));
+        int p = 1023 - (__double2loint(K) & 1023);
+        if (K == 0.0 || p >= S) p = kcol;        // no usable pivot: flagged, stays in bounds
+        if (active && i == p) {
+#pragma unroll
+          for (int q = 0; q < CW; ++q) rowp[j0 + q] = A[q];
+        }
+        if (own) colk[i] = A[0];
+        if (t == 0) pvrow[kcol] = p;
+        __syncthreads();
+        const double pv = rowp[hk * CW];
+        if (!(fabs(pv) > 0.0 && isfinite(pv)) && badcol < 0) badcol = kcol;
+        const double rp = 1.0 / pv;
+        if (active) {
+          if (i == p) {
+            A[0] = own ? rp : A[0] * rp;
+#pragma unroll
+            for (int q = 1; q < CW; ++q) A[q] *= rp;
+            used = true;
+            colof = kcol;
+          } else {
+            const double g = colk[i] * rp;
+            A[0] = own ? -g : fma(-g, rowp[j0], A[0]);
+#pragma unroll
+            for (int q = 1; q < CW; ++q) A[q] = fma(-g, rowp[j0 + q], A[q]);
+          }
+        }
+        // no barrier here: the next column rewrites wkey only after every
+        // thread passed this column's second barrier (so has read wkey), and
+        // rowp / colk only after its first one (so has finished this update)
+      }
+      const double a0 = A[0];
+#pragma unroll
+      for (int q = 0; q + 1 < CW; ++q) A[q] = A[q + 1];
+      A[CW - 1] = a0;
+    }
+    // the tile is back in natural column order: E[colof[r]][pvrow[j]] = W[r][j]
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < CW; ++q) Es[colof][pvrow[j0 + q]] = A[q];
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < CW; ++q) {
+        A[q] = Es[i][j0 + q];
+        Bk[(size_t)i * LD + j0 + q] = A[q];
+      }
+    }
+    if (t < LD) {
+      c.piv[(size_t)k * LD + t] = t;
+      c.rstep[(size_t)k * LD + t] = t;
+    }
+    if (t == 0 && badcol >= 0 && !flagged) {
+      flagged = true;
+      if (atomicCAS(c.flag, -1, k) == -1) c.flag[1] = badcol;
+    }
+    __syncthreads();
+  }
+}
+
+template <class Acc, int LD>
+__global__ void __launch_bounds__(256) k_btd_fused_solve(Acc acc) {
+  using F = FusedShape<LD>;
+  constexpr int CW = F::CW;
+  const ColArgs &c = acc(blockIdx.x);
+  const int N = c.N, S = c.S;
+  const int t = threadIdx.x;
+  const bool active = t < F::THREADS;
+  const int i = active ? t / F::TPR : 0, j0 = active ? (t % F::TPR) * CW : 0;
+  const bool owner = active && j0 == 0;
+  __shared__ double v[LD], y[LD];
+  if (t < LD) y[t] = 0.0;
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {
+    if (t < LD)
+      v[t] = t < S ? c.x[(size_t)k * S + t] - (k > 0 ? c.a[(size_t)k * LD + t] * y[t] : 0.0) : 0.0;
+    __syncthreads();
+    const double *E = c.B + (size_t)k * LD * LD + (size_t)i * LD + j0;
+    double z = 0.0;
+#pragma unroll
+    for (int q = 0; q < CW; ++q) z = fma(E[q], v[j0 + q], z);
+    z = row_sum<F::TPR>(z);
+    __syncthreads();
+    if (owner) {
+      y[i] = z;
+      c.gs[(size_t)k * LD + i] = z;
+    }
+    __syncthreads();
+  }
+  // y holds y_{N-1} = x_{N-1}
+  if (t < S) c.x[(size_t)(N - 1) * S + t] = y[t];
+  for (int k = N - 2; k >= 0; --k) {
+    if (t < LD) v[t] = t < S ? c.c[(size_t)k * LD + t] * y[t] : 0.0;
+    __syncthreads();
+    const double *E = c.B + (size_t)k * LD * LD + (size_t)i * LD + j0;
+    double z = 0.0;
+#pragma unroll
+    for (int q = 0; q < CW; ++q) z = fma(E[q], v[j0 + q], z);
+    z = row_sum<F::TPR>(z);
+    __syncthreads();
+    if (owner) {
+      const double xi = c.gs[(size_t)k * LD + i] - z;
+      y[i] = xi;
+      if (i < S) c.x[(size_t)k * S + i] = xi;
+    }
+    __syncthreads();
+  }
+}
+
+template <class Acc>
+hipError_t launch_fused_factor(const Acc &acc, int ncols, int ld, hipStream_t s) {
+  switch (ld) {
+    case 32: hipLaunchKernelGGL((k_btd_fused_factor<Acc, 32>), dim3(ncols), dim3(256), 0, s, acc); break;
+    case 64: hipLaunchKernelGGL((k_btd_fused_factor<Acc, 64>), dim3(ncols), dim3(256), 0, s, acc); break;
+    case 96: hipLaunchKernelGGL((k_btd_fused_factor<Acc, 96>), dim3(ncols), dim3(256), 0, s, acc); break;
+    case 128: hipLaunchKernelGGL((k_btd_fused_factor<Acc, 128>), dim3(ncols), dim3(256), 0, s, acc); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class Acc>
+hipError_t launch_fused_solve(const Acc &acc, int ncols, int ld, hipStream_t s) {
+  switch (ld) {
+    case 32: hipLaunchKernelGGL((k_btd_fused_solve<Acc, 32>), dim3(ncols), dim3(256), 0, s, acc); break;
+    case 64: hipLaunchKernelGGL((k_btd_fused_solve<Acc, 64>), dim3(ncols), dim3(256), 0, s, acc); break;
+    case 96: hipLaunchKernelGGL((k_btd_fused_solve<Acc, 96>), dim3(ncols), dim3(256), 0, s, acc); break;
+    case 128: hipLaunchKernelGGL((k_btd_fused_solve<Acc, 128>), dim3(ncols), dim3(256), 0, s, acc); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+inline bool use_fused(int ld) { return ld <= options().fused_max_ld && ld <= kFusedMaxLd; }
+
 template <class Acc, class T>
 hipError_t launch_factor(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s) {
   if (maxN <= 0) return hipSuccess;
+  if (std::is_same<T, double>::value && use_fused(ld)) {
+    if (options().profile) prof_begin(kProfPanel, s);
+    const hipError_t e = launch_fused_factor(acc, ncols, ld, s);
+    if (options().profile) prof_end(kProfPanel, s);
+    return e;
+  }
   hipLaunchKernelGGL(k_rstep_init<Acc>, dim3(64, ncols), dim3(256), 0, s, acc, maxN);
   const ThomasMats<Acc, T> ma{acc};
   for (int k = 0; k < maxN; ++k) {
@@ -840,6 +1078,12 @@ __global__ void __launch_bounds__(256) k_solve_step(Acc acc, int k) {
 template <class Acc, class T>
 hipError_t launch_solve(const Acc &acc, int ncols, int maxN, int ld, hipStream_t s) {
   if (maxN <= 0) return hipSuccess;
+  if (std::is_same<T, double>::value && use_fused(ld)) {
+    if (options().profile) prof_begin(kProfSolve, s);
+    const hipError_t e = launch_fused_solve(acc, ncols, ld, s);
+    if (options().profile) prof_end(kProfSolve, s);
+    return e;
+  }
   dim3 grid((ld + 15) / 16, ncols);
   for (int k = 0; k < maxN; ++k) {
     const bool prof = prof_layer(k);

@@ -100,6 +100,8 @@ struct Options {
   int panel_defer = 0;    // 1: panel eliminations of other columns deferred by one column
   int gemm_lib = 0;       // cyclic-reduction block products: 1 = rocBLAS batched GEMM
   int graph = 1;          // replay captured launch sequences (cyclic reduction)
+  int fused_max_ld = 64;  // FP64 block Thomas with ld up to this (<= 128, 0: never): one
+                          // persistent launch each for a column's factorisation and solve
   int profile = 0;        // record HIP events around profiled launches
   int profile_every = 1;  // profile layers k with k % profile_every == 0
 };

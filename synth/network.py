@@ -110,6 +110,10 @@ NETWORK_PRESETS = {
     "t12": dict(S=12, elements=CHON, n_bi=20, n_ter=8, n_ph=0,
                 t_range=(700.0, 2800.0), kooij_frac=0.3, max_atoms=4,
                 p_sum=0.6, weights={"H": .4, "C": .3, "O": .2, "N": .1}),
+    # 48 species / 500 reactions (padded block size 64), same mix as c2.
+    "s48": dict(S=48, elements=CHON, n_bi=400, n_ter=50, n_ph=50,
+                t_range=(700.0, 2800.0), kooij_frac=0.3, max_atoms=5,
+                p_sum=0.5, weights=None),
     # 90 species / 1200 reactions, 80/10/10 two-body/three-body/photolysis.
     "c2": dict(S=90, elements=CHON, n_bi=960, n_ter=120, n_ph=120,
                t_range=(700.0, 2800.0), kooij_frac=0.3, max_atoms=6,
