@@ -551,6 +551,11 @@ xod_status xod_photolysis_spectral_noalloc(int32_t N, int32_t S, int32_t A, int3
  *            negativity test then sees the linearised step's own negative
  *            trace densities, which the unrefined solve happens to miss;
  *            the 90-species steady state then stalls with block Thomas;
+ *   "fused_max_ld": FP64 block Thomas of columns with padded blocks up to
+ *            this size (0, 32, 64 (default), 96 or 128; 0 = never) runs in
+ *            two persistent launches per column, one work-group each, for
+ *            the factorisation and for the solve, instead of per-layer panel
+ *            launches; the solve reads either kind of factors;
  *   "outer": Gauss-Jordan outer panel width, 32 (default), 64, 96 or 128:
  *            with a width above 32 the 32-column panels of an outer panel
  *            update only its own columns, then one rank-width update covers
@@ -598,6 +603,54 @@ xod_status xod_batch_destroy(xod_batch *b);
  * (host array [ncols]) may be NULL.  Synchronous. */
 xod_status xod_batch_step(xod_batch *b, const double *dt_per_col,
                           xod_step_stats *stats);
+
+/* ---- tile-shape autotuner for the block factorisations ---------------- */
+
+/* The factorisations' tile options ("fused_max_ld", "outer", "update32",
+ * "gemm_large", "gemm_k", "panel_sync" of xod_set_option) have settings
+ * that differ in speed with the block size, the precision, the
+ * factorisation, the number of blocks a launch covers and the GPU.  The
+ * tuner times candidate settings on the caller's own work and keeps the
+ * fastest per (GPU architecture, padded block size, precision,
+ * factorisation, single column or batch) in a process-wide table; from then
+ * on, factorisations of that kind of column (steps, drivers, batches,
+ * serving) run with it, and other kinds keep the xod_set_option values.
+ * Every candidate computes the same factorisation up to the order of
+ * rounding.  Candidates: block Thomas: the persistent small-block kernels
+ * (blocks up to 128, FP64), or the panel kernels with outer panels of 32,
+ * 64 or 128 columns and 16- or 32-column strip updates; cyclic reduction:
+ * block-product tiles 128 or 64, K step 32 or 16, one or two barriers per
+ * pivot column.  The first candidate is always the current xod_set_option
+ * setting (default_ms). */
+typedef struct {
+  char key[96];          /* "arch/ldN/precision/factorisation/column|batch" */
+  int32_t candidates;    /* settings timed */
+  int32_t fused_max_ld, outer, update32, gemm_large, gemm_k, panel_sync;
+                         /* the chosen setting */
+  int32_t pad_;
+  double best_ms;        /* its time (one step's solve, or one group's step) */
+  double default_ms;     /* the first candidate's time */
+} xod_tune_result;
+
+/* Tune for columns like col: each candidate runs one untimed and `trials`
+ * timed linearised steps of size dt (rates, F, Jacobian, factorisation,
+ * solve, mixed refinement; the state is not advanced), HIP events on the
+ * column's stream.  The column's held factorisation is dropped.  trials in
+ * 1..100; XOD_EINVAL for a column in a batch or dt <= 0. */
+xod_status xod_autotune(xod_column *col, double dt, int32_t trials,
+                        xod_tune_result *res);
+
+/* Tune every group (padded block size, precision) of a batch: each
+ * candidate runs one untimed and `trials` timed batch steps with the dts
+ * given (states not advanced), and a group's time is its own device time
+ * (events on its stream).  res has room for max_results groups; *nresults
+ * receives their number.  trials in 1..20. */
+xod_status xod_batch_autotune(xod_batch *b, const double *dt_per_col, int32_t trials,
+                              xod_tune_result *res, int32_t max_results,
+                              int32_t *nresults);
+
+/* Forget every tuned setting. */
+xod_status xod_autotune_clear(void);
 
 /* ---- serving: continuous batching of steady-state solves -------------- */
 

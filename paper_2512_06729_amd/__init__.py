@@ -102,6 +102,18 @@ class ParcelStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_char * 96), ("candidates", c_int32),
+                ("fused_max_ld", c_int32), ("outer", c_int32), ("update32", c_int32),
+                ("gemm_large", c_int32), ("gemm_k", c_int32), ("panel_sync", c_int32),
+                ("pad_", c_int32), ("best_ms", c_double), ("default_ms", c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+        d["key"] = self.key.decode()
+        return d
+
+
 class SSResult(ctypes.Structure):
     _fields_ = [("t", c_double), ("dt", c_double), ("clipped", c_double),
                 ("steps", ctypes.c_int64), ("rejects", ctypes.c_int64),
@@ -175,6 +187,10 @@ _f = {
                              ctypes.POINTER(c_void_p)),
     "xod_batch_destroy": _sig("xod_batch_destroy", c_void_p),
     "xod_batch_step": _sig("xod_batch_step", c_void_p, P_dbl, ctypes.POINTER(StepStats)),
+    "xod_autotune": _sig("xod_autotune", c_void_p, c_double, c_int32, ctypes.POINTER(TuneResult)),
+    "xod_batch_autotune": _sig("xod_batch_autotune", c_void_p, P_dbl, c_int32,
+                               ctypes.POINTER(TuneResult), c_int32, ctypes.POINTER(c_int32)),
+    "xod_autotune_clear": _sig("xod_autotune_clear"),
     "xod_profile_read": _sig("xod_profile_read", ctypes.c_char_p, P_dbl,
                              ctypes.POINTER(ctypes.c_int64)),
     "xod_profile_reset": _sig("xod_profile_reset"),
@@ -528,6 +544,17 @@ def xod_parcel_pass(col, dt0=1e-8):
     return out
 
 
+def xod_autotune(col, dt, trials=3):
+    """Tile settings for columns like col (xod_autotune)."""
+    r = TuneResult()
+    _check(_f["xod_autotune"](col.handle, float(dt), int(trials), ctypes.byref(r)))
+    return r.as_dict()
+
+
+def xod_autotune_clear():
+    _check(_f["xod_autotune_clear"]())
+
+
 def xod_integrate_fixed_dt(col, dt, nsteps, reuse=1):
     """nsteps backward-Euler steps of size dt, keeping the step matrix across
     steps (modified Newton) when reuse = 1; returns the step statistics."""
@@ -552,6 +579,15 @@ class Batch:
         stats = (StepStats * len(self.columns))()
         _check(_f["xod_batch_step"](self.handle, _ptr(dts, c_double), stats))
         return [s.as_dict() for s in stats]
+
+    def autotune(self, dts, trials=2):
+        """Tile settings per group of this batch (xod_batch_autotune)."""
+        dts = np.ascontiguousarray(dts, np.float64)
+        res = (TuneResult * 16)()
+        n = c_int32()
+        _check(_f["xod_batch_autotune"](self.handle, _ptr(dts, c_double), int(trials), res, 16,
+                                        ctypes.byref(n)))
+        return [res[i].as_dict() for i in range(n.value)]
 
     def close(self):
         if getattr(self, "handle", None):

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libxod.so")
 ARCH = os.environ.get("XOD_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "k_chem.hip", "k_btd.hip", "k_mixed.hip", "k_step.hip", "k_cr.hip", "k_photo.hip",
-           "cr.cpp", "batch.cpp", "prof.cpp", "serve.cpp", "parcel.cpp"]
+           "cr.cpp", "batch.cpp", "prof.cpp", "serve.cpp", "parcel.cpp", "tune.cpp"]
 
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

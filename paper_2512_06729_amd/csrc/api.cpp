@@ -19,9 +19,17 @@ namespace xod {
 static thread_local std::string g_err;
 void set_error(const std::string &m) { g_err = m; }
 std::string &last_error() { return g_err; }
-Options &options() {
+Options &global_options() {
   static Options o;
   return o;
+}
+Options *&options_override() {
+  thread_local Options *p = nullptr;
+  return p;
+}
+Options &options() {
+  Options *p = options_override();
+  return p ? *p : global_options();
 }
 
 }  // namespace xod
@@ -71,6 +79,7 @@ xod_status dupload(T **p, const T *host, size_t count) {
 
 #include "handles.h"
 #include "cr.h"
+#include "tune.h"
 
 namespace {
 
@@ -104,89 +113,89 @@ extern "C" xod_status xod_set_option(const char *name, int64_t value) {
   XOD_CHECK(name != nullptr, "xod_set_option: null name");
   if (std::strcmp(name, "gemm") == 0) {
     XOD_CHECK(value == 0 || value == 1, "xod_set_option: gemm must be 0 or 1");
-    options().gemm_mfma = (int)value;
+    global_options().gemm_mfma = (int)value;
     return XOD_OK;
   }
   if (std::strcmp(name, "gemm_large") == 0) {
     XOD_CHECK(value == 0 || value == 1, "xod_set_option: gemm_large must be 0 or 1");
-    options().gemm_large = (int)value;
+    global_options().gemm_large = (int)value;
     return XOD_OK;
   }
   if (std::strcmp(name, "gemm_lib") == 0) {
     XOD_CHECK(value == 0 || value == 1, "xod_set_option: gemm_lib must be 0 or 1");
-    options().gemm_lib = (int)value;
+    global_options().gemm_lib = (int)value;
     return XOD_OK;
   }
   if (std::strcmp(name, "panel_sync") == 0) {
     XOD_CHECK(value == 1 || value == 2, "xod_set_option: panel_sync must be 1 or 2");
-    options().panel_sync = (int)value;
+    global_options().panel_sync = (int)value;
     return XOD_OK;
   }
   if (std::strcmp(name, "panel_defer") == 0) {
     XOD_CHECK(value == 0 || value == 1, "xod_set_option: panel_defer must be 0 or 1");
-    options().panel_defer = (int)value;
+    global_options().panel_defer = (int)value;
     return XOD_OK;
   }
   if (std::strcmp(name, "gemm_k") == 0) {
     XOD_CHECK(value == 16 || value == 32, "xod_set_option: gemm_k must be 16 or 32");
-    options().gemm_k = (int)value;
+    global_options().gemm_k = (int)value;
     return XOD_OK;
   }
   if (std::strcmp(name, "refine_tol_exp") == 0) {
     XOD_CHECK(value >= 3 && value <= 15, "xod_set_option: refine_tol_exp must be in 3..15");
-    options().refine_tol = std::pow(10.0, -(double)value);
+    global_options().refine_tol = std::pow(10.0, -(double)value);
     return XOD_OK;
   }
   if (std::strcmp(name, "fused_max_ld") == 0) {
     XOD_CHECK(value == 0 || value == 32 || value == 64 || value == 96 || value == 128,
               "xod_set_option: fused_max_ld must be 0, 32, 64, 96 or 128");
-    options().fused_max_ld = (int)value;
+    global_options().fused_max_ld = (int)value;
     return XOD_OK;
   }
   if (std::strcmp(name, "refine64") == 0) {
     XOD_CHECK(value >= 0 && value <= 10, "xod_set_option: refine64 must be in 0..10");
-    options().refine64 = (int)value;
+    global_options().refine64 = (int)value;
     return XOD_OK;
   }
   if (std::strcmp(name, "refine_atol_exp") == 0) {
     XOD_CHECK(value >= 8 && value <= 17, "xod_set_option: refine_atol_exp must be in 8..17");
-    options().refine_atol = std::pow(10.0, -(double)value);
+    global_options().refine_atol = std::pow(10.0, -(double)value);
     return XOD_OK;
   }
   if (std::strcmp(name, "outer") == 0) {
     XOD_CHECK(value == 32 || value == 64 || value == 96 || value == 128,
               "xod_set_option: outer must be 32, 64, 96 or 128");
-    options().outer = (int)value;
+    global_options().outer = (int)value;
     return XOD_OK;
   }
   if (std::strcmp(name, "outer_nmat") == 0) {
     XOD_CHECK(value >= 1 && value <= 1000000, "xod_set_option: outer_nmat must be >= 1");
-    options().outer_nmat = (int)value;
+    global_options().outer_nmat = (int)value;
     return XOD_OK;
   }
   if (std::strcmp(name, "update32_min") == 0) {
     XOD_CHECK(value >= 0 && value <= 1000000, "xod_set_option: update32_min must be in 0..1000000");
-    options().update32_min = (int)value;
+    global_options().update32_min = (int)value;
     return XOD_OK;
   }
   if (std::strcmp(name, "update32") == 0) {
     XOD_CHECK(value == 0 || value == 1, "xod_set_option: update32 must be 0 or 1");
-    options().update32 = (int)value;
+    global_options().update32 = (int)value;
     return XOD_OK;
   }
   if (std::strcmp(name, "graph") == 0) {
     XOD_CHECK(value == 0 || value == 1, "xod_set_option: graph must be 0 or 1");
-    options().graph = (int)value;
+    global_options().graph = (int)value;
     return XOD_OK;
   }
   if (std::strcmp(name, "profile") == 0) {
     XOD_CHECK(value == 0 || value == 1, "xod_set_option: profile must be 0 or 1");
-    options().profile = (int)value;
+    global_options().profile = (int)value;
     return XOD_OK;
   }
   if (std::strcmp(name, "profile_every") == 0) {
     XOD_CHECK(value >= 1 && value <= 1000000, "xod_set_option: profile_every must be >= 1");
-    options().profile_every = (int)value;
+    global_options().profile_every = (int)value;
     return XOD_OK;
   }
   set_error(std::string("xod_set_option: unknown option ") + name);
@@ -195,7 +204,7 @@ extern "C" xod_status xod_set_option(const char *name, int64_t value) {
 
 extern "C" xod_status xod_get_option(const char *name, int64_t *value) {
   XOD_CHECK(name != nullptr && value != nullptr, "xod_get_option: null argument");
-  const Options &o = options();
+  const Options &o = global_options();
   struct Entry { const char *name; int64_t v; };
   const Entry entries[] = {
       {"gemm", o.gemm_mfma},           {"gemm_large", o.gemm_large},
@@ -208,7 +217,7 @@ extern "C" xod_status xod_get_option(const char *name, int64_t *value) {
       {"profile_every", o.profile_every},
       {"refine_tol_exp", (int64_t)std::lround(-std::log10(o.refine_tol))},
       {"refine_atol_exp", (int64_t)std::lround(-std::log10(o.refine_atol))},
-      {"refine64", o.refine64},
+      {"refine64", o.refine64},        {"fused_max_ld", o.fused_max_ld},
   };
   for (const Entry &e : entries)
     if (std::strcmp(name, e.name) == 0) {
@@ -774,6 +783,7 @@ xod_status ensure_fp32_blocks(xod_column *col) {
 // (cyclic reduction, or the fallback of a mixed explicit solve).
 xod_status factor_own_fp64(xod_column *col, const double *B, const double *av,
                            const double *cv) {
+  const TunedScope tuned(col->ld, XOD_FP64, col->solver, false);
   const size_t NL = (size_t)col->N * col->ld;
   XOD_HIP(hipMemcpyAsync(col->B, B, NL * col->ld * sizeof(double), hipMemcpyDeviceToDevice,
                          col->stream));
@@ -1026,6 +1036,7 @@ xod_status refine_fp64(xod_column *c, int *iters) {
 
 xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, double *resid,
                          const double *hist, double hist_coef) {
+  const TunedScope tuned(c->ld, c->prec, c->solver, false);
   c->dt = dt;
   ColArgs a = c->args();
   OneCol one{a};

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "batch.h"
+#include "tune.h"
 
 using namespace xod;
 
@@ -30,6 +31,7 @@ BatchRunner::~BatchRunner() {
   (void)hipFree(d_stats);
   (void)hipFree(d_partial);
   for (hipEvent_t e : gevent) (void)hipEventDestroy(e);
+  for (hipEvent_t e : tev) (void)hipEventDestroy(e);
   for (hipStream_t st : gstream) (void)hipStreamDestroy(st);
   if (fork_ev) (void)hipEventDestroy(fork_ev);
   (void)hipFree(d_ratio);
@@ -147,6 +149,13 @@ xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double
     gstream.push_back(st);
     gevent.push_back(ev);
   }
+  if (time_groups) {
+    while (tev.size() < 2 * gs.size()) {
+      hipEvent_t ev = nullptr;
+      XOD_HIP(hipEventCreate(&ev));
+      tev.push_back(ev);
+    }
+  }
   XOD_HIP(hipEventRecord(fork_ev, s));
   // phase 1: factor and first solve of every group
   for (size_t gi = 0; gi < gs.size(); ++gi) {
@@ -154,6 +163,8 @@ xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double
     g.st = gstream[gi];
     const hipStream_t st = g.st;
     XOD_HIP(hipStreamWaitEvent(st, fork_ev, 0));
+    if (time_groups) XOD_HIP(hipEventRecord(tev[2 * gi], st));
+    const TunedScope tuned(g.ld, g.mixed ? XOD_MIXED : XOD_FP64, XOD_SOLVER_THOMAS, true);
     XOD_HIP(hipMemcpyAsync(d_args + g.base, h_args + g.base, g.nc * sizeof(ColArgs),
                            hipMemcpyHostToDevice, st));
     XOD_HIP(hipMemcpyAsync(d_upd + g.base, h_upd + g.base, g.nc * sizeof(UpdArgs),
@@ -206,6 +217,7 @@ xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double
     Group &g = gs[gi];
     if (!g.mixed) continue;
     const hipStream_t st = g.st;
+    const TunedScope tuned(g.ld, XOD_MIXED, XOD_SOLVER_THOMAS, true);
     const ManyCols acc{d_args + g.base};
     double *ratio = d_ratio + g.roff;
     RefineNext verdict = kRefineFallback;
@@ -247,6 +259,7 @@ xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double
   for (size_t gi = 0; gi < gs.size(); ++gi) {
     Group &g = gs[gi];
     XOD_HIP(launch_update_state(d_upd + g.base, d_red + g.base, g.nc, g.st));
+    if (time_groups) XOD_HIP(hipEventRecord(tev[2 * gi + 1], g.st));
     XOD_HIP(hipEventRecord(gevent[gi], g.st));
     XOD_HIP(hipStreamWaitEvent(s, gevent[gi], 0));
     for (int j = 0; j < g.nc; ++j) {
@@ -259,6 +272,13 @@ xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double
   XOD_HIP(hipMemcpyAsync(h_stats, d_stats, (size_t)n * kStatLen * sizeof(double),
                          hipMemcpyDeviceToHost, s));
   XOD_HIP(hipStreamSynchronize(s));
+  last_group_ms.clear();
+  if (time_groups)
+    for (size_t gi = 0; gi < gs.size(); ++gi) {
+      float ms = 0.f;
+      XOD_HIP(hipEventElapsedTime(&ms, tev[2 * gi], tev[2 * gi + 1]));
+      last_group_ms.push_back({{gs[gi].ld, gs[gi].mixed ? (int)XOD_MIXED : (int)XOD_FP64}, ms});
+    }
   for (auto &pr : slots)
     std::memcpy(&stats[(size_t)pr.first * kStatLen], h_stats + (size_t)pr.second * kStatLen,
                 kStatLen * sizeof(double));
@@ -267,14 +287,9 @@ xod_status BatchRunner::step(const std::vector<xod_column *> &cols, const double
 
 }  // namespace xod
 
-struct xod_batch {
-  std::vector<xod_column *> cols;
-  BatchRunner runner;
-  hipStream_t stream = nullptr;
-  ~xod_batch() {
-    for (auto *c : cols) c->in_batch = false;
-  }
-};
+xod_batch::~xod_batch() {
+  for (auto *c : cols) c->in_batch = false;
+}
 
 #define BCHECK(cond, msg)  \
   do {                     \

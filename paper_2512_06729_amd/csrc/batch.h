@@ -31,6 +31,11 @@ struct BatchRunner {
   // per caller index, from the last step: refinements, FP64 fallback, final ratio
   std::vector<int> last_iters, last_fallback;
   std::vector<double> last_resid;
+  // with time_groups set, each group's device time (ms, events on its
+  // stream around its work) of the last step, keyed by (ld, precision)
+  bool time_groups = false;
+  std::vector<std::pair<std::pair<int, int>, float>> last_group_ms;
+  std::vector<hipEvent_t> tev;
   ~BatchRunner();
   xod_status init(int capacity);
   xod_status step(const std::vector<xod_column *> &cols, const double *dts, bool clip,
@@ -39,3 +44,11 @@ struct BatchRunner {
 };
 
 }  // namespace xod
+
+// A batch handle: its columns and the runner that steps them together.
+struct xod_batch {
+  std::vector<xod_column *> cols;
+  xod::BatchRunner runner;
+  hipStream_t stream = nullptr;
+  ~xod_batch();
+};

@@ -29,6 +29,7 @@
 #include <rocblas/rocblas.h>
 
 #include "cr.h"
+#include "tune.h"
 
 namespace xod {
 
@@ -475,12 +476,14 @@ xod_status CrPlan<T>::replay(hipGraphExec_t *g, bool factor, xod_column *c) {
 
 template <class T>
 xod_status CrPlan<T>::factor(xod_column *c) {
+  const TunedScope tuned(c->ld, c->prec, XOD_SOLVER_CR, false);
   if (options().graph && !options().profile) return replay(&gfactor, true, c);
   return enqueue_factor(c->stream);
 }
 
 template <class T>
 xod_status CrPlan<T>::solve(xod_column *c) {
+  const TunedScope tuned(c->ld, c->prec, XOD_SOLVER_CR, false);
   if (options().graph && !options().profile) return replay(&gsolve, false, c);
   return enqueue_solve(c->stream, c);
 }

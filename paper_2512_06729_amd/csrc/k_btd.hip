@@ -770,7 +770,9 @@ void invert_blocks(const MA &ma, int nmat, int ld, int k, hipStream_t s, bool pr
 // then the backward chain
 //   x_{N-1} = y_{N-1},  x_k = y_k - E_k (c_k x_{k+1}),
 // each step a matrix-vector product of the thread's row segment and a
-// reduction over the TPR threads of the row.
+// reduction over the TPR threads of the row.  It reads the stored pivots,
+// so it also solves with factors of the panel kernels (the option can
+// change between a factorisation and a later solve with it).
 constexpr int kFusedMaxLd = 128;
 
 template <int LD>
@@ -909,19 +911,34 @@ __global__ void __launch_bounds__(256) k_btd_fused_solve(Acc acc) {
   __shared__ double v[LD], y[LD];
   if (t < LD) y[t] = 0.0;
   __syncthreads();
+  // z_r = sum_m W[r][m] v[piv[m]] for this thread's row r = i and segment,
+  // summed over the row's threads; the result belongs to entry rstep[r].
+  // (Factors of the persistent kernel have identity pivots; those of the
+  // panel kernels are in pivot order.  Out-of-range entries of an
+  // incomplete factorisation, which is flagged, read nothing.)
+  auto row_product = [&](int k) -> double {
+    const double *W = c.B + (size_t)k * LD * LD + (size_t)i * LD + j0;
+    const int *pv = c.piv + (size_t)k * LD + j0;
+    double z = 0.0;
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+      const int m = pv[q];
+      z = fma(W[q], (unsigned)m < (unsigned)S ? v[m] : 0.0, z);
+    }
+    return row_sum<F::TPR>(z);
+  };
   for (int k = 0; k < N; ++k) {
     if (t < LD)
       v[t] = t < S ? c.x[(size_t)k * S + t] - (k > 0 ? c.a[(size_t)k * LD + t] * y[t] : 0.0) : 0.0;
     __syncthreads();
-    const double *E = c.B + (size_t)k * LD * LD + (size_t)i * LD + j0;
-    double z = 0.0;
-#pragma unroll
-    for (int q = 0; q < CW; ++q) z = fma(E[q], v[j0 + q], z);
-    z = row_sum<F::TPR>(z);
+    const double z = row_product(k);
     __syncthreads();
     if (owner) {
-      y[i] = z;
-      c.gs[(size_t)k * LD + i] = z;
+      const int j = c.rstep[(size_t)k * LD + i];
+      if ((unsigned)j < (unsigned)LD) {
+        y[j] = z;
+        c.gs[(size_t)k * LD + j] = z;
+      }
     }
     __syncthreads();
   }
@@ -930,16 +947,15 @@ __global__ void __launch_bounds__(256) k_btd_fused_solve(Acc acc) {
   for (int k = N - 2; k >= 0; --k) {
     if (t < LD) v[t] = t < S ? c.c[(size_t)k * LD + t] * y[t] : 0.0;
     __syncthreads();
-    const double *E = c.B + (size_t)k * LD * LD + (size_t)i * LD + j0;
-    double z = 0.0;
-#pragma unroll
-    for (int q = 0; q < CW; ++q) z = fma(E[q], v[j0 + q], z);
-    z = row_sum<F::TPR>(z);
+    const double z = row_product(k);
     __syncthreads();
     if (owner) {
-      const double xi = c.gs[(size_t)k * LD + i] - z;
-      y[i] = xi;
-      if (i < S) c.x[(size_t)k * S + i] = xi;
+      const int j = c.rstep[(size_t)k * LD + i];
+      if ((unsigned)j < (unsigned)LD) {
+        const double xj = c.gs[(size_t)k * LD + j] - z;
+        y[j] = xj;
+        if (j < S) c.x[(size_t)k * S + j] = xj;
+      }
     }
     __syncthreads();
   }

@@ -105,7 +105,9 @@ struct Options {
   int profile = 0;        // record HIP events around profiled launches
   int profile_every = 1;  // profile layers k with k % profile_every == 0
 };
-Options &options();
+Options &options();          // the effective options (a tuned scope's, if one is active)
+Options &global_options();   // the process-wide options (xod_set_option)
+Options *&options_override();   // this thread's tuned options, or null
 
 // Event-based launch timing (enabled with the "profile" option).  Kinds:
 enum ProfKind { kProfPanel = 0, kProfUpdate, kProfPrologue, kProfSolve, kProfJac,
