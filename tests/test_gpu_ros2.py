@@ -93,9 +93,11 @@ def test_steady_state_driver_matches_oracle(method, name):
     assert res["converged"] == 1 and ref.converged and ref.t < 1e30
     assert res["steps"] == ref.steps and res["rejects"] == ref.rejects
     assert res["t"] == pytest.approx(ref.t, rel=1e-12)
+    # same decisions, so the end states differ only by the solves' rounding
+    # (measured at most 1.7e-13 with either block-Thomas kernel and ROS2)
     n = gcol.state()
-    keep = ref.n > 1e-20 * prob.grid.ngas[:, None]
-    np.testing.assert_allclose(n[keep], ref.n[keep], rtol=1e-6)
+    keep = ref.n > 1e-30 * prob.grid.ngas[:, None]
+    np.testing.assert_allclose(n[keep], ref.n[keep], rtol=1e-10)
 
 
 def test_steady_state_driver_method_checks():
