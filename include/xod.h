@@ -531,6 +531,10 @@ xod_status xod_photolysis_spectral_noalloc(int32_t N, int32_t S, int32_t A, int3
  *            gather kernel copies each product's row-permuted operand into
  *            scratch blocks.  The two sum in different orders (same to
  *            rounding).
+ *   "gemm_waves": waves per work-group of the 128 x 128 block-product
+ *            tiles, 16 (default: 2 x 2 MFMA tiles per wave) or 8 (4 x 2,
+ *            each LDS fragment of A feeding two MFMAs and of B four); same
+ *            K order, same bits;
  *   "gemm_k": K step of the block products staged through LDS, 16 or 32
  *            (default 32); every element sums its K terms in the same order
  *            with either.
@@ -619,15 +623,14 @@ xod_status xod_batch_step(xod_batch *b, const double *dt_per_col,
  * rounding.  Candidates: block Thomas: the persistent small-block kernels
  * (blocks up to 128, FP64), or the panel kernels with outer panels of 32,
  * 64 or 128 columns and 16- or 32-column strip updates; cyclic reduction:
- * block-product tiles 128 or 64, K step 32 or 16, one or two barriers per
- * pivot column.  The first candidate is always the current xod_set_option
+ * block-product tiles 128 (16 or 8 waves) or 64, K step 32 or 16, one or
+ * two barriers per pivot column.  The first candidate is always the current xod_set_option
  * setting (default_ms). */
 typedef struct {
   char key[96];          /* "arch/ldN/precision/factorisation/column|batch" */
   int32_t candidates;    /* settings timed */
-  int32_t fused_max_ld, outer, update32, gemm_large, gemm_k, panel_sync;
-                         /* the chosen setting */
-  int32_t pad_;
+  int32_t fused_max_ld, outer, update32, gemm_large, gemm_k, panel_sync,
+          gemm_waves;    /* the chosen setting */
   double best_ms;        /* its time (one step's solve, or one group's step) */
   double default_ms;     /* the first candidate's time */
 } xod_tune_result;

@@ -106,10 +106,10 @@ class TuneResult(ctypes.Structure):
     _fields_ = [("key", ctypes.c_char * 96), ("candidates", c_int32),
                 ("fused_max_ld", c_int32), ("outer", c_int32), ("update32", c_int32),
                 ("gemm_large", c_int32), ("gemm_k", c_int32), ("panel_sync", c_int32),
-                ("pad_", c_int32), ("best_ms", c_double), ("default_ms", c_double)]
+                ("gemm_waves", c_int32), ("best_ms", c_double), ("default_ms", c_double)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
         d["key"] = self.key.decode()
         return d
 

@@ -136,6 +136,11 @@ extern "C" xod_status xod_set_option(const char *name, int64_t value) {
     global_options().panel_defer = (int)value;
     return XOD_OK;
   }
+  if (std::strcmp(name, "gemm_waves") == 0) {
+    XOD_CHECK(value == 8 || value == 16, "xod_set_option: gemm_waves must be 8 or 16");
+    global_options().gemm_waves = (int)value;
+    return XOD_OK;
+  }
   if (std::strcmp(name, "gemm_k") == 0) {
     XOD_CHECK(value == 16 || value == 32, "xod_set_option: gemm_k must be 16 or 32");
     global_options().gemm_k = (int)value;
@@ -209,6 +214,7 @@ extern "C" xod_status xod_get_option(const char *name, int64_t *value) {
   const Entry entries[] = {
       {"gemm", o.gemm_mfma},           {"gemm_large", o.gemm_large},
       {"gemm_k", o.gemm_k},            {"outer", o.outer},
+      {"gemm_waves", o.gemm_waves},
       {"panel_sync", o.panel_sync},    {"gemm_lib", o.gemm_lib},
       {"panel_defer", o.panel_defer},
       {"outer_nmat", o.outer_nmat},    {"update32", o.update32},

@@ -445,11 +445,12 @@ xod_status CrPlan<T>::enqueue_solve(hipStream_t s, xod_column *c) {
 // stream.  The graphs hold kernel nodes only.
 template <class T>
 xod_status CrPlan<T>::replay(hipGraphExec_t *g, bool factor, xod_column *c) {
-  const long long key = (((long long)options().outer_nmat * 256 + options().outer) * 64 +
-                         options().gemm_k * 4 + options().panel_sync * 2 + options().gemm_lib) * 8 +
-                        options().gemm_large * 4 + options().gemm_mfma * 2 + options().update32 +
-                        (long long)options().update32_min * (1LL << 40);
-  if (graph_gemm != key) {
+  const Options &o = options();
+  const std::array<int, 11> key = {o.outer_nmat, o.outer,      o.gemm_k,     o.panel_sync,
+                                   o.gemm_lib,   o.gemm_large, o.gemm_mfma,  o.update32,
+                                   o.update32_min, o.gemm_waves, o.panel_defer};
+  if (!graph_valid || graph_gemm != key) {
+    graph_valid = true;
     if (gfactor) XOD_HIP(hipGraphExecDestroy(gfactor));
     if (gsolve) XOD_HIP(hipGraphExecDestroy(gsolve));
     gfactor = gsolve = nullptr;

@@ -1,6 +1,7 @@
 // Block cyclic reduction plan of one column (host side).
 #pragma once
 
+#include <array>
 #include <vector>
 
 #include "handles.h"
@@ -65,7 +66,8 @@ struct CrPlan {
   // column's stream; built on first use with the options then in force
   hipStream_t cap = nullptr;   // capture stream
   hipGraphExec_t gfactor = nullptr, gsolve = nullptr;
-  long long graph_gemm = -1;   // the kernel options the graphs were captured with
+  std::array<int, 11> graph_gemm{};   // the kernel options the graphs were captured with
+  bool graph_valid = false;
 
   ~CrPlan();
   // Device descriptors for the column's buffers (blocks, couplings, pivots).

@@ -28,21 +28,25 @@ __device__ __forceinline__ int in_block(int i, int ld) {
 }
 
 // ---------------------------------------------------------------------------
-// Block products.  One work-group of 16 waves per BM x BM output tile (BM =
-// 64 or 128); the waves form a 4 x 4 grid, each owning a (BM/4)^2 sub-tile
-// of (BM/64)^2 16 x 16 MFMA accumulators, so each LDS fragment feeds BM/64
-// MFMAs.  K is staged through LDS in steps of KB (double-buffered: the next
+// Block products.  One work-group of NT / 64 waves per BM x BM output tile
+// (BM = 64 or 128; NT = 1024, or 512 for 128-tiles with option gemm_waves =
+// 8); the waves form a (NT / 256) x 4 grid, each owning a sub-tile of
+// TMR x TMC 16 x 16 MFMA accumulators (2 x 2 with 16 waves, 4 x 2 with 8),
+// so each LDS fragment feeds TMC or TMR MFMAs.  K is staged through LDS in steps of KB (double-buffered: the next
 // step's global loads are issued before the MFMAs of the current one).  Every
 // output element accumulates its K terms in increasing order whatever BM and
 // KB are.  Rows / columns beyond ld are never touched (ld is a multiple of
 // 32).
 constexpr int kGemmThreads = 1024;
 
-template <class T, int BM, int KB>
-__global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmOp<T> *ops, int ld) {
-  constexpr int TM = BM / 64;                       // MFMA tiles per wave and dimension
-  constexpr int AL = BM * KB / kGemmThreads;        // A elements staged per thread
-  constexpr int BL = KB * BM / kGemmThreads;        // B elements staged per thread
+template <class T, int BM, int KB, int NT = kGemmThreads>
+__global__ void __launch_bounds__(NT) k_gemm(const GemmOp<T> *ops, int ld) {
+  constexpr int WR = NT / 256;                      // wave rows (4 wave columns)
+  constexpr int TMR = BM / (16 * WR);               // MFMA tiles per wave, rows
+  constexpr int TMC = BM / 64;                      // MFMA tiles per wave, columns
+  constexpr int AL = BM * KB / NT;                  // A elements staged per thread
+  constexpr int BL = KB * BM / NT;                  // B elements staged per thread
+  static_assert(AL >= 1 && BL >= 1 && TMR >= 1, "tile shape");
   const GemmOp<T> g = ops[blockIdx.z];
   const int tm0 = blockIdx.y * BM, tn0 = blockIdx.x * BM;
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
@@ -50,11 +54,11 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmOp<T> *ops, int
   __shared__ T As[2][BM][KB + 1];
   __shared__ T Bs[2][KB][BM + 2];
   __shared__ int sbg[2][kMaxLd];   // the row gathers of B and B2
-  typename Vec4<T>::type acc[TM][TM];
+  typename Vec4<T>::type acc[TMR][TMC];
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int i = 0; i < TMR; ++i)
 #pragma unroll
-    for (int j = 0; j < TM; ++j) acc[i][j] = {0, 0, 0, 0};
+    for (int j = 0; j < TMC; ++j) acc[i][j] = {0, 0, 0, 0};
   const int nk1 = ld / KB;
   const int nk = g.A2 ? 2 * nk1 : nk1;
   for (int m = threadIdx.x; m < ld; m += blockDim.x) {
@@ -73,36 +77,35 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmOp<T> *ops, int
     const int *gb = sbg[second ? 1 : 0];
 #pragma unroll
     for (int e = 0; e < AL; ++e) {
-      const int idx = t + e * kGemmThreads, r = tm0 + idx / KB;
+      const int idx = t + e * NT, r = tm0 + idx / KB;
       ra[e] = r < ld ? A[(size_t)r * ld + k0 + idx % KB] : T(0);
     }
 #pragma unroll
     for (int e = 0; e < BL; ++e) {
-      const int idx = t + e * kGemmThreads, c = tn0 + idx % BM;
+      const int idx = t + e * NT, c = tn0 + idx % BM;
       rb[e] = c < ld ? B[(size_t)gb[k0 + idx / BM] * ld + c] : T(0);
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < AL; ++e) {
-      const int idx = t + e * kGemmThreads;
+      const int idx = t + e * NT;
       As[buf][idx / KB][idx % KB] = ra[e];
     }
 #pragma unroll
     for (int e = 0; e < BL; ++e) {
-      const int idx = t + e * kGemmThreads;
+      const int idx = t + e * NT;
       Bs[buf][idx / BM][idx % BM] = rb[e];
     }
   };
   // 16 x 16 output tiles wholly beyond ld (the last tile row / column of a
   // block whose size is not a multiple of BM) are skipped: wave-uniform
   // conditions, so waves of edge tiles leave their SIMD to other work-groups.
-  bool live_r[TM], live_c[TM];
+  bool live_r[TMR], live_c[TMC];
 #pragma unroll
-  for (int i = 0; i < TM; ++i) {
-    live_r[i] = tm0 + (wr * TM + i) * 16 < ld;
-    live_c[i] = tn0 + (wc * TM + i) * 16 < ld;
-  }
+  for (int i = 0; i < TMR; ++i) live_r[i] = tm0 + (wr * TMR + i) * 16 < ld;
+#pragma unroll
+  for (int j = 0; j < TMC; ++j) live_c[j] = tn0 + (wc * TMC + j) * 16 < ld;
   gload(0);
   sstore(0);
   __syncthreads();
@@ -111,30 +114,30 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmOp<T> *ops, int
     if (kt + 1 < nk) gload(kt + 1);
 #pragma unroll
     for (int kk = 0; kk < KB / 4; ++kk) {
-      T av[TM], bv[TM];
+      T av[TMR], bv[TMC];
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
-        av[i] = As[buf][(wr * TM + i) * 16 + (lane & 15)][kk * 4 + (lane >> 4)];
+      for (int i = 0; i < TMR; ++i)
+        av[i] = As[buf][(wr * TMR + i) * 16 + (lane & 15)][kk * 4 + (lane >> 4)];
 #pragma unroll
-      for (int j = 0; j < TM; ++j)
-        bv[j] = Bs[buf][kk * 4 + (lane >> 4)][(wc * TM + j) * 16 + (lane & 15)];
+      for (int j = 0; j < TMC; ++j)
+        bv[j] = Bs[buf][kk * 4 + (lane >> 4)][(wc * TMC + j) * 16 + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+      for (int i = 0; i < TMR; ++i)
 #pragma unroll
-        for (int j = 0; j < TM; ++j)
+        for (int j = 0; j < TMC; ++j)
           if (live_r[i] && live_c[j]) acc[i][j] = mfma16(av[i], bv[j], acc[i][j]);
     }
     if (kt + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int i = 0; i < TMR; ++i)
 #pragma unroll
-    for (int j = 0; j < TM; ++j) {
-      const int c = tn0 + (wc * TM + j) * 16 + (lane & 15);
+    for (int j = 0; j < TMC; ++j) {
+      const int c = tn0 + (wc * TMC + j) * 16 + (lane & 15);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int r = tm0 + (wr * TM + i) * 16 + mfma_row(T(0), lane, q);
+        const int r = tm0 + (wr * TMR + i) * 16 + mfma_row(T(0), lane, q);
         if (r < ld && c < ld) {
           const auto p = gmem(g.C) + (size_t)r * ld + c;
           const double v = g.alpha * (double)acc[i][j][q];
@@ -154,7 +157,10 @@ hipError_t launch_gemm(const GemmOp<T> *dops, int count, int ld, hipStream_t s) 
   if (prof) prof_begin(kProfGemm, s);
   // large tiles when the batch alone gives every CU two work-groups
   if (options().gemm_large && (size_t)count * ntl * ntl >= 512) {
-    if (k32)
+    if (k32 && options().gemm_waves == 8)
+      hipLaunchKernelGGL((k_gemm<T, 128, 32, 512>), dim3(ntl, ntl, count), dim3(512), 0, s, dops,
+                         ld);
+    else if (k32)
       hipLaunchKernelGGL((k_gemm<T, 128, 32>), dim3(ntl, ntl, count), dim3(kGemmThreads), 0, s,
                          dops, ld);
     else

@@ -56,10 +56,12 @@ void apply(const TuneVals &v, Options &o) {
   o.gemm_large = v.gemm_large;
   o.gemm_k = v.gemm_k;
   o.panel_sync = v.panel_sync;
+  o.gemm_waves = v.gemm_waves;
 }
 
 TuneVals current(const Options &o) {
-  return TuneVals{o.fused_max_ld, o.outer, o.update32, o.gemm_large, o.gemm_k, o.panel_sync};
+  return TuneVals{o.fused_max_ld, o.outer, o.update32, o.gemm_large, o.gemm_k, o.panel_sync,
+                  o.gemm_waves};
 }
 
 // Candidates for one kind of column; the first is the process-wide setting.
@@ -81,6 +83,14 @@ std::vector<TuneVals> candidates(int ld, xod_precision prec, xod_solver solver) 
           v.panel_sync = sync;
           add(v);
         }
+    for (int sync : {2, 1}) {   // 8-wave 128-tiles (32-wide K only)
+      TuneVals v = base;
+      v.gemm_large = 1;
+      v.gemm_k = 32;
+      v.gemm_waves = 8;
+      v.panel_sync = sync;
+      add(v);
+    }
     return out;
   }
   if (prec == XOD_FP64 && ld <= 128) {
@@ -117,6 +127,7 @@ void fill_result(xod_tune_result *r, const std::string &key, const TuneVals &v, 
   r->gemm_large = v.gemm_large;
   r->gemm_k = v.gemm_k;
   r->panel_sync = v.panel_sync;
+  r->gemm_waves = v.gemm_waves;
 }
 
 }  // namespace

@@ -10,7 +10,7 @@ namespace xod {
 
 // The tile options the tuner chooses.
 struct TuneVals {
-  int fused_max_ld, outer, update32, gemm_large, gemm_k, panel_sync;
+  int fused_max_ld, outer, update32, gemm_large, gemm_k, panel_sync, gemm_waves;
 };
 
 // While alive, options() on this thread returns the process-wide options

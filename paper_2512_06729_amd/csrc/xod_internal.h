@@ -96,6 +96,7 @@ struct Options {
   int refine64 = 0;            // FP64 steps: refinements with the FP64 factors (0: none)
   int gemm_large = 1;     // 128 x 128 product tiles for large batches
   int gemm_k = 32;        // K step of the block products staged in LDS (16 or 32)
+  int gemm_waves = 16;    // waves per 128-tile work-group of the block products (16 or 8)
   int panel_sync = 2;     // barriers per Gauss-Jordan column (1 or 2)
   int panel_defer = 0;    // 1: panel eliminations of other columns deferred by one column
   int gemm_lib = 0;       // cyclic-reduction block products: 1 = rocBLAS batched GEMM
