@@ -206,21 +206,24 @@ def trajectory(xod, gnet, col, precision, solver, dt, steps, stream):
     return out
 
 
-def bench_config1(xod, torch, stream):
+def bench_config1(xod, torch, stream, only=None):
     """Latency-bound workload: the 12-species x 20-layer column through the
     200-step fixed schedule dt_j = 1e-8 1.2^j, back to back (every step is
-    synchronous: it reads its statistics)."""
+    synchronous: it reads its statistics).  only: one variant ("cr",
+    "thomas", "thomas_panels"), for a kernel trace of that variant alone."""
     import synth
     from paper_2512_06729_amd import XOD_SOLVER_CR, XOD_SOLVER_THOMAS
     net, col = synth.make_config(1)
     gnet = xod.Network(net)
     sched = [1e-8 * 1.2 ** j for j in range(200)]
     out = {"workload": "S=12, R=30, N=20: 200 fixed-schedule backward-Euler steps",
-           "thomas": "block Thomas in one persistent launch each for the factorisation and "
+           "variants": "thomas: block Thomas in one persistent launch each for the factorisation and "
                      "the solve (blocks up to 64); thomas_panels: the per-layer panel "
                      "kernels of the large blocks"}
     for name, solver, fused in (("cr", XOD_SOLVER_CR, 64), ("thomas", XOD_SOLVER_THOMAS, 64),
                                 ("thomas_panels", XOD_SOLVER_THOMAS, 0)):
+        if only and name != only:
+            continue
         xod.set_option("fused_max_ld", fused)
         g = xod.Column(gnet, col, stream=stream, solver=solver)
         xod.xod_step(g, 1e-8)
@@ -635,6 +638,9 @@ def main():
     ap.add_argument("--skip-serve", action="store_true")
     ap.add_argument("--skip-photolysis", action="store_true")
     ap.add_argument("--skip-parcel", action="store_true")
+    ap.add_argument("--only-config1", choices=("cr", "thomas", "thomas_panels"),
+                    help="run only the 12-species latency leg with one factorisation variant "
+                         "(201 steps: one warm-up and the 200-step schedule) and print its line")
     ap.add_argument("--skip-reuse", action="store_true",
                     help="skip the kept-factorisation legs (steady state method 2, fixed dt)")
     ap.add_argument("--serve-requests", type=int, default=4)
@@ -666,6 +672,11 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.only_config1:
+        stream = torch.cuda.current_stream().cuda_stream
+        print(json.dumps({"config1_latency": bench_config1(xod, torch, stream,
+                                                           only=args.only_config1)}))
+        return
     if args.pmc_calibrate:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

@@ -775,13 +775,20 @@ void invert_blocks(const MA &ma, int nmat, int ld, int k, hipStream_t s, bool pr
 // change between a factorisation and a later solve with it).
 constexpr int kFusedMaxLd = 128;
 
-template <int LD>
+// NT threads per work-group: four waves.  (One wave for blocks up to 64,
+// the pivot exchange then staying inside the wave, measured slower: 384
+// against 277 us per 12-species step, the wave issuing every step alone.)
+template <int LD, int NT>
 struct FusedShape {
-  static constexpr int TPR = LD <= 32 ? 8 : (LD <= 64 ? 4 : 2);   // threads per row
-  static constexpr int CW = LD / TPR;                             // columns per thread
-  static constexpr int THREADS = LD * TPR;                        // 256, 256, 192, 256
+  static constexpr int R = NT / LD;
+  static constexpr int TPR = R >= 8 ? 8 : (R >= 4 ? 4 : (R >= 2 ? 2 : 1));   // threads per row
+  static constexpr int CW = LD / TPR;                                     // columns per thread
+  static constexpr int THREADS = LD * TPR;
+  static constexpr int WAVES = NT / 64;
+  static_assert(THREADS <= NT && CW * TPR == LD && WAVES >= 1 && WAVES <= 4, "shape");
 };
-static_assert(FusedShape<96>::THREADS <= 256 && FusedShape<128>::THREADS <= 256, "shape");
+template <int LD>
+constexpr int fused_threads() { return 256; }
 
 // Sum over the TPR consecutive lanes that share a row.
 template <int TPR>
@@ -791,9 +798,9 @@ __device__ __forceinline__ double row_sum(double z) {
   return z;
 }
 
-template <class Acc, int LD>
-__global__ void __launch_bounds__(256) k_btd_fused_factor(Acc acc) {
-  using F = FusedShape<LD>;
+template <class Acc, int LD, int NT = fused_threads<LD>()>
+__global__ void __launch_bounds__(NT) k_btd_fused_factor(Acc acc) {
+  using F = FusedShape<LD, NT>;
   constexpr int CW = F::CW, TPR = F::TPR;
   const ColArgs &c = acc(blockIdx.x);
   const int N = c.N, S = c.S;
@@ -802,7 +809,7 @@ __global__ void __launch_bounds__(256) k_btd_fused_factor(Acc acc) {
   const int i = active ? t / TPR : 0, h = active ? t % TPR : 0, j0 = h * CW;
   __shared__ double Es[LD][LD];
   __shared__ double rowp[LD], colk[LD];   // rowp in (part, slot) order
-  __shared__ double wkey[4];
+  __shared__ double wkey[F::WAVES];
   __shared__ int pvrow[LD];
   if (t < 4) c.flag[t] = -1;
   double A[CW];
@@ -837,7 +844,9 @@ __global__ void __launch_bounds__(256) k_btd_fused_factor(Acc acc) {
         const double m = wave_max(key);
         if (lane == 0) wkey[t >> 6] = m;
         __syncthreads();
-        const double K = fmax(fmax(wkey[0], wkey[1]), fmax(wkey[2], wkey[3]));
+        double K = wkey[0];
+#pragma unroll
+        for (int wv = 1; wv < F::WAVES; ++wv) K = fmax(K, wkey[wv]);
         int p = 1023 - (__double2loint(K) & 1023);
         if (K == 0.0 || p >= S) p = kcol;        // no usable pivot: flagged, stays in bounds
         if (active && i == p) {
@@ -898,9 +907,9 @@ __global__ void __launch_bounds__(256) k_btd_fused_factor(Acc acc) {
   }
 }
 
-template <class Acc, int LD>
-__global__ void __launch_bounds__(256) k_btd_fused_solve(Acc acc) {
-  using F = FusedShape<LD>;
+template <class Acc, int LD, int NT = fused_threads<LD>()>
+__global__ void __launch_bounds__(NT) k_btd_fused_solve(Acc acc) {
+  using F = FusedShape<LD, NT>;
   constexpr int CW = F::CW;
   const ColArgs &c = acc(blockIdx.x);
   const int N = c.N, S = c.S;
@@ -964,10 +973,10 @@ __global__ void __launch_bounds__(256) k_btd_fused_solve(Acc acc) {
 template <class Acc>
 hipError_t launch_fused_factor(const Acc &acc, int ncols, int ld, hipStream_t s) {
   switch (ld) {
-    case 32: hipLaunchKernelGGL((k_btd_fused_factor<Acc, 32>), dim3(ncols), dim3(256), 0, s, acc); break;
-    case 64: hipLaunchKernelGGL((k_btd_fused_factor<Acc, 64>), dim3(ncols), dim3(256), 0, s, acc); break;
-    case 96: hipLaunchKernelGGL((k_btd_fused_factor<Acc, 96>), dim3(ncols), dim3(256), 0, s, acc); break;
-    case 128: hipLaunchKernelGGL((k_btd_fused_factor<Acc, 128>), dim3(ncols), dim3(256), 0, s, acc); break;
+    case 32: hipLaunchKernelGGL((k_btd_fused_factor<Acc, 32>), dim3(ncols), dim3(fused_threads<32>()), 0, s, acc); break;
+    case 64: hipLaunchKernelGGL((k_btd_fused_factor<Acc, 64>), dim3(ncols), dim3(fused_threads<64>()), 0, s, acc); break;
+    case 96: hipLaunchKernelGGL((k_btd_fused_factor<Acc, 96>), dim3(ncols), dim3(fused_threads<96>()), 0, s, acc); break;
+    case 128: hipLaunchKernelGGL((k_btd_fused_factor<Acc, 128>), dim3(ncols), dim3(fused_threads<128>()), 0, s, acc); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -976,10 +985,10 @@ hipError_t launch_fused_factor(const Acc &acc, int ncols, int ld, hipStream_t s)
 template <class Acc>
 hipError_t launch_fused_solve(const Acc &acc, int ncols, int ld, hipStream_t s) {
   switch (ld) {
-    case 32: hipLaunchKernelGGL((k_btd_fused_solve<Acc, 32>), dim3(ncols), dim3(256), 0, s, acc); break;
-    case 64: hipLaunchKernelGGL((k_btd_fused_solve<Acc, 64>), dim3(ncols), dim3(256), 0, s, acc); break;
-    case 96: hipLaunchKernelGGL((k_btd_fused_solve<Acc, 96>), dim3(ncols), dim3(256), 0, s, acc); break;
-    case 128: hipLaunchKernelGGL((k_btd_fused_solve<Acc, 128>), dim3(ncols), dim3(256), 0, s, acc); break;
+    case 32: hipLaunchKernelGGL((k_btd_fused_solve<Acc, 32>), dim3(ncols), dim3(fused_threads<32>()), 0, s, acc); break;
+    case 64: hipLaunchKernelGGL((k_btd_fused_solve<Acc, 64>), dim3(ncols), dim3(fused_threads<64>()), 0, s, acc); break;
+    case 96: hipLaunchKernelGGL((k_btd_fused_solve<Acc, 96>), dim3(ncols), dim3(fused_threads<96>()), 0, s, acc); break;
+    case 128: hipLaunchKernelGGL((k_btd_fused_solve<Acc, 128>), dim3(ncols), dim3(fused_threads<128>()), 0, s, acc); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
