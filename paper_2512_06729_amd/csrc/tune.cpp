@@ -31,14 +31,23 @@ std::map<std::string, TuneVals> &tune_table() {
   return t;
 }
 
+// The architecture name of the current device, looked up once per device
+// (every tuned factorisation asks for it).
 std::string arch_name() {
+  static std::mutex mu;
+  static std::map<int, std::string> names;
   int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = names.find(dev);
+  if (it != names.end()) return it->second;
   hipDeviceProp_t p;
-  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess)
-    return "unknown";
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
   std::string a = p.gcnArchName;
   const size_t colon = a.find(':');
-  return colon == std::string::npos ? a : a.substr(0, colon);
+  if (colon != std::string::npos) a = a.substr(0, colon);
+  names[dev] = a;
+  return a;
 }
 
 std::string tune_key(int ld, xod_precision prec, xod_solver solver, bool batch) {
