@@ -153,7 +153,9 @@ xod_status xod_column_create(const xod_network *net, const xod_profile *prof,
 xod_status xod_column_destroy(xod_column *col);
 
 /* State transfer (synchronous).  n is a HOST pointer [N*S]; t and dt may be
- * NULL.  The state (n, t, dt) is the whole checkpoint of a column. */
+ * NULL.  The state (n, t, dt) is the whole checkpoint of a column; setting
+ * it also clears the step history (BDF2's previous step, the mixed-precision
+ * step size that fell back to FP64). */
 xod_status xod_column_get_state(const xod_column *col, double *n, double *t,
                                 double *dt);
 xod_status xod_column_set_state(xod_column *col, const double *n, double t,
@@ -257,8 +259,13 @@ xod_status xod_btd_solve_info(const xod_column *col, int32_t *refine_iters,
  * max_k |delta_k| (rtol 1e-7, atol 1e-14: options "refine_tol_exp",
  * "refine_atol_exp"), or, once the corrections stop halving or after 10
  * refinements, if they are within ten times that; otherwise the step is
- * refactored and solved in FP64.  Synchronous (reads the
- * statistics). */
+ * refactored and solved in FP64.  After such a fallback at step size dt_f,
+ * the column's next steps of size >= dt_f go to FP64 directly (option
+ * "mixed_sticky", default 16 steps; fp64_fallback 1, refine_iters 0), then
+ * FP32 is tried again; one that converges at a size >= dt_f clears dt_f.
+ * The larger steps' FP32 factors would not converge either: along a
+ * steady-state solve of the 594-species column every step from dt ~ 2 s on
+ * fell back.  Synchronous (reads the statistics). */
 typedef struct {
   double max_rel_change;   /* max |delta| / |n_new| over n_new/n_gas > 1e-30 */
   double min_ratio;        /* min n_new / n_gas                               */
@@ -544,6 +551,9 @@ xod_status xod_photolysis_spectral_noalloc(int32_t N, int32_t S, int32_t A, int3
  *            absolute floor below;
  *   "refine_atol_exp": e in 8..17: that floor, 10^-e times the layer's
  *            largest increment (default 14);
+ *   "mixed_sticky": 0..1000 (default 16): the number of steps a
+ *            mixed-precision column takes in FP64 directly after a fallback
+ *            (see xod_step); 0 = always try FP32 first;
  *   "refine64": 0..10 corrections of every FP64 solve of a step with its
  *            own factors (residual in FP64 from the reaction list), a fixed
  *            number with no host round trip; a layer whose last correction

@@ -136,6 +136,11 @@ extern "C" xod_status xod_set_option(const char *name, int64_t value) {
     global_options().panel_defer = (int)value;
     return XOD_OK;
   }
+  if (std::strcmp(name, "mixed_sticky") == 0) {
+    XOD_CHECK(value >= 0 && value <= 1000, "xod_set_option: mixed_sticky must be in 0..1000");
+    global_options().mixed_sticky = (int)value;
+    return XOD_OK;
+  }
   if (std::strcmp(name, "gemm_waves") == 0) {
     XOD_CHECK(value == 8 || value == 16, "xod_set_option: gemm_waves must be 8 or 16");
     global_options().gemm_waves = (int)value;
@@ -214,7 +219,7 @@ extern "C" xod_status xod_get_option(const char *name, int64_t *value) {
   const Entry entries[] = {
       {"gemm", o.gemm_mfma},           {"gemm_large", o.gemm_large},
       {"gemm_k", o.gemm_k},            {"outer", o.outer},
-      {"gemm_waves", o.gemm_waves},
+      {"gemm_waves", o.gemm_waves},    {"mixed_sticky", o.mixed_sticky},
       {"panel_sync", o.panel_sync},    {"gemm_lib", o.gemm_lib},
       {"panel_defer", o.panel_defer},
       {"outer_nmat", o.outer_nmat},    {"update32", o.update32},
@@ -542,6 +547,8 @@ extern "C" xod_status xod_column_set_state(xod_column *col, const double *n, dou
   col->t = t;
   col->dt = dt;
   col->prev_dt = 0.0;
+  col->mixed_fb_dt = 0.0;   // a new state starts a new history of precision choices
+  col->mixed_direct = 0;
   return XOD_OK;
 }
 
@@ -1078,41 +1085,57 @@ xod_status enqueue_solve(xod_column *c, double dt, int *iters, int *fallback, do
   }
   // Mixed precision: row-scaled FP32 Schur complements, FP64 refinement with a
   // matrix-free FP64 residual; FP64 refactorisation if refinement stalls.
+  // Precision control: once a step of size dt_f fell back, the next
+  // `mixed_sticky` steps of size >= dt_f go to FP64 directly (the FP32
+  // factors of the larger, worse-conditioned steps would not converge
+  // either), then one tries FP32 again; a step of size >= dt_f that
+  // converges in FP32 clears dt_f.
   const size_t NSb = (size_t)c->N * c->S * sizeof(double);
-  XOD_HIP(launch_jacobian(one, 1, c->N, c->R, c->ld, true, c->stream));
-  if (cr)
-    XOD_TRY(c->cr32->factor(c));
-  else
-    XOD_HIP(launch_factor_mixed(one, 1, c->N, c->ld, c->stream));
-  XOD_HIP(launch_scale(one, 1, c->N, c->S, c->stream));
-  if (cr)
-    XOD_TRY(c->cr32->solve(c));
-  else
-    XOD_HIP(launch_solve_mixed(one, 1, c->N, c->ld, c->stream));
-  XOD_HIP(hipMemcpyAsync(c->dx, c->x, NSb, hipMemcpyDeviceToDevice, c->stream));
-  RefineNext verdict = kRefineFallback;
-  double prev = 1e300, ratio = 1e300;
-  for (int it = 1; it <= c->max_refine; ++it) {
-    XOD_HIP(launch_residual(one, 1, c->N, c->S, c->R, c->stream));
+  const int sticky = options().mixed_sticky;
+  const bool direct = sticky > 0 && c->mixed_fb_dt > 0.0 && dt >= c->mixed_fb_dt &&
+                      c->mixed_direct < sticky;
+  if (direct) {
+    ++c->mixed_direct;
+  } else {
+    XOD_HIP(launch_jacobian(one, 1, c->N, c->R, c->ld, true, c->stream));
+    if (cr)
+      XOD_TRY(c->cr32->factor(c));
+    else
+      XOD_HIP(launch_factor_mixed(one, 1, c->N, c->ld, c->stream));
+    XOD_HIP(launch_scale(one, 1, c->N, c->S, c->stream));
     if (cr)
       XOD_TRY(c->cr32->solve(c));
     else
       XOD_HIP(launch_solve_mixed(one, 1, c->N, c->ld, c->stream));
-    XOD_HIP(launch_axpy_ratio(one, 1, c->N, c->ratio, c->rmax, c->stream));
-    XOD_HIP(hipMemcpyAsync(c->stats_host, c->rmax, sizeof(double), hipMemcpyDeviceToHost,
-                           c->stream));
-    XOD_HIP(hipStreamSynchronize(c->stream));
-    ratio = c->stats_host[0];
-    *iters = it;
-    verdict = refine_next(ratio, prev, it, c->max_refine);
-    if (verdict != kRefineMore) break;
-    prev = ratio;
-  }
-  const bool ok = verdict == kRefineDone;
-  *resid = ratio;
-  if (ok) {
-    XOD_HIP(hipMemcpyAsync(c->x, c->dx, NSb, hipMemcpyDeviceToDevice, c->stream));
-    return XOD_OK;
+    XOD_HIP(hipMemcpyAsync(c->dx, c->x, NSb, hipMemcpyDeviceToDevice, c->stream));
+    RefineNext verdict = kRefineFallback;
+    double prev = 1e300, ratio = 1e300;
+    for (int it = 1; it <= c->max_refine; ++it) {
+      XOD_HIP(launch_residual(one, 1, c->N, c->S, c->R, c->stream));
+      if (cr)
+        XOD_TRY(c->cr32->solve(c));
+      else
+        XOD_HIP(launch_solve_mixed(one, 1, c->N, c->ld, c->stream));
+      XOD_HIP(launch_axpy_ratio(one, 1, c->N, c->ratio, c->rmax, c->stream));
+      XOD_HIP(hipMemcpyAsync(c->stats_host, c->rmax, sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+      XOD_HIP(hipStreamSynchronize(c->stream));
+      ratio = c->stats_host[0];
+      *iters = it;
+      verdict = refine_next(ratio, prev, it, c->max_refine);
+      if (verdict != kRefineMore) break;
+      prev = ratio;
+    }
+    const bool ok = verdict == kRefineDone;
+    *resid = ratio;
+    if (ok) {
+      XOD_HIP(hipMemcpyAsync(c->x, c->dx, NSb, hipMemcpyDeviceToDevice, c->stream));
+      if (dt >= c->mixed_fb_dt) c->mixed_fb_dt = 0.0;
+      c->mixed_direct = 0;
+      return XOD_OK;
+    }
+    c->mixed_fb_dt = c->mixed_fb_dt > 0.0 ? std::min(c->mixed_fb_dt, dt) : dt;
+    c->mixed_direct = 0;
   }
   *fallback = 1;
   XOD_HIP(launch_jacobian(one, 1, c->N, c->R, c->ld, false, c->stream));

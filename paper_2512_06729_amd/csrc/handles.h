@@ -88,6 +88,10 @@ struct xod_column {
   RedArgs *red_dev = nullptr, *red_host = nullptr;
   double t = 0.0, dt = 0.0;
   double fact_dt = 0.0;   // dt of the FP64 factorisation held in the blocks (0: none)
+  // mixed precision control: smallest step size that fell back to FP64 (0:
+  // none) and the steps since taken in FP64 directly
+  double mixed_fb_dt = 0.0;
+  int mixed_direct = 0;
   double prev_dt = 0.0;   // dt of the step whose starting state ntmp holds (0: none)
   bool in_batch = false;
   // The factorisation xod_btd_factor left in the column's own workspace

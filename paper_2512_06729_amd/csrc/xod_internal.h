@@ -94,6 +94,8 @@ struct Options {
   double refine_tol = 1e-7;    // mixed refinement: relative size of the last correction
   double refine_atol = 1e-14;  // ... and its floor, relative to the layer's largest increment
   int refine64 = 0;            // FP64 steps: refinements with the FP64 factors (0: none)
+  int mixed_sticky = 16;       // mixed steps at or above a step size that fell back: this many
+                               // go to FP64 directly before FP32 is tried again (0: never)
   int gemm_large = 1;     // 128 x 128 product tiles for large batches
   int gemm_k = 32;        // K step of the block products staged in LDS (16 or 32)
   int gemm_waves = 16;    // waves per 128-tile work-group of the block products (16 or 8)
