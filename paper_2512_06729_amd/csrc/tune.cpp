@@ -187,10 +187,14 @@ extern "C" xod_status xod_autotune(xod_column *col, double dt, int32_t trials,
   double best = 1e300, def = 0.0;
   TuneVals bestv = cand[0];
   xod_status st = XOD_OK;
+  const double fb_dt0 = col->mixed_fb_dt;   // the column's precision history, kept
+  const int direct0 = col->mixed_direct;
   for (size_t ci = 0; ci < cand.size() && st == XOD_OK; ++ci) {
     store(key, cand[ci]);
     int it, fb;
     double rr;
+    col->mixed_fb_dt = 0.0;   // every candidate starts from FP32 (mixed columns)
+    col->mixed_direct = 0;
     st = enqueue_solve(col, dt, &it, &fb, &rr, nullptr, 0.0);   // untimed first use
     if (st != XOD_OK) break;
     if (hipEventRecord(e0, col->stream) != hipSuccess) { st = XOD_EHIP; break; }
@@ -212,6 +216,8 @@ extern "C" xod_status xod_autotune(xod_column *col, double dt, int32_t trials,
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  col->mixed_fb_dt = fb_dt0;
+  col->mixed_direct = direct0;
   store(key, bestv);
   col->fact_dt = 0.0;   // the tuning steps' factors are not the caller's
   col->btd.valid = false;
