@@ -230,41 +230,99 @@ hipError_t launch_cr_level0(const CrLevel0Op<T> *dops, int count, int ld, hipStr
 }
 
 // ---------------------------------------------------------------------------
-// Matrix-vector terms.  One work-group of four waves per 8 output rows of
-// one op; the (gathered) input vectors are staged in LDS.  Each wave reduces
+// Matrix-vector terms.  One work-group of four waves (256 threads) per 8
+// output rows of one op; the (gathered) input vectors are staged in LDS.  Each wave reduces
 // two rows, with every matrix element it needs loaded before the first is
 // used (ld <= kMaxLd: at most 16 per lane, row and term).
 constexpr int kMvRows = 2;                 // rows per wave
 constexpr int kMvChunks = kMaxLd / 64;     // row elements per lane
 
 template <class T>
-__global__ void __launch_bounds__(256) k_mv(const MvOp<T> *ops, int ld) {
+__global__ void __launch_bounds__(256) k_mv(const MvOp<T> *__restrict__ ops, int ld) {
   const MvOp<T> &o = ops[blockIdx.y];
   __shared__ double xs[2][kMaxLd];
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   const int nterm = o.nterm;
-  for (int q = 0; q < nterm; ++q) {
-    const MvTerm<T> &tm = o.t[q];
-    const auto x = gmem(tm.x);
-    for (int m = t; m < ld; m += blockDim.x)
-      xs[q][m] = x[tm.xm ? in_block(gmem(tm.xm)[m], ld) : m];
+  // The (gathered) input vectors: every gather index first, then every
+  // value, then the LDS stores, with no branch around a load, so the chain
+  // is two loads deep.  A term without a gather (or absent) reads the op's
+  // output vector (ld doubles, always valid) in place of an index list and
+  // discards what it read.
+  constexpr int kXs = kMaxLd / 256;          // elements per thread and term
+  int xi[2][kXs];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const bool gath = q < nterm && o.t[q].xm;
+    const auto xm = gmem(gath ? o.t[q].xm : reinterpret_cast<const int *>(o.y));
+#pragma unroll
+    for (int e = 0; e < kXs; ++e) xi[q][e] = xm[min(t + 256 * e, ld - 1)];
+#pragma unroll
+    for (int e = 0; e < kXs; ++e) xi[q][e] = gath ? in_block(xi[q][e], ld) : min(t + 256 * e, ld - 1);
   }
+  double xv[2][kXs];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const auto x = gmem(q < nterm ? o.t[q].x : o.y);
+#pragma unroll
+    for (int e = 0; e < kXs; ++e) xv[q][e] = x[xi[q][e]];
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+    if (q < nterm) {
+#pragma unroll
+      for (int e = 0; e < kXs; ++e)
+        if (t + 256 * e < ld) xs[q][t + 256 * e] = xv[q][e];
+    }
   const int j0 = (blockIdx.x * 4 + wid) * kMvRows;
   T mv[kMvRows][2][kMvChunks];
+  if constexpr (sizeof(T) == 4) {
+    // FP32: every chunk of every (row, term) pair is loaded with its column
+    // clamped into the row and no branch, so all 64 loads of a lane are in
+    // flight together (branches would each wait for their loads, as the
+    // conversion to FP64 moves into them).  A pair that is not present (the
+    // same for the whole wave) reads the op's output vector, ld doubles and
+    // always valid; the products below skip it and the chunks past ld.
+    const T *base[kMvRows][2];
+    int src[kMvRows][2];
 #pragma unroll
-  for (int rr = 0; rr < kMvRows; ++rr)
+    for (int rr = 0; rr < kMvRows; ++rr)
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int j = j0 + rr;
-      const MvTerm<T> &tm = o.t[q];
-      const bool on = q < nterm && tm.M && j < ld;
-      const auto row = gmem(tm.M) + (size_t)(on && tm.rm ? in_block(gmem(tm.rm)[j], ld) : j) * ld;
-#pragma unroll
-      for (int c = 0; c < kMvChunks; ++c) {
-        const int m = lane + 64 * c;
-        mv[rr][q][c] = (on && m < ld) ? row[m] : T(0);
+      for (int q = 0; q < 2; ++q) {
+        const int j = j0 + rr;
+        const MvTerm<T> &tm = o.t[q];
+        const bool on = q < nterm && tm.M && j < ld;
+        const bool perm = on && tm.rm;
+        base[rr][q] = on ? tm.M : reinterpret_cast<const T *>(o.y);
+        src[rr][q] = gmem(perm ? tm.rm : reinterpret_cast<const int *>(o.y))[min(j, ld - 1)];
+        src[rr][q] = perm ? in_block(src[rr][q], ld) : (on ? j : 0);
       }
-    }
+#pragma unroll
+    for (int rr = 0; rr < kMvRows; ++rr)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const auto row = gmem(base[rr][q]) + (size_t)src[rr][q] * ld;
+#pragma unroll
+        for (int c = 0; c < kMvChunks; ++c) mv[rr][q][c] = row[min(lane + 64 * c, ld - 1)];
+      }
+  } else {
+    // FP64: one (row, term) pair's 16 loads in flight at a time, which keeps
+    // the registers (and so the waves per SIMD) of the FP64 kernel.
+#pragma unroll
+    for (int rr = 0; rr < kMvRows; ++rr)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int j = j0 + rr;
+        const MvTerm<T> &tm = o.t[q];
+        const bool on = q < nterm && tm.M && j < ld;
+        const auto row =
+            gmem(tm.M) + (size_t)(on && tm.rm ? in_block(gmem(tm.rm)[j], ld) : j) * ld;
+#pragma unroll
+        for (int c = 0; c < kMvChunks; ++c) {
+          const int m = lane + 64 * c;
+          mv[rr][q][c] = (on && m < ld) ? row[m] : T(0);
+        }
+      }
+  }
   __syncthreads();
 #pragma unroll
   for (int rr = 0; rr < kMvRows; ++rr) {
