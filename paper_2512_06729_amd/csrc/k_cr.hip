@@ -49,7 +49,8 @@ __global__ void __launch_bounds__(NT) k_gemm(const GemmOp<T> *ops, int ld) {
   static_assert(AL >= 1 && BL >= 1 && TMR >= 1, "tile shape");
   const GemmOp<T> g = ops[blockIdx.z];
   const int tm0 = blockIdx.y * BM, tn0 = blockIdx.x * BM;
-  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform
   const int wr = wid >> 2, wc = wid & 3;
   __shared__ T As[2][BM][KB + 1];
   __shared__ T Bs[2][KB][BM + 2];
@@ -75,60 +76,84 @@ __global__ void __launch_bounds__(NT) k_gemm(const GemmOp<T> *ops, int ld) {
     const auto B = gmem(second ? g.B2 : g.B);
     const int k0 = (second ? kt - nk1 : kt) * KB;
     const int *gb = sbg[second ? 1 : 0];
+    // every load unconditional (row / column clamped into the block), so
+    // the whole step's loads and gather-index reads issue together; the
+    // elements beyond ld become zeros when they are stored to LDS
+    int gr[BL];
+#pragma unroll
+    for (int e = 0; e < BL; ++e) gr[e] = gb[k0 + (t + e * NT) / BM];
 #pragma unroll
     for (int e = 0; e < AL; ++e) {
-      const int idx = t + e * NT, r = tm0 + idx / KB;
-      ra[e] = r < ld ? A[(size_t)r * ld + k0 + idx % KB] : T(0);
+      const int idx = t + e * NT, r = min(tm0 + idx / KB, ld - 1);
+      ra[e] = A[(size_t)r * ld + k0 + idx % KB];
     }
 #pragma unroll
     for (int e = 0; e < BL; ++e) {
-      const int idx = t + e * NT, c = tn0 + idx % BM;
-      rb[e] = c < ld ? B[(size_t)gb[k0 + idx / BM] * ld + c] : T(0);
+      const int idx = t + e * NT, c = min(tn0 + idx % BM, ld - 1);
+      rb[e] = B[(size_t)gr[e] * ld + c];
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < AL; ++e) {
       const int idx = t + e * NT;
-      As[buf][idx / KB][idx % KB] = ra[e];
+      As[buf][idx / KB][idx % KB] = tm0 + idx / KB < ld ? ra[e] : T(0);
     }
 #pragma unroll
     for (int e = 0; e < BL; ++e) {
       const int idx = t + e * NT;
-      Bs[buf][idx / BM][idx % BM] = rb[e];
+      Bs[buf][idx / BM][idx % BM] = tn0 + idx % BM < ld ? rb[e] : T(0);
     }
   };
-  // 16 x 16 output tiles wholly beyond ld (the last tile row / column of a
-  // block whose size is not a multiple of BM) are skipped: wave-uniform
-  // conditions, so waves of edge tiles leave their SIMD to other work-groups.
-  bool live_r[TMR], live_c[TMC];
-#pragma unroll
-  for (int i = 0; i < TMR; ++i) live_r[i] = tm0 + (wr * TMR + i) * 16 < ld;
-#pragma unroll
-  for (int j = 0; j < TMC; ++j) live_c[j] = tn0 + (wc * TMC + j) * 16 < ld;
+  // A wave whose output tiles all lie beyond ld (the last tile row / column
+  // of a block whose size is not a multiple of BM) skips its products, one
+  // wave-uniform test per K step, and leaves its SIMD to other work-groups.
+  // A wave with some tiles inside multiplies all of them (the staged
+  // operands beyond ld are zeros, and the stores are masked); with 16 waves
+  // each wave's 32 x 32 outputs are wholly inside or outside (ld is a
+  // multiple of 32), so only the 8-wave tiles carry such zero products.
+  const bool wave_live = tm0 + wr * TMR * 16 < ld && tn0 + wc * TMC * 16 < ld;
   gload(0);
   sstore(0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < nk) gload(kt + 1);
+    if (wave_live) {
 #pragma unroll
-    for (int kk = 0; kk < KB / 4; ++kk) {
-      T av[TMR], bv[TMC];
+      for (int kk = 0; kk < KB / 4; ++kk) {
+        T av[TMR], bv[TMC];
 #pragma unroll
-      for (int i = 0; i < TMR; ++i)
-        av[i] = As[buf][(wr * TMR + i) * 16 + (lane & 15)][kk * 4 + (lane >> 4)];
-#pragma unroll
-      for (int j = 0; j < TMC; ++j)
-        bv[j] = Bs[buf][kk * 4 + (lane >> 4)][(wc * TMC + j) * 16 + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < TMR; ++i)
+        for (int i = 0; i < TMR; ++i)
+          av[i] = As[buf][(wr * TMR + i) * 16 + (lane & 15)][kk * 4 + (lane >> 4)];
 #pragma unroll
         for (int j = 0; j < TMC; ++j)
-          if (live_r[i] && live_c[j]) acc[i][j] = mfma16(av[i], bv[j], acc[i][j]);
+          bv[j] = Bs[buf][kk * 4 + (lane >> 4)][(wc * TMC + j) * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < TMR; ++i)
+#pragma unroll
+          for (int j = 0; j < TMC; ++j) acc[i][j] = mfma16(av[i], bv[j], acc[i][j]);
+      }
     }
     if (kt + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
+  }
+  // C is read (when accumulated into) for every output of the wave at once,
+  // the addresses clamped into the block, then written where inside it.
+  const auto C = gmem(g.C);
+  T cold[TMR][TMC][4];
+  if (g.beta && wave_live) {
+#pragma unroll
+    for (int i = 0; i < TMR; ++i)
+#pragma unroll
+      for (int j = 0; j < TMC; ++j) {
+        const int c = min(tn0 + (wc * TMC + j) * 16 + (lane & 15), ld - 1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = min(tm0 + (wr * TMR + i) * 16 + mfma_row(T(0), lane, q), ld - 1);
+          cold[i][j][q] = C[(size_t)r * ld + c];
+        }
+      }
   }
 #pragma unroll
   for (int i = 0; i < TMR; ++i)
@@ -139,9 +164,8 @@ __global__ void __launch_bounds__(NT) k_gemm(const GemmOp<T> *ops, int ld) {
       for (int q = 0; q < 4; ++q) {
         const int r = tm0 + (wr * TMR + i) * 16 + mfma_row(T(0), lane, q);
         if (r < ld && c < ld) {
-          const auto p = gmem(g.C) + (size_t)r * ld + c;
           const double v = g.alpha * (double)acc[i][j][q];
-          *p = (T)(g.beta ? (double)*p + v : v);
+          C[(size_t)r * ld + c] = (T)(g.beta ? (double)cold[i][j][q] + v : v);
         }
       }
     }
