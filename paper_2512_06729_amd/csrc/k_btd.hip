@@ -562,19 +562,12 @@ __global__ void __launch_bounds__(kUpd32Threads) k_update32(MA ma, int k, int p,
   const auto rstep = gmem((const int *)mat.rstep);
   __shared__ T sU[kNB][kNB + 1];
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-  for (int e = t; e < kNB * kNB; e += blockDim.x) {
-    const int r = e / kNB, col = e % kNB;
-    sU[r][col] = W[(size_t)piv[r] * ld + c0 + col];
-  }
-  __syncthreads();
-  // B operand of the two 16-column halves, 8 k-steps each: U[4kk + l/16][16h + l%16]
-  T bf[2][kNB / 4];
+  // U: every pivot index first, then every value (two loads deep instead of
+  // two per element), with the first tile's operands issued in between.
+  constexpr int kUE = kNB * kNB / kUpd32Threads;
+  int ur[kUE];
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int kk = 0; kk < kNB / 4; ++kk) bf[h][kk] = sU[4 * kk + (lane >> 4)][16 * h + (lane & 15)];
-  __syncthreads();   // every wave holds U before any pivot row of the strip is rewritten
-
+  for (int e = 0; e < kUE; ++e) ur[e] = piv[(t + e * kUpd32Threads) / kNB];
   const int ntile = ld / 16;
   // Loads only: the pivot mask is applied when the tile is used, so the
   // next tile's loads stay in flight during the current tile's MFMAs.
@@ -595,6 +588,23 @@ __global__ void __launch_bounds__(kUpd32Threads) k_update32(MA ma, int k, int p,
   };
   int tile = wid;
   if (tile < ntile) load(tile);
+  T uv[kUE];
+#pragma unroll
+  for (int e = 0; e < kUE; ++e)
+    uv[e] = W[(size_t)ur[e] * ld + c0 + (t + e * kUpd32Threads) % kNB];
+#pragma unroll
+  for (int e = 0; e < kUE; ++e) {
+    const int idx = t + e * kUpd32Threads;
+    sU[idx / kNB][idx % kNB] = uv[e];
+  }
+  __syncthreads();
+  // B operand of the two 16-column halves, 8 k-steps each: U[4kk + l/16][16h + l%16]
+  T bf[2][kNB / 4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int kk = 0; kk < kNB / 4; ++kk) bf[h][kk] = sU[4 * kk + (lane >> 4)][16 * h + (lane & 15)];
+  __syncthreads();   // every wave holds U before any pivot row of the strip is rewritten
   while (tile < ntile) {
     typename Vec4<T>::type acc[2];
     T a_now[kNB / 4];
