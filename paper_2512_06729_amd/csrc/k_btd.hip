@@ -453,7 +453,7 @@ constexpr int kUpdThreads = 1024;   // 16 waves share the row tiles of a strip
 // Strips s0 + blockIdx.x are updated, except the panel's own and those in
 // [skip0, skip1).  A full launch (s0 = 0) keeps strip s on work-group s, so a
 // strip stays on the same XCD for every panel.
-template <class MA, class T, bool kMfma>
+template <class MA, class T, bool kMfma, int kMaxTiles = kMaxLd / 16 / (kUpdThreads / 64)>
 __global__ void __launch_bounds__(kUpdThreads) k_update(MA ma, int k, int p, int ld, int s0,
                                                         int skip0, int skip1) {
   MatRef<T> mat;
@@ -475,8 +475,8 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(MA ma, int k, int p, int
     // Prefetch this wave's tiles (A operand, C tile, pivot mask) before U is
     // published, so their latency overlaps the U gather.
     // The pivot mask is applied when the tile is used, so that no load waits
-    // for another.
-    constexpr int kMaxTiles = kMaxLd / 16 / (kUpdThreads / 64);
+    // for another.  kMaxTiles (tiles per wave) is chosen from ld at launch, so
+    // that the prefetched tiles stay in registers.
     T av[kMaxTiles][kNB / 4];
     T cv[kMaxTiles][4];
     int sv[kMaxTiles][4];
@@ -648,9 +648,23 @@ void launch_update(const MA &ma, int nmat, int ld, int k, int p, hipStream_t s, 
       nstrip % spp == 0 && skip0 % spp == 0 && skip1 - skip0 <= spp)
     hipLaunchKernelGGL((k_update32<MA, T>), dim3(nstrip / spp, nmat), dim3(kUpd32Threads), 0, s,
                        ma, k, p, ld, s0 / spp, skip1 > skip0 ? skip0 / spp : -1);
-  else if (options().gemm_mfma)
-    hipLaunchKernelGGL((k_update<MA, T, true>), dim3(nstrip, nmat), dim3(kUpdThreads), 0, s, ma,
-                       k, p, ld, s0, skip0, skip1);
+  else if (options().gemm_mfma) {
+    // tiles per wave: 16-row tiles of the block over the 16 waves
+    const int tpw = (ld / 16 + kUpdThreads / 64 - 1) / (kUpdThreads / 64);
+    const dim3 grid(nstrip, nmat);
+    if (tpw <= 1)
+      hipLaunchKernelGGL((k_update<MA, T, true, 1>), grid, dim3(kUpdThreads), 0, s, ma, k, p, ld,
+                         s0, skip0, skip1);
+    else if (tpw <= 2)
+      hipLaunchKernelGGL((k_update<MA, T, true, 2>), grid, dim3(kUpdThreads), 0, s, ma, k, p, ld,
+                         s0, skip0, skip1);
+    else if (tpw <= 3)
+      hipLaunchKernelGGL((k_update<MA, T, true, 3>), grid, dim3(kUpdThreads), 0, s, ma, k, p, ld,
+                         s0, skip0, skip1);
+    else
+      hipLaunchKernelGGL((k_update<MA, T, true>), grid, dim3(kUpdThreads), 0, s, ma, k, p, ld, s0,
+                         skip0, skip1);
+  }
   else
     hipLaunchKernelGGL((k_update<MA, T, false>), dim3(nstrip, nmat), dim3(kUpdThreads), 0, s,
                        ma, k, p, ld, s0, skip0, skip1);
