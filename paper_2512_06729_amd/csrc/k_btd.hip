@@ -840,17 +840,28 @@ __global__ void __launch_bounds__(NT) k_btd_fused_factor(Acc acc) {
 #pragma unroll
   for (int q = 0; q < CW; ++q) A[q] = 0.0;
   bool flagged = false;
+  // The next layer's block row and couplings are loaded while this layer is
+  // eliminated (block k+1 is written only by its own layer).
+  double nb[CW], ncp[CW], nai = 0.0;
+  auto fetch = [&](int k) {
+    if (!active) return;
+    const double *Bn = c.B + (size_t)k * LD * LD;
+    const double *cp = c.c + (size_t)(k > 0 ? k - 1 : 0) * LD;
+    nai = k > 0 ? c.a[(size_t)k * LD + i] : 0.0;
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+      nb[q] = Bn[(size_t)i * LD + j0 + q];
+      ncp[q] = cp[j0 + q];
+    }
+  };
+  if (N > 0) fetch(0);
   for (int k = 0; k < N; ++k) {
     double *Bk = c.B + (size_t)k * LD * LD;
     if (active) {
-      const double ai = k > 0 ? c.a[(size_t)k * LD + i] : 0.0;
-      const double *cp = c.c + (size_t)(k > 0 ? k - 1 : 0) * LD;
 #pragma unroll
-      for (int q = 0; q < CW; ++q) {
-        const double b = Bk[(size_t)i * LD + j0 + q];
-        A[q] = k > 0 ? b - ai * A[q] * cp[j0 + q] : b;
-      }
+      for (int q = 0; q < CW; ++q) A[q] = k > 0 ? nb[q] - nai * A[q] * ncp[q] : nb[q];
     }
+    if (k + 1 < N) fetch(k + 1);
     if (t < LD) pvrow[t] = t;   // padding columns keep their own row
     bool used = i >= S;         // padding rows are never pivots
     int colof = i;              // the column this row pivots
@@ -949,25 +960,71 @@ __global__ void __launch_bounds__(NT) k_btd_fused_solve(Acc acc) {
   // (Factors of the persistent kernel have identity pivots; those of the
   // panel kernels are in pivot order.  Out-of-range entries of an
   // incomplete factorisation, which is flagged, read nothing.)
-  auto row_product = [&](int k) -> double {
-    const double *W = c.B + (size_t)k * LD * LD + (size_t)i * LD + j0;
-    const int *pv = c.piv + (size_t)k * LD + j0;
-    double z = 0.0;
+  // Every operand of a layer (the thread's block-row segment and its
+  // pivots, the right-hand side or coupling entry, the pivot step of its row)
+  // is independent of the solve, so it is loaded one layer ahead; the
+  // block-row segment only for blocks up to 64, where registers allow.
+  constexpr bool kRowAhead = LD <= 64;
+  constexpr int kCW = kRowAhead ? CW : 1;
+  struct Ops {
+    double w[kCW];
+    int pv[kCW];
+    double e0, e1;   // forward: x and a entries; backward: the c entry (e1 unused)
+    int rs, k;
+  };
+  auto fetch = [&](int k, bool fwd, Ops &o) {
+    o.k = k;
+    if constexpr (kRowAhead) {
+      const double *W = c.B + (size_t)k * LD * LD + (size_t)i * LD + j0;
+      const int *pv = c.piv + (size_t)k * LD + j0;
 #pragma unroll
-    for (int q = 0; q < CW; ++q) {
-      const int m = pv[q];
-      z = fma(W[q], (unsigned)m < (unsigned)S ? v[m] : 0.0, z);
+      for (int q = 0; q < CW; ++q) {
+        o.w[q] = W[q];
+        o.pv[q] = pv[q];
+      }
+    }
+    const int tt = t < S ? t : 0;
+    o.rs = c.rstep[(size_t)k * LD + i];
+    if (fwd) {
+      o.e0 = c.x[(size_t)k * S + tt];
+      o.e1 = k > 0 ? c.a[(size_t)k * LD + tt] : 0.0;
+    } else {
+      o.e0 = c.c[(size_t)k * LD + tt];
+      o.e1 = 0.0;
+    }
+  };
+  // z_r = sum_m W[r][m] v[piv[m]] over the row's threads
+  auto row_product = [&](const Ops &o) -> double {
+    double z = 0.0;
+    if constexpr (kRowAhead) {
+#pragma unroll
+      for (int q = 0; q < CW; ++q) {
+        const int m = o.pv[q];
+        z = fma(o.w[q], (unsigned)m < (unsigned)S ? v[m] : 0.0, z);
+      }
+    } else {
+      const double *W = c.B + (size_t)o.k * LD * LD + (size_t)i * LD + j0;
+      const int *pv = c.piv + (size_t)o.k * LD + j0;
+#pragma unroll
+      for (int q = 0; q < CW; ++q) {
+        const int m = pv[q];
+        z = fma(W[q], (unsigned)m < (unsigned)S ? v[m] : 0.0, z);
+      }
     }
     return row_sum<F::TPR>(z);
   };
+  Ops cur, nxt;
+  if (N > 0) fetch(0, true, nxt);
   for (int k = 0; k < N; ++k) {
-    if (t < LD)
-      v[t] = t < S ? c.x[(size_t)k * S + t] - (k > 0 ? c.a[(size_t)k * LD + t] * y[t] : 0.0) : 0.0;
+    cur = nxt;
+    if (k + 1 < N) fetch(k + 1, true, nxt);
+    else if (N >= 2) fetch(N - 2, false, nxt);   // the backward pass's first layer
+    if (t < LD) v[t] = t < S ? cur.e0 - (k > 0 ? cur.e1 * y[t] : 0.0) : 0.0;
     __syncthreads();
-    const double z = row_product(k);
+    const double z = row_product(cur);
     __syncthreads();
     if (owner) {
-      const int j = c.rstep[(size_t)k * LD + i];
+      const int j = cur.rs;
       if ((unsigned)j < (unsigned)LD) {
         y[j] = z;
         c.gs[(size_t)k * LD + j] = z;
@@ -978,12 +1035,14 @@ __global__ void __launch_bounds__(NT) k_btd_fused_solve(Acc acc) {
   // y holds y_{N-1} = x_{N-1}
   if (t < S) c.x[(size_t)(N - 1) * S + t] = y[t];
   for (int k = N - 2; k >= 0; --k) {
-    if (t < LD) v[t] = t < S ? c.c[(size_t)k * LD + t] * y[t] : 0.0;
+    cur = nxt;
+    if (k > 0) fetch(k - 1, false, nxt);
+    if (t < LD) v[t] = t < S ? cur.e0 * y[t] : 0.0;
     __syncthreads();
-    const double z = row_product(k);
+    const double z = row_product(cur);
     __syncthreads();
     if (owner) {
-      const int j = c.rstep[(size_t)k * LD + i];
+      const int j = cur.rs;
       if ((unsigned)j < (unsigned)LD) {
         const double xj = c.gs[(size_t)k * LD + j] - z;
         y[j] = xj;
