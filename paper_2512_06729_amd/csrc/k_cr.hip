@@ -221,7 +221,8 @@ hipError_t launch_gather_rows(const GatherOp<T> *dops, int count, int ld, hipStr
 }
 
 // ---------------------------------------------------------------------------
-// Level-0 Schur terms.  One work-group per (row r, kept layer).
+// Level-0 Schur terms.  One work-group of 256 threads per (row r, kept
+// layer).
 template <class T>
 __global__ void __launch_bounds__(256) k_cr_level0(const CrLevel0Op<T> *ops, int ld) {
   const CrLevel0Op<T> &o = ops[blockIdx.y];
@@ -230,17 +231,52 @@ __global__ void __launch_bounds__(256) k_cr_level0(const CrLevel0Op<T> *ops, int
   const T *wr = o.Wr ? o.Wr + (size_t)in_block(o.pr[r], ld) * ld : nullptr;
   const double akr = o.ak[r], ckr = o.ck[r];
   T *D = o.D + (size_t)r * ld;
-  for (int j = threadIdx.x; j < ld; j += blockDim.x) {
-    double d = (double)D[j];
+  // A thread's (up to four) entries: every gather index first, then every
+  // gathered and row value, then the arithmetic, with no branch around a
+  // load (an absent side reads this row of D in place of its index list and
+  // inverse row, and discards it), so the chain is two loads deep.
+  constexpr int kE = kMaxLd / 256;
+  const int t = threadIdx.x;
+  const auto ql = gmem(wl ? o.ql : reinterpret_cast<const int *>(D));
+  const auto qr = gmem(wr ? o.qr : reinterpret_cast<const int *>(D));
+  const auto wlg = gmem(wl ? wl : D), wrg = gmem(wr ? wr : D);
+  int il[kE], ir[kE];
+#pragma unroll
+  for (int e = 0; e < kE; ++e) {
+    const int j = min(t + 256 * e, ld - 1);
+    il[e] = ql[j];
+    ir[e] = qr[j];
+  }
+  // the op's coupling vectors and outputs, read before any store (a store
+  // could otherwise alias them and force every later load to wait)
+  const double *cl = o.cl, *al = o.al, *ar = o.ar, *cr = o.cr;
+  T *Ao = o.A, *Co = o.C;
+  const auto clg = gmem(wl ? cl : o.ak), alg = gmem(wl && Ao ? al : o.ak);
+  const auto arg = gmem(wr ? ar : o.ak), crg = gmem(wr && Co ? cr : o.ak);
+  double dv[kE], el[kE], er[kE], vcl[kE], val[kE], var[kE], vcr[kE];
+#pragma unroll
+  for (int e = 0; e < kE; ++e) {
+    const int j = min(t + 256 * e, ld - 1);
+    dv[e] = (double)gmem(D)[j];
+    el[e] = (double)wlg[wl ? in_block(il[e], ld) : j];
+    er[e] = (double)wrg[wr ? in_block(ir[e], ld) : j];
+    vcl[e] = clg[j];
+    val[e] = alg[j];
+    var[e] = arg[j];
+    vcr[e] = crg[j];
+  }
+#pragma unroll
+  for (int e = 0; e < kE; ++e) {
+    const int j = t + 256 * e;
+    if (j >= ld) break;
+    double d = dv[e];
     if (wl) {
-      const double el = (double)wl[in_block(o.ql[j], ld)];
-      d -= akr * el * o.cl[j];
-      if (o.A) o.A[(size_t)r * ld + j] = (T)(-akr * el * o.al[j]);
+      d -= akr * el[e] * vcl[e];
+      if (Ao) Ao[(size_t)r * ld + j] = (T)(-akr * el[e] * val[e]);
     }
     if (wr) {
-      const double er = (double)wr[in_block(o.qr[j], ld)];
-      d -= ckr * er * o.ar[j];
-      if (o.C) o.C[(size_t)r * ld + j] = (T)(-ckr * er * o.cr[j]);
+      d -= ckr * er[e] * var[e];
+      if (Co) Co[(size_t)r * ld + j] = (T)(-ckr * er[e] * vcr[e]);
     }
     D[j] = (T)d;
   }
